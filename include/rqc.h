@@ -1,0 +1,319 @@
+/*
+ * rqc.h -- C ABI of the sliced tensor-network amplitude engine for random
+ * quantum circuits on one AMD MI355X (gfx950).
+ *
+ * The method (paper: "Closing the 'Quantum Supremacy' Gap", SC'21):
+ *   - a circuit becomes a tensor network, one tensor per gate (Section 3.2,
+ *     tensor approach);
+ *   - a contraction path is searched (Section 5.2) and a set of wires is
+ *     sliced: each slice fixes those wires to one assignment of values and
+ *     the independent slice results are summed (Section 5.1);
+ *   - every contraction step is an index permutation followed by a complex
+ *     matrix multiply (Section 5.4), here fused into one GPU kernel;
+ *   - a batch of "open" qubits yields 2^n_open amplitudes per contraction
+ *     (Section 5.1, last paragraph);
+ *   - reduced precision with adaptive scaling (Section 5.5);
+ *   - a final reduction of the slice results (Section 6.4).
+ *
+ * Conventions
+ *   - Complex numbers are stored interleaved (re, im).
+ *   - Bit strings: qubit q of an n-qubit state is bit (n-1-q) of the state
+ *     index.  An amplitude batch has 2^n_open entries; bit i of the entry
+ *     index is the value of open_qubits[i] (the first open qubit is the
+ *     least significant bit).  Closed bits are given in increasing qubit
+ *     order of the closed qubits.
+ *   - A canonical wire (q, s), s >= 1, is the wire of qubit q leaving the
+ *     s-th two-qubit gate that acts on q.  Slice id bit j is the value of the
+ *     j-th sliced wire in plan order.
+ *   - Device pointers come from the caller (for example torch tensors); the
+ *     library never frees caller memory.  Handles belong to the library
+ *     until their destroy call.  A plan is not thread-safe; a server is.
+ *   - Every function returns RQC_OK (0) or a negative rqc_status; no C++
+ *     exception crosses this boundary.  rqc_last_error() gives a message for
+ *     the last failure on the calling thread.  Errors of asynchronous device
+ *     work surface at the next call that synchronises (for example
+ *     rqc_contract_report).
+ */
+#ifndef RQC_H
+#define RQC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rqc_status;
+#define RQC_OK            0
+#define RQC_EINVAL       -1  /* invalid argument */
+#define RQC_ENOMEM       -2  /* host allocation failed */
+#define RQC_EHBM         -3  /* device memory given (or budget) too small */
+#define RQC_EDEVICE      -4  /* HIP runtime error */
+#define RQC_EUNSUPPORTED -5  /* valid request the library does not support */
+#define RQC_ENUMERIC     -6  /* non-finite values persisted after FP32 rerun */
+
+/* Gate kinds.  Matrices are M[out][in]; two-qubit basis index 2*b(q0)+b(q1).
+ * FSIM(theta, phi) = [[1,0,0,0],[0,c,-is,0],[0,-is,c,0],[0,0,0,e^{-i phi}]]
+ * with c = cos(theta), s = sin(theta) (the fSim gate of Section 5.2);
+ * SQRT_G satisfies SQRT_G^2 = -i G for G in {X, Y, W=(X+Y)/sqrt(2)}. */
+enum {
+  RQC_GATE_H = 0,
+  RQC_GATE_SQRT_X = 1,
+  RQC_GATE_SQRT_Y = 2,
+  RQC_GATE_SQRT_W = 3,
+  RQC_GATE_FSIM = 4,
+  RQC_GATE_U1 = 5,  /* explicit 2x2 matrix in u[0..7] (re, im row-major) */
+  RQC_GATE_U2 = 6   /* explicit 4x4 matrix in u[0..31] */
+};
+
+typedef struct rqc_gate {
+  int32_t kind;
+  int32_t q0;
+  int32_t q1;   /* -1 for single-qubit gates */
+  int32_t reserved;
+  double theta;
+  double phi;
+  double u[32];
+} rqc_gate;
+
+/* Arithmetic of the contraction steps.  F32: complex64 storage, FP32 MFMA.
+ * F16 / BF16: large intermediates stored as complex half / bfloat16 with a
+ * per-slice power-of-two exponent (adaptive scaling, Section 5.5), FP32
+ * accumulation; small tensors stay complex64.  The cross-slice sum is FP64
+ * in every mode. */
+enum { RQC_F32 = 0, RQC_F16 = 1, RQC_BF16 = 2 };
+
+typedef struct rqc_circuit rqc_circuit;
+typedef struct rqc_network rqc_network;
+typedef struct rqc_plan rqc_plan;
+typedef struct rqc_server rqc_server;
+typedef void* rqc_stream; /* a hipStream_t; NULL is the default stream */
+
+/* ---- circuit and network (Section 3.2, tensor approach) ---------------- */
+
+/* Copy n_gates gates applied in array order to |0...0> of n_qubits qubits.
+ * EINVAL for a qubit index out of range, q0 == q1, or an unknown kind. */
+rqc_status rqc_circuit_create(int32_t n_qubits, const rqc_gate* gates,
+                              size_t n_gates, rqc_circuit** out);
+void rqc_circuit_destroy(rqc_circuit* c);
+
+/* Tensor network of <b|U|0> with the listed qubits left open.  Single-qubit
+ * gates and the input |0> are absorbed forward into the next two-qubit gate
+ * of their qubit; each qubit's final single-qubit gates and its output
+ * (projection onto the closed bit, or the open index) into its last
+ * two-qubit gate.  The circuit may be destroyed afterwards. */
+rqc_status rqc_network_create(const rqc_circuit* c, const int32_t* open_qubits,
+                              int32_t n_open, rqc_network** out);
+void rqc_network_destroy(rqc_network* n);
+
+/* ---- plan: contraction path and slicing (Sections 5.1-5.2) ------------- */
+
+typedef struct rqc_plan_opts {
+  int32_t max_log2_elems; /* bound on any per-slice intermediate, log2 of
+                             elements; 0 = no bound */
+  int32_t n_sliced;       /* -1: as few wires as the bound needs; else exact */
+  int32_t path_trials;    /* randomized path searches; 0 = default (256) */
+  int32_t reconf_rounds;  /* subtree re-optimisation sweeps; -1 = default */
+  uint64_t seed;
+  int32_t n_forced;       /* wires that must be sliced, first in slice order */
+  const int32_t* forced_wires; /* n_forced (qubit, segment) pairs */
+  int32_t lp_min_log2;    /* reduced-precision modes store intermediates of at
+                             least 2^lp_min_log2 elements per slice in 16 bits;
+                             0 = default (14) */
+  int32_t reserved;
+} rqc_plan_opts;
+
+void rqc_plan_opts_default(rqc_plan_opts* o);
+
+/* Search a path, slice it and lay out every step.  Host only. */
+rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts,
+                           rqc_plan** out);
+void rqc_plan_destroy(rqc_plan* p);
+
+typedef struct rqc_plan_info {
+  int32_t n_qubits, n_open, n_closed, n_sliced;
+  uint64_t n_slices;
+  int32_t n_leaves, n_steps;       /* steps = pairwise contractions */
+  int32_t n_invariant_steps;       /* steps shared by all slices and bitstrings */
+  int32_t max_log2_elems;          /* largest per-slice intermediate */
+  double flops_per_slice;          /* 8 real flops per complex multiply-add */
+  double flops_invariant;          /* once per plan (slice-invariant subtrees) */
+  double bytes_per_slice;          /* complex64 bytes read+written per slice */
+  double log2_total_flops;         /* all slices, one bitstring batch */
+} rqc_plan_info;
+
+rqc_status rqc_plan_get_info(const rqc_plan* p, rqc_plan_info* out);
+
+/* Per-step shape: m, n, k are the numbers of row, column and summed index
+ * bits of C[m,n] = A[m,k] B[k,n]; kernel 0 = SIMT streaming, 1 = MFMA. */
+typedef struct rqc_step_info {
+  int32_t m, n, k;
+  int32_t kernel;
+  int32_t depends_on_slice, depends_on_bits;
+  int32_t lp_output;      /* output stored in 16 bits in reduced precision */
+  int32_t reserved;
+  double flops;           /* 8 * 2^(m+n+k) */
+  double bytes_c64;       /* 8 * (|A| + |B| + |C|) */
+} rqc_step_info;
+
+rqc_status rqc_plan_get_step(const rqc_plan* p, int32_t i, rqc_step_info* out);
+
+/* JSON description: sliced canonical wires (slice-bit order), open and
+ * closed qubits, the contraction tree and every step's layouts.  Writes at
+ * most cap bytes (NUL-terminated when it fits); *needed gets the full size
+ * including the NUL. */
+rqc_status rqc_plan_export_json(const rqc_plan* p, char* buf, size_t cap,
+                                size_t* needed);
+
+/* ---- device residency and contraction ---------------------------------- */
+
+/* Device bytes the plan keeps resident: leaf tensors and slice-invariant
+ * intermediates for all three precisions. */
+rqc_status rqc_plan_resident_bytes(const rqc_plan* p, size_t* bytes);
+
+/* Upload leaves into caller memory (dev_ptr, 256-byte aligned, at least
+ * rqc_plan_resident_bytes) and compute the slice-invariant subtrees on
+ * `stream`.  The memory must stay valid until the plan is destroyed or
+ * re-bound. */
+rqc_status rqc_plan_bind(rqc_plan* p, void* dev_ptr, size_t bytes,
+                         rqc_stream stream);
+
+/* Workspace for a contraction of n_ids slices and n_batch bitstrings:
+ * *min_bytes runs one slice and one bitstring at a time, *pref_bytes runs
+ * everything in one group.  More workspace lets more slices run together. */
+rqc_status rqc_contract_workspace(const rqc_plan* p, uint64_t n_ids,
+                                  uint64_t n_batch, int32_t prec,
+                                  size_t* min_bytes, size_t* pref_bytes);
+
+/* Amplitudes of n_batch bitstrings, summed over the given slices.
+ *   slice_ids   host array of n_ids slice ids (NULL with n_ids = 0: all);
+ *   closed_bits host array n_batch x n_closed (0/1 bytes);
+ *   workspace   device memory, 256-byte aligned, ws_bytes >= min_bytes;
+ *   out         device, n_batch x 2^n_open x 2 doubles (overwritten);
+ *   per_slice   device or NULL: n_ids x n_batch x 2^n_open x 2 doubles
+ *               holding each slice's own contribution.
+ * All work is enqueued on `stream` as one graph launch (cached per shape);
+ * the call returns before it finishes.  Slices whose reduced-precision run
+ * produced a non-finite value are re-run in FP32 when rqc_contract_report
+ * is called. */
+rqc_status rqc_contract(rqc_plan* p, const uint64_t* slice_ids, uint64_t n_ids,
+                        const uint8_t* closed_bits, uint64_t n_batch,
+                        int32_t prec, void* workspace, size_t ws_bytes,
+                        double* out, double* per_slice, rqc_stream stream);
+
+typedef struct rqc_run_report {
+  uint64_t n_slices;       /* slices summed */
+  uint64_t fp32_reruns;    /* slices re-run in FP32 (filter of Section 5.5) */
+  int32_t slices_per_group, bits_per_group;
+  int32_t graph_reused;    /* 1 when the cached graph was launched again */
+  int32_t reserved;
+  double flops;            /* algorithmic flops of the call */
+} rqc_run_report;
+
+/* Synchronise `stream`, re-run flagged slices in FP32 (synchronously) and
+ * report.  ENUMERIC if non-finite values remain. */
+rqc_status rqc_contract_report(rqc_plan* p, rqc_stream stream,
+                               rqc_run_report* out);
+
+/* ---- one pairwise contraction (Section 5.4) ----------------------------- */
+
+/* C = sum over shared labels of A * B for tensors with every dimension 2.
+ * labels_x lists operand x's index labels from the most significant address
+ * bit to the least significant one (numpy C order of shape (2,)*rank).  A
+ * label in A and B but not in C is summed; labels_c must be exactly the
+ * other labels.  A, B, C are device complex64 arrays (float2); batch_count
+ * independent problems lie at strides (elements) stride_a, stride_b,
+ * stride_c (0 = shared).  Ranks up to 40.  kernel: -1 auto, 0 SIMT, 1 MFMA. */
+rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a,
+                             const int32_t* labels_b, int32_t rank_b,
+                             const int32_t* labels_c, int32_t rank_c,
+                             const void* A, const void* B, void* C,
+                             int32_t batch_count, int64_t stride_a,
+                             int64_t stride_b, int64_t stride_c,
+                             int32_t kernel, rqc_stream stream);
+
+/* Bit permutation of a complex64 tensor: out (labels_out) = in (labels_in).
+ * The separate-permutation baseline of Section 5.4. */
+rqc_status rqc_permute(const int32_t* labels_in, const int32_t* labels_out,
+                       int32_t rank, const void* in, void* out,
+                       rqc_stream stream);
+
+/* Plain row-major complex64 GEMM C[M,N] = A[M,K] B[K,N] on MFMA, used with
+ * rqc_permute as the unfused baseline. */
+rqc_status rqc_cgemm(int64_t M, int64_t N, int64_t K, const void* A,
+                     const void* B, void* C, rqc_stream stream);
+
+/* ---- serving: continuous batching of amplitude requests ---------------- */
+
+typedef struct rqc_server_opts {
+  void* device_pool;          /* caller-owned device memory the server
+                                 sub-allocates (256-byte aligned) */
+  uint64_t hbm_budget_bytes;  /* size of device_pool: plans, workspaces and
+                                 outputs of admitted requests must fit */
+  int32_t max_inflight;       /* contraction calls on the device at once */
+  int32_t n_streams;          /* HIP streams used (default priority) */
+  int32_t max_batch;          /* requests of one plan merged into one call */
+  int32_t device;             /* HIP device ordinal */
+} rqc_server_opts;
+
+typedef struct rqc_request {
+  int32_t n_qubits;
+  int32_t n_open;
+  const rqc_gate* gates;      /* copied at submit */
+  uint64_t n_gates;
+  const int32_t* open_qubits; /* copied */
+  const uint8_t* closed_bits; /* one bitstring, n_qubits - n_open bytes */
+  int32_t prec;
+  int32_t max_log2_elems;     /* plan bound, 0 = default (26) */
+  uint64_t plan_key;          /* requests with equal nonzero keys share a plan */
+  uint64_t seed;
+} rqc_request;
+
+typedef struct rqc_result {
+  uint64_t ticket;
+  rqc_status status;
+  int32_t n_open;
+  double* amplitudes;         /* 2^n_open x 2 doubles, owned by the server
+                                 until rqc_server_release(ticket) */
+  double t_submit, t_start, t_done; /* seconds on the server clock */
+  uint64_t fp32_reruns;
+} rqc_result;
+
+rqc_status rqc_server_create(const rqc_server_opts* o, rqc_server** out);
+/* Queue a request; never blocks on the device.  Requests are admitted in
+ * arrival order as device memory and in-flight slots free up; requests that
+ * share a plan (equal nonzero plan_key, or identical circuit, open qubits
+ * and precision) and are waiting together run as one batched contraction.
+ * A request whose plan alone cannot fit the budget finishes with EHBM. */
+rqc_status rqc_server_submit(rqc_server* s, const rqc_request* r,
+                             uint64_t* ticket);
+/* Collect finished results (up to cap). */
+rqc_status rqc_server_poll(rqc_server* s, rqc_result* out, size_t cap,
+                           size_t* n);
+rqc_status rqc_server_release(rqc_server* s, uint64_t ticket);
+/* Block until every submitted request has finished. */
+rqc_status rqc_server_drain(rqc_server* s);
+typedef struct rqc_server_stats {
+  uint64_t submitted, completed, rejected;
+  uint64_t plans_built, plans_reused;
+  uint64_t peak_bytes, max_inflight_seen;
+} rqc_server_stats;
+rqc_status rqc_server_get_stats(rqc_server* s, rqc_server_stats* out);
+void rqc_server_destroy(rqc_server* s);
+
+/* ---- misc --------------------------------------------------------------- */
+
+const char* rqc_last_error(void);
+const char* rqc_version(void);
+
+/* Test hook for the failure path of Section 5.5: adds `bias` to every
+ * reduced-precision storage exponent shift of the plan (positive values
+ * force overflow to inf, which flags the slice for an FP32 re-run). */
+rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQC_H */

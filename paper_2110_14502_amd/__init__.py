@@ -1,0 +1,453 @@
+"""Python binding of librqc (include/rqc.h): argument marshalling only.
+
+Every computation runs in the native library and its HIP kernels; PyTorch
+only provides device memory and the current HIP stream.  Importing this
+module fails loudly when the native library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librqc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2110_14502_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants
+OK, EINVAL, ENOMEM, EHBM, EDEVICE, EUNSUPPORTED, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+F32, F16, BF16 = 0, 1, 2
+PRECISIONS = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
+GATE_H, GATE_SQRT_X, GATE_SQRT_Y, GATE_SQRT_W, GATE_FSIM, GATE_U1, GATE_U2 = range(7)
+
+
+class RqcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rqc error {code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------- structs
+class rqc_gate(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("q0", C.c_int32), ("q1", C.c_int32),
+                ("reserved", C.c_int32), ("theta", C.c_double), ("phi", C.c_double),
+                ("u", C.c_double * 32)]
+
+
+class rqc_plan_opts(C.Structure):
+    _fields_ = [("max_log2_elems", C.c_int32), ("n_sliced", C.c_int32),
+                ("path_trials", C.c_int32), ("reconf_rounds", C.c_int32),
+                ("seed", C.c_uint64), ("n_forced", C.c_int32),
+                ("forced_wires", C.POINTER(C.c_int32)), ("lp_min_log2", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class rqc_plan_info(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_open", C.c_int32), ("n_closed", C.c_int32),
+                ("n_sliced", C.c_int32), ("n_slices", C.c_uint64), ("n_leaves", C.c_int32),
+                ("n_steps", C.c_int32), ("n_invariant_steps", C.c_int32),
+                ("max_log2_elems", C.c_int32), ("flops_per_slice", C.c_double),
+                ("flops_invariant", C.c_double), ("bytes_per_slice", C.c_double),
+                ("log2_total_flops", C.c_double)]
+
+
+class rqc_step_info(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("k", C.c_int32), ("kernel", C.c_int32),
+                ("depends_on_slice", C.c_int32), ("depends_on_bits", C.c_int32),
+                ("lp_output", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double),
+                ("bytes_c64", C.c_double)]
+
+
+class rqc_run_report(C.Structure):
+    _fields_ = [("n_slices", C.c_uint64), ("fp32_reruns", C.c_uint64),
+                ("slices_per_group", C.c_int32), ("bits_per_group", C.c_int32),
+                ("graph_reused", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double)]
+
+
+class rqc_server_opts(C.Structure):
+    _fields_ = [("device_pool", C.c_void_p), ("hbm_budget_bytes", C.c_uint64),
+                ("max_inflight", C.c_int32), ("n_streams", C.c_int32),
+                ("max_batch", C.c_int32), ("device", C.c_int32)]
+
+
+class rqc_request(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("n_open", C.c_int32),
+                ("gates", C.POINTER(rqc_gate)), ("n_gates", C.c_uint64),
+                ("open_qubits", C.POINTER(C.c_int32)), ("closed_bits", C.POINTER(C.c_uint8)),
+                ("prec", C.c_int32), ("max_log2_elems", C.c_int32), ("plan_key", C.c_uint64),
+                ("seed", C.c_uint64)]
+
+
+class rqc_result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("n_open", C.c_int32),
+                ("amplitudes", C.POINTER(C.c_double)), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double), ("fp32_reruns", C.c_uint64)]
+
+
+class rqc_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rejected", C.c_uint64),
+                ("plans_built", C.c_uint64), ("plans_reused", C.c_uint64),
+                ("peak_bytes", C.c_uint64), ("max_inflight_seen", C.c_uint64)]
+
+
+# ---------------------------------------------------------------- prototypes
+_P = C.c_void_p
+_S = C.c_int32
+_PROTOS = {
+    "rqc_circuit_create": (_S, [C.c_int32, C.POINTER(rqc_gate), C.c_size_t, C.POINTER(_P)]),
+    "rqc_circuit_destroy": (None, [_P]),
+    "rqc_network_create": (_S, [_P, C.POINTER(C.c_int32), C.c_int32, C.POINTER(_P)]),
+    "rqc_network_destroy": (None, [_P]),
+    "rqc_plan_opts_default": (None, [C.POINTER(rqc_plan_opts)]),
+    "rqc_plan_create": (_S, [_P, C.POINTER(rqc_plan_opts), C.POINTER(_P)]),
+    "rqc_plan_destroy": (None, [_P]),
+    "rqc_plan_get_info": (_S, [_P, C.POINTER(rqc_plan_info)]),
+    "rqc_plan_get_step": (_S, [_P, C.c_int32, C.POINTER(rqc_step_info)]),
+    "rqc_plan_export_json": (_S, [_P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "rqc_plan_resident_bytes": (_S, [_P, C.POINTER(C.c_size_t)]),
+    "rqc_plan_bind": (_S, [_P, _P, C.c_size_t, _P]),
+    "rqc_contract_workspace": (_S, [_P, C.c_uint64, C.c_uint64, C.c_int32,
+                                    C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "rqc_contract": (_S, [_P, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint8),
+                          C.c_uint64, C.c_int32, _P, C.c_size_t, _P, _P, _P]),
+    "rqc_contract_report": (_S, [_P, _P, C.POINTER(rqc_run_report)]),
+    "rqc_pair_contract": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                               C.POINTER(C.c_int32), C.c_int32, _P, _P, _P, C.c_int32,
+                               C.c_int64, C.c_int64, C.c_int64, C.c_int32, _P]),
+    "rqc_permute": (_S, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, _P, _P, _P]),
+    "rqc_cgemm": (_S, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P]),
+    "rqc_server_create": (_S, [C.POINTER(rqc_server_opts), C.POINTER(_P)]),
+    "rqc_server_submit": (_S, [_P, C.POINTER(rqc_request), C.POINTER(C.c_uint64)]),
+    "rqc_server_poll": (_S, [_P, C.POINTER(rqc_result), C.c_size_t, C.POINTER(C.c_size_t)]),
+    "rqc_server_release": (_S, [_P, C.c_uint64]),
+    "rqc_server_drain": (_S, [_P]),
+    "rqc_server_get_stats": (_S, [_P, C.POINTER(rqc_server_stats)]),
+    "rqc_server_destroy": (None, [_P]),
+    "rqc_last_error": (C.c_char_p, []),
+    "rqc_version": (C.c_char_p, []),
+    "rqc_plan_set_scale_bias": (_S, [_P, C.c_int32]),
+}
+for _name, (_res, _args) in _PROTOS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = sorted(_PROTOS)
+
+
+def _check(code):
+    if code != OK:
+        raise RqcError(code, _lib.rqc_last_error().decode())
+
+
+def version() -> str:
+    return _lib.rqc_version().decode()
+
+
+def _i32(seq):
+    arr = (C.c_int32 * max(1, len(seq)))(*[int(x) for x in seq])
+    return arr
+
+
+def _stream_handle(stream=None):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+
+
+def _ptr(t):
+    return C.c_void_p(int(t.data_ptr()))
+
+
+# ---------------------------------------------------------------- gates
+def to_gate_array(gates):
+    """rqcgen.Gate list (or tuples) -> ctypes array of rqc_gate."""
+    arr = (rqc_gate * max(1, len(gates)))()
+    for i, g in enumerate(gates):
+        a = arr[i]
+        a.kind = int(g.kind)
+        a.q0 = int(g.q0)
+        a.q1 = int(g.q1) if g.q1 is not None else -1
+        a.theta = float(g.theta)
+        a.phi = float(g.phi)
+        if g.u is not None:
+            u = np.asarray(g.u, dtype=np.complex128).reshape(-1)
+            for j, v in enumerate(u):
+                a.u[2 * j] = v.real
+                a.u[2 * j + 1] = v.imag
+    return arr
+
+
+class Circuit:
+    def __init__(self, n_qubits: int, gates):
+        self._gates = to_gate_array(gates)
+        h = C.c_void_p()
+        _check(_lib.rqc_circuit_create(int(n_qubits), self._gates, len(gates), C.byref(h)))
+        self.h = h
+        self.n_qubits = int(n_qubits)
+
+    @classmethod
+    def from_rqcgen(cls, circ):
+        return cls(circ.n_qubits, circ.gates)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.rqc_circuit_destroy(self.h)
+            self.h = None
+
+
+class Network:
+    def __init__(self, circuit: Circuit, open_qubits):
+        self.open = [int(q) for q in open_qubits]
+        h = C.c_void_p()
+        _check(_lib.rqc_network_create(circuit.h, _i32(self.open), len(self.open), C.byref(h)))
+        self.h = h
+        self.n_qubits = circuit.n_qubits
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.rqc_network_destroy(self.h)
+            self.h = None
+
+
+class Plan:
+    """Contraction path + slicing plan, optionally bound to device memory."""
+
+    def __init__(self, network: Network, max_log2_elems=0, n_sliced=-1, path_trials=256,
+                 reconf_rounds=-1, seed=0, forced_wires=(), lp_min_log2=0):
+        o = rqc_plan_opts()
+        _lib.rqc_plan_opts_default(C.byref(o))
+        o.max_log2_elems = int(max_log2_elems)
+        o.n_sliced = int(n_sliced)
+        o.path_trials = int(path_trials)
+        o.reconf_rounds = int(reconf_rounds)
+        o.seed = int(seed)
+        flat = [int(x) for w in forced_wires for x in w]
+        self._forced = _i32(flat)
+        o.n_forced = len(forced_wires)
+        o.forced_wires = C.cast(self._forced, C.POINTER(C.c_int32))
+        o.lp_min_log2 = int(lp_min_log2)
+        h = C.c_void_p()
+        _check(_lib.rqc_plan_create(network.h, C.byref(o), C.byref(h)))
+        self.h = h
+        self.open = list(network.open)
+        self.n_qubits = network.n_qubits
+        self._resident = None
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.rqc_plan_destroy(self.h)
+            self.h = None
+
+    # ---- host-side description
+    def info(self) -> dict:
+        i = rqc_plan_info()
+        _check(_lib.rqc_plan_get_info(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in rqc_plan_info._fields_}
+
+    def steps(self):
+        out = []
+        for k in range(self.info()["n_steps"]):
+            s = rqc_step_info()
+            _check(_lib.rqc_plan_get_step(self.h, k, C.byref(s)))
+            out.append({f: getattr(s, f) for f, _ in rqc_step_info._fields_})
+        return out
+
+    def export(self) -> dict:
+        need = C.c_size_t()
+        _check(_lib.rqc_plan_export_json(self.h, None, 0, C.byref(need)))
+        buf = C.create_string_buffer(need.value)
+        _check(_lib.rqc_plan_export_json(self.h, buf, need.value, C.byref(need)))
+        return json.loads(buf.value.decode())
+
+    def sliced_wires(self):
+        return [tuple(w) for w in self.export()["sliced_wires"]]
+
+    def resident_bytes(self) -> int:
+        b = C.c_size_t()
+        _check(_lib.rqc_plan_resident_bytes(self.h, C.byref(b)))
+        return b.value
+
+    def workspace_bytes(self, n_ids=0, n_batch=1, prec=F32):
+        lo, pref = C.c_size_t(), C.c_size_t()
+        _check(_lib.rqc_contract_workspace(self.h, int(n_ids), int(n_batch), int(prec),
+                                           C.byref(lo), C.byref(pref)))
+        return lo.value, pref.value
+
+    # ---- device
+    def bind(self, device="cuda", stream=None):
+        import torch
+        nbytes = max(256, self.resident_bytes())
+        self._resident = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _check(_lib.rqc_plan_bind(self.h, _ptr(self._resident), nbytes, _stream_handle(stream)))
+        return self
+
+    def set_scale_bias(self, bias: int):
+        _check(_lib.rqc_plan_set_scale_bias(self.h, int(bias)))
+
+    def contract(self, closed_bits, slice_ids=None, prec=F32, workspace=None,
+                 per_slice=False, stream=None, sync=True, out=None):
+        """Amplitudes (complex128, shape (n_batch, 2^n_open)) summed over slices.
+
+        closed_bits: array (n_batch, n_closed) or (n_closed,) of 0/1.
+        workspace: torch uint8 device tensor, or None for the preferred size.
+        """
+        import torch
+        bits = np.ascontiguousarray(np.asarray(closed_bits, dtype=np.uint8))
+        if bits.ndim == 1:
+            bits = bits.reshape(1, -1)
+        n_batch = bits.shape[0]
+        prec = PRECISIONS.get(prec, prec) if isinstance(prec, str) else int(prec)
+        ids = None if slice_ids is None else np.ascontiguousarray(np.asarray(slice_ids, dtype=np.uint64))
+        n_ids = 0 if ids is None else ids.size
+        n_out = n_batch * (1 << len(self.open))
+        dev = self._resident.device
+        if out is None:
+            out = torch.empty(2 * n_out, dtype=torch.float64, device=dev)
+        ps = None
+        if per_slice:
+            cnt = n_ids if ids is not None else self.info()["n_slices"]
+            ps = torch.zeros(2 * n_out * cnt, dtype=torch.float64, device=dev)
+        if workspace is None:
+            lo, pref = self.workspace_bytes(n_ids, n_batch, prec)
+            if self._ws is None or self._ws.numel() < pref:
+                self._ws = torch.empty(pref, dtype=torch.uint8, device=dev)
+            workspace = self._ws
+        idp = ids.ctypes.data_as(C.POINTER(C.c_uint64)) if ids is not None else None
+        _check(_lib.rqc_contract(self.h, idp, n_ids, bits.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                 n_batch, prec, _ptr(workspace), workspace.numel(), _ptr(out),
+                                 _ptr(ps) if ps is not None else None, _stream_handle(stream)))
+        self.last_report = None
+        if sync:
+            self.last_report = self.report(stream)
+        amps = out.view(n_batch, -1, 2)
+        if per_slice:
+            return amps, ps.view(-1, n_batch, 1 << len(self.open), 2)
+        return amps
+
+    def report(self, stream=None) -> dict:
+        r = rqc_run_report()
+        _check(_lib.rqc_contract_report(self.h, _stream_handle(stream), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in rqc_run_report._fields_}
+
+
+def to_complex(t):
+    """(..., 2) float64 tensor/array -> complex128 numpy array."""
+    a = t.detach().cpu().numpy() if hasattr(t, "detach") else np.asarray(t)
+    return a[..., 0] + 1j * a[..., 1]
+
+
+# ---------------------------------------------------------------- single steps
+def pair_contract(A, B, labels_a, labels_b, labels_c, C_out=None, kernel=-1, batch=1,
+                  stride_a=0, stride_b=0, stride_c=0, stream=None):
+    """C = A * B summed over shared labels (complex64 torch tensors on device)."""
+    import torch
+    if C_out is None:
+        C_out = torch.empty(batch << len(labels_c), dtype=torch.complex64, device=A.device)
+        stride_c = 1 << len(labels_c) if batch > 1 else stride_c
+    _check(_lib.rqc_pair_contract(_i32(labels_a), len(labels_a), _i32(labels_b), len(labels_b),
+                                  _i32(labels_c), len(labels_c), _ptr(A), _ptr(B), _ptr(C_out),
+                                  int(batch), int(stride_a), int(stride_b), int(stride_c),
+                                  int(kernel), _stream_handle(stream)))
+    return C_out
+
+
+def permute(X, labels_in, labels_out, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty_like(X)
+    _check(_lib.rqc_permute(_i32(labels_in), _i32(labels_out), len(labels_in), _ptr(X), _ptr(out),
+                            _stream_handle(stream)))
+    return out
+
+
+def cgemm(A, B, M, N, K, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty(M * N, dtype=torch.complex64, device=A.device)
+    _check(_lib.rqc_cgemm(int(M), int(N), int(K), _ptr(A), _ptr(B), _ptr(out), _stream_handle(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching server over a device pool allocated with torch."""
+
+    def __init__(self, budget_bytes, max_inflight=8, n_streams=4, max_batch=64, device=0):
+        import torch
+        self._pool = torch.empty(int(budget_bytes), dtype=torch.uint8, device=f"cuda:{device}")
+        o = rqc_server_opts()
+        o.device_pool = C.c_void_p(int(self._pool.data_ptr()))
+        o.hbm_budget_bytes = int(budget_bytes)
+        o.max_inflight = int(max_inflight)
+        o.n_streams = int(n_streams)
+        o.max_batch = int(max_batch)
+        o.device = int(device)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        _check(_lib.rqc_server_create(C.byref(o), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, n_qubits, gates, open_qubits, closed_bits, prec=F32, max_log2_elems=0,
+               plan_key=0, seed=0) -> int:
+        g = to_gate_array(gates)
+        op = _i32(open_qubits)
+        bits = (C.c_uint8 * max(1, len(closed_bits)))(*[int(b) for b in closed_bits])
+        r = rqc_request()
+        r.n_qubits = int(n_qubits)
+        r.n_open = len(open_qubits)
+        r.gates = C.cast(g, C.POINTER(rqc_gate))
+        r.n_gates = len(gates)
+        r.open_qubits = C.cast(op, C.POINTER(C.c_int32))
+        r.closed_bits = C.cast(bits, C.POINTER(C.c_uint8))
+        r.prec = int(prec)
+        r.max_log2_elems = int(max_log2_elems)
+        r.plan_key = int(plan_key)
+        r.seed = int(seed)
+        t = C.c_uint64()
+        _check(_lib.rqc_server_submit(self.h, C.byref(r), C.byref(t)))
+        return t.value
+
+    def poll(self, cap=256):
+        arr = (rqc_result * cap)()
+        n = C.c_size_t()
+        _check(_lib.rqc_server_poll(self.h, arr, cap, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = arr[i]
+            amps = None
+            if r.status == OK:
+                ne = 1 << r.n_open
+                buf = np.ctypeslib.as_array(r.amplitudes, shape=(2 * ne,)).copy()
+                amps = buf[0::2] + 1j * buf[1::2]
+            _check(_lib.rqc_server_release(self.h, r.ticket))
+            out.append({"ticket": r.ticket, "status": r.status, "amplitudes": amps,
+                        "t_submit": r.t_submit, "t_start": r.t_start, "t_done": r.t_done,
+                        "fp32_reruns": r.fp32_reruns})
+        return out
+
+    def drain(self):
+        _check(_lib.rqc_server_drain(self.h))
+
+    def stats(self) -> dict:
+        s = rqc_server_stats()
+        _check(_lib.rqc_server_get_stats(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in rqc_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.rqc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,371 @@
+// C ABI (include/rqc.h).  Every entry point catches C++ exceptions and turns
+// them into rqc_status codes with a thread-local message.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "executor.h"
+
+struct rqc_circuit {
+  rqc::Circuit c;
+};
+struct rqc_network {
+  rqc::Network n;
+};
+
+namespace rqc {
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+}  // namespace rqc
+
+#define RQC_TRY try {
+#define RQC_CATCH                                              \
+  }                                                            \
+  catch (const rqc::Error& e) {                                \
+    rqc::set_error(e.msg);                                     \
+    return e.code;                                             \
+  }                                                            \
+  catch (const std::bad_alloc&) {                              \
+    rqc::set_error("host allocation failed");                  \
+    return RQC_ENOMEM;                                         \
+  }                                                            \
+  catch (const std::exception& e) {                            \
+    rqc::set_error(e.what());                                  \
+    return RQC_EINVAL;                                         \
+  }
+
+extern "C" {
+
+const char* rqc_last_error(void) { return rqc::g_err.c_str(); }
+const char* rqc_version(void) { return "rqc 0.1 gfx950"; }
+
+rqc_status rqc_circuit_create(int32_t n_qubits, const rqc_gate* gates, size_t n_gates,
+                              rqc_circuit** out) {
+  RQC_TRY
+  if (!out) throw rqc::Error{RQC_EINVAL, "out is NULL"};
+  *out = nullptr;
+  if (n_qubits <= 0 || n_qubits > 4096) throw rqc::Error{RQC_EINVAL, "n_qubits out of range"};
+  if (n_gates && !gates) throw rqc::Error{RQC_EINVAL, "gates is NULL"};
+  auto* c = new rqc_circuit;
+  c->c.n = n_qubits;
+  for (size_t i = 0; i < n_gates; ++i) {
+    const rqc_gate& g = gates[i];
+    rqc::Gate h;
+    h.kind = g.kind;
+    h.q0 = g.q0;
+    h.q1 = g.q1;
+    h.theta = g.theta;
+    h.phi = g.phi;
+    const bool two = g.kind == RQC_GATE_FSIM || g.kind == RQC_GATE_U2;
+    if (g.kind < RQC_GATE_H || g.kind > RQC_GATE_U2) {
+      delete c;
+      throw rqc::Error{RQC_EINVAL, "unknown gate kind at index " + std::to_string(i)};
+    }
+    if (g.q0 < 0 || g.q0 >= n_qubits || (two && (g.q1 < 0 || g.q1 >= n_qubits || g.q1 == g.q0))) {
+      delete c;
+      throw rqc::Error{RQC_EINVAL, "bad qubit index at gate " + std::to_string(i)};
+    }
+    if (!two) h.q1 = -1;
+    if (g.kind == RQC_GATE_U1)
+      for (int j = 0; j < 4; ++j) h.u.emplace_back(g.u[2 * j], g.u[2 * j + 1]);
+    if (g.kind == RQC_GATE_U2)
+      for (int j = 0; j < 16; ++j) h.u.emplace_back(g.u[2 * j], g.u[2 * j + 1]);
+    c->c.gates.push_back(std::move(h));
+  }
+  *out = c;
+  return RQC_OK;
+  RQC_CATCH
+}
+
+void rqc_circuit_destroy(rqc_circuit* c) { delete c; }
+
+rqc_status rqc_network_create(const rqc_circuit* c, const int32_t* open_qubits, int32_t n_open,
+                              rqc_network** out) {
+  RQC_TRY
+  if (!c || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  *out = nullptr;
+  if (n_open < 0 || n_open > 24 || (n_open && !open_qubits))
+    throw rqc::Error{RQC_EINVAL, "n_open must be in [0, 24]"};
+  std::vector<int> open(open_qubits, open_qubits + n_open);
+  auto* n = new rqc_network;
+  try {
+    n->n = rqc::build_network(c->c, open);
+  } catch (...) {
+    delete n;
+    throw;
+  }
+  *out = n;
+  return RQC_OK;
+  RQC_CATCH
+}
+
+void rqc_network_destroy(rqc_network* n) { delete n; }
+
+void rqc_plan_opts_default(rqc_plan_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->max_log2_elems = 0;
+  o->n_sliced = -1;
+  o->path_trials = 256;
+  o->reconf_rounds = -1;
+  o->seed = 0;
+  o->lp_min_log2 = 14;
+}
+
+rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_plan** out) {
+  RQC_TRY
+  if (!n || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  *out = nullptr;
+  rqc_plan_opts o;
+  rqc_plan_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.max_log2_elems < 0 || o.max_log2_elems > 40) throw rqc::Error{RQC_EINVAL, "max_log2_elems out of range"};
+  if (o.n_sliced < -1) throw rqc::Error{RQC_EINVAL, "n_sliced < -1"};
+  if (o.n_forced < 0 || (o.n_forced && !o.forced_wires)) throw rqc::Error{RQC_EINVAL, "forced wires"};
+  auto* p = new rqc_plan;
+  try {
+    p->pd.net = n->n;
+    rqc::PlanOpts& po = p->pd.opts;
+    po.max_log2 = o.max_log2_elems;
+    po.n_sliced = o.n_sliced;
+    po.trials = o.path_trials > 0 ? o.path_trials : 256;
+    po.reconf_rounds = o.reconf_rounds < 0 ? 4 : o.reconf_rounds;
+    po.seed = o.seed;
+    for (int i = 0; i < o.n_forced; ++i) po.forced.push_back({o.forced_wires[2 * i], o.forced_wires[2 * i + 1]});
+    po.lp_min_log2 = o.lp_min_log2 > 0 ? o.lp_min_log2 : 14;
+    rqc::make_plan(p->pd);
+    rqc::resident_bytes(p);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  *out = p;
+  return RQC_OK;
+  RQC_CATCH
+}
+
+void rqc_plan_destroy(rqc_plan* p) { delete p; }
+
+rqc_status rqc_plan_get_info(const rqc_plan* p, rqc_plan_info* out) {
+  RQC_TRY
+  if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  const rqc::PlanData& pd = p->pd;
+  std::memset(out, 0, sizeof *out);
+  out->n_qubits = pd.net.n_qubits;
+  out->n_open = (int)pd.net.open.size();
+  out->n_closed = (int)pd.net.closed.size();
+  out->n_sliced = (int)pd.sliced.size();
+  out->n_slices = uint64_t(1) << pd.sliced.size();
+  out->n_leaves = pd.tree.n_leaves;
+  out->n_steps = (int)pd.steps.size();
+  for (auto& st : pd.steps) out->n_invariant_steps += st.invariant ? 1 : 0;
+  out->max_log2_elems = pd.max_log2;
+  out->flops_per_slice = pd.flops_per_slice;
+  out->flops_invariant = pd.flops_invariant;
+  out->bytes_per_slice = pd.bytes_per_slice;
+  out->log2_total_flops = std::log2(pd.flops_per_slice * (double)out->n_slices + pd.flops_invariant + 1e-300);
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_get_step(const rqc_plan* p, int32_t i, rqc_step_info* out) {
+  RQC_TRY
+  if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  if (i < 0 || i >= (int)p->pd.steps.size()) throw rqc::Error{RQC_EINVAL, "step index out of range"};
+  const rqc::Step& st = p->pd.steps[i];
+  std::memset(out, 0, sizeof *out);
+  out->m = st.m;
+  out->n = st.n;
+  out->k = st.k;
+  out->kernel = (st.kernel == 1 && st.m >= 7 && st.n >= 6 && st.k >= 4) ? 1 : 0;
+  out->depends_on_slice = st.dep_s;
+  out->depends_on_bits = st.dep_b;
+  out->lp_output = st.lp;
+  out->flops = 8.0 * std::ldexp(1.0, st.m + st.n + st.k);
+  out->bytes_c64 = 8.0 * (std::ldexp(1.0, st.m + st.k) + std::ldexp(1.0, st.n + st.k) + std::ldexp(1.0, st.m + st.n));
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_export_json(const rqc_plan* p, char* buf, size_t cap, size_t* needed) {
+  RQC_TRY
+  if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
+  const std::string s = rqc::plan_json(p->pd);
+  if (needed) *needed = s.size() + 1;
+  if (buf && cap) {
+    const size_t n = std::min(cap - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+    if (cap < s.size() + 1) throw rqc::Error{RQC_EINVAL, "buffer too small"};
+  }
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_resident_bytes(const rqc_plan* p, size_t* bytes) {
+  RQC_TRY
+  if (!p || !bytes) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  *bytes = (size_t)p->inv_bytes;
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_bind(rqc_plan* p, void* dev_ptr, size_t bytes, rqc_stream stream) {
+  RQC_TRY
+  if (!p || !dev_ptr) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  rqc::bind_plan(p, dev_ptr, bytes, static_cast<hipStream_t>(stream));
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_contract_workspace(const rqc_plan* pc, uint64_t n_ids, uint64_t n_batch, int32_t prec,
+                                  size_t* min_bytes, size_t* pref_bytes) {
+  RQC_TRY
+  if (!pc) throw rqc::Error{RQC_EINVAL, "NULL plan"};
+  rqc_plan* p = const_cast<rqc_plan*>(pc);
+  if (prec != RQC_F32 && prec != RQC_F16 && prec != RQC_BF16) throw rqc::Error{RQC_EINVAL, "bad precision"};
+  if (n_ids == 0) n_ids = uint64_t(1) << p->pd.sliced.size();
+  if (n_batch == 0) throw rqc::Error{RQC_EINVAL, "n_batch must be positive"};
+  const rqc::GroupLayout& L1 = rqc::group_layout(p, prec, 1, 1);
+  if (min_bytes) *min_bytes = (size_t)rqc::ws_layout(p, L1, n_ids, n_batch).total;
+  if (pref_bytes) {
+    const int gs = (int)std::min<uint64_t>(n_ids, 4096), gb = (int)std::min<uint64_t>(n_batch, 4096);
+    const rqc::GroupLayout& L = rqc::group_layout(p, prec, gs, gb);
+    *pref_bytes = (size_t)rqc::ws_layout(p, L, n_ids, n_batch).total;
+  }
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_contract(rqc_plan* p, const uint64_t* slice_ids, uint64_t n_ids,
+                        const uint8_t* closed_bits, uint64_t n_batch, int32_t prec, void* workspace,
+                        size_t ws_bytes, double* out, double* per_slice, rqc_stream stream) {
+  RQC_TRY
+  if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
+  rqc::contract(p, slice_ids, n_ids, closed_bits, n_batch, prec, workspace, ws_bytes, out, per_slice,
+                static_cast<hipStream_t>(stream), p->pending);
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_contract_report(rqc_plan* p, rqc_stream stream, rqc_run_report* out) {
+  RQC_TRY
+  if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  rqc::report(p, p->pending, static_cast<hipStream_t>(stream), out);
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias) {
+  RQC_TRY
+  if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
+  if (bias < -64 || bias > 64) throw rqc::Error{RQC_EINVAL, "bias out of range"};
+  p->scale_bias = bias;
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+  return RQC_OK;
+  RQC_CATCH
+}
+
+// ---- single pairwise contraction, permutation, GEMM ---------------------
+
+rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int32_t* labels_b,
+                             int32_t rank_b, const int32_t* labels_c, int32_t rank_c, const void* A,
+                             const void* B, void* C, int32_t batch_count, int64_t stride_a,
+                             int64_t stride_b, int64_t stride_c, int32_t kernel, rqc_stream stream) {
+  RQC_TRY
+  if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
+  if (rank_a < 0 || rank_b < 0 || rank_c < 0 || rank_a > 40 || rank_b > 40 || rank_c > 40)
+    throw rqc::Error{RQC_EINVAL, "rank out of range"};
+  if ((rank_a && !labels_a) || (rank_b && !labels_b) || (rank_c && !labels_c))
+    throw rqc::Error{RQC_EINVAL, "NULL labels"};
+  if (batch_count < 1 || batch_count > 65535) throw rqc::Error{RQC_EINVAL, "batch_count out of range"};
+  if (kernel < -1 || kernel > 1) throw rqc::Error{RQC_EINVAL, "kernel must be -1, 0 or 1"};
+  std::vector<int> la(labels_a, labels_a + rank_a), lb(labels_b, labels_b + rank_b),
+      lc(labels_c, labels_c + rank_c);
+  for (auto* l : {&la, &lb}) {
+    std::vector<int> s(*l);
+    std::sort(s.begin(), s.end());
+    if (std::adjacent_find(s.begin(), s.end()) != s.end()) throw rqc::Error{RQC_EINVAL, "repeated label"};
+  }
+  int m = 0, n = 0, k = 0;
+  for (int x : la) (std::find(lb.begin(), lb.end(), x) != lb.end() ? k : m)++;
+  n = rank_b - k;
+  const int kern = kernel >= 0 ? kernel : rqc::choose_kernel(m, n, k);
+  rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, kern);
+  d.A = A;
+  d.B = B;
+  d.C = C;
+  d.sA_s = stride_a;
+  d.sB_s = stride_b;
+  d.sC_s = stride_c;
+  d.gs_c = batch_count;
+  d.copies = batch_count;
+  const int use = (kern == 1 && d.rt == 7 && d.nt == 6 && d.kt == 4) ? 1 : 0;
+  rqc::hip_check(rqc::launch_step(d, use, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, 0,
+                                  static_cast<hipStream_t>(stream)),
+                 "pair contract");
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_permute(const int32_t* labels_in, const int32_t* labels_out, int32_t rank,
+                       const void* in, void* out, rqc_stream stream) {
+  RQC_TRY
+  if (!in || !out || rank < 0 || rank > 40 || (rank && (!labels_in || !labels_out)))
+    throw rqc::Error{RQC_EINVAL, "bad argument"};
+  if (in == out) throw rqc::Error{RQC_EINVAL, "in-place permutation not supported"};
+  std::vector<int8_t> src(rank > 0 ? rank : 1);
+  std::vector<int> li(labels_in, labels_in + rank);
+  for (int i = 0; i < rank; ++i) {
+    const int x = labels_out[rank - 1 - i];  // output bit i
+    auto it = std::find(li.begin(), li.end(), x);
+    if (it == li.end()) throw rqc::Error{RQC_EINVAL, "labels_out is not a permutation of labels_in"};
+    src[i] = (int8_t)(rank - 1 - (it - li.begin()));
+  }
+  {
+    std::vector<int8_t> s(src.begin(), src.begin() + rank);
+    std::sort(s.begin(), s.end());
+    if (std::adjacent_find(s.begin(), s.end()) != s.end()) throw rqc::Error{RQC_EINVAL, "repeated label"};
+  }
+  if (rank == 0) {
+    rqc::hip_check(hipMemcpyAsync(out, in, 8, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)), "copy");
+    return RQC_OK;
+  }
+  rqc::hip_check(rqc::launch_permute(in, out, rank, src.data(), static_cast<hipStream_t>(stream)), "permute");
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_cgemm(int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
+                     rqc_stream stream) {
+  RQC_TRY
+  auto lg = [](int64_t x) {
+    if (x <= 0 || (x & (x - 1))) throw rqc::Error{RQC_EUNSUPPORTED, "dimensions must be powers of two"};
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+  };
+  const int m = lg(M), n = lg(N), k = lg(K);
+  if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
+  std::vector<int> la, lb, lc;
+  for (int i = 0; i < m; ++i) la.push_back(i);
+  for (int i = 0; i < k; ++i) la.push_back(100 + i);
+  for (int i = 0; i < k; ++i) lb.push_back(100 + i);
+  for (int i = 0; i < n; ++i) lb.push_back(200 + i);
+  for (int i = 0; i < m; ++i) lc.push_back(i);
+  for (int i = 0; i < n; ++i) lc.push_back(200 + i);
+  rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, 1);
+  d.A = A;
+  d.B = B;
+  d.C = C;
+  const int use = (d.rt == 7 && d.nt == 6 && d.kt == 4) ? 1 : 0;
+  rqc::hip_check(rqc::launch_step(d, use, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, 0,
+                                  static_cast<hipStream_t>(stream)),
+                 "cgemm");
+  return RQC_OK;
+  RQC_CATCH
+}
+
+}  // extern "C"

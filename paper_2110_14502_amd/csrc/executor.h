@@ -1,0 +1,113 @@
+// Executor: residency, per-group memory layout, step descriptors, graph
+// capture of a whole contraction call.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <tuple>
+
+#include "core.h"
+#include "kernels.h"
+
+namespace rqc {
+
+// Where a tensor of the contraction tree lives during a call.
+struct Placement {
+  bool resident = false;     // invariant: in the plan's resident memory
+  int64_t off = 0;           // bytes from the region base
+  int store = ST_C64;
+  int64_t s_stride = 0, b_stride = 0;  // copy strides, elements
+  int64_t e_off = -1;        // bytes of the exponent array (-1: none)
+  int64_t m_off = -1;        // bytes of the max array (-1: none)
+  int32_t es = 0, eb = 0;    // copy strides of the scale arrays
+  float max_const = 0.f;     // leaves: bound on |re|, |im|
+  bool dep_s = false, dep_b = false;
+};
+
+// Memory layout of one (precision, slices per group, bits per group).
+struct GroupLayout {
+  int prec = RQC_F32, gs = 1, gb = 1;
+  std::vector<Placement> place;  // per tree node
+  int64_t arena_bytes = 0;       // variable tensors
+  int64_t scale_bytes = 0;       // exponent / max arrays
+  std::vector<LeafJob> jobs;     // variable leaves
+  int max_leaf_rank = 0;
+};
+
+struct GraphKey {
+  int prec, gs, gb;
+  uint64_t n_ids, n_batch;
+  const void* ws;
+  const void* out;
+  const void* per_slice;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(prec, gs, gb, n_ids, n_batch, ws, out, per_slice) <
+           std::tie(o.prec, o.gs, o.gb, o.n_ids, o.n_batch, o.ws, o.out, o.per_slice);
+  }
+};
+
+struct PendingRun {
+  bool active = false;
+  int prec = RQC_F32;
+  uint64_t n_ids = 0, n_batch = 0;
+  std::vector<uint64_t> ids;
+  std::vector<uint8_t> bits;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* out = nullptr;
+  double* per_slice = nullptr;
+  int gs = 1, gb = 1;
+  int graph_reused = 0;
+  double flops = 0;
+};
+
+struct WsLayout {
+  int64_t ids_off, bits_off, flags_off, jobs_off, tmp_off, scale_off, arena_off, total;
+};
+
+}  // namespace rqc
+
+struct rqc_plan {
+  rqc::PlanData pd;
+  // Resident memory.
+  char* res = nullptr;
+  size_t res_bytes = 0;
+  bool bound = false;
+  std::vector<int64_t> leaf_store_off;  // per leaf, element offset (c64)
+  int64_t leaf_store_elems = 0;
+  std::vector<float> leaf_max;          // per leaf
+  std::vector<int64_t> inv_off;         // per node: bytes in resident, -1
+  int64_t inv_max_off = 0;              // bytes: float per node
+  int64_t inv_bytes = 0;
+  int scale_bias = 0;
+  // Caches.
+  std::map<std::tuple<int, int, int>, rqc::GroupLayout> layouts;
+  std::map<rqc::GraphKey, hipGraphExec_t> graphs;
+  hipStream_t capture_stream = nullptr;
+  rqc::PendingRun pending;
+  ~rqc_plan();
+};
+
+namespace rqc {
+
+size_t resident_bytes(rqc_plan* p);
+void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s);
+const GroupLayout& group_layout(rqc_plan* p, int prec, int gs, int gb);
+WsLayout ws_layout(rqc_plan* p, const GroupLayout& L, uint64_t n_ids, uint64_t n_batch);
+// Enqueue a contraction call on `s` (one graph launch); `run` keeps what the
+// report needs.
+void contract(rqc_plan* p, const uint64_t* ids, uint64_t n_ids, const uint8_t* bits,
+              uint64_t n_batch, int prec, void* ws, size_t ws_bytes, double* out,
+              double* per_slice, hipStream_t s, PendingRun& run);
+// Synchronise `s`, re-run flagged slices in FP32, fill the report.
+void report(rqc_plan* p, PendingRun& run, hipStream_t s, rqc_run_report* r);
+
+// Build the descriptor of one pairwise contraction given operand labels
+// (MSB first), the kernel and copy strides.
+StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
+                        const std::vector<int>& lc, int kernel);
+
+void hip_check(hipError_t e, const char* what);
+
+}  // namespace rqc

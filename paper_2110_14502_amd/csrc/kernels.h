@@ -1,0 +1,96 @@
+// Device-side descriptors shared by the kernels and the executor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace rqc {
+
+// Storage type codes of an operand.
+enum Store : int { ST_C64 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+constexpr int kMaxTile = 16;   // tile bits per operand
+constexpr int kMaxOuter = 44;  // outer bits per role
+
+// Where each tile bit of one operand lives: its address bit in global
+// memory and its coordinate bit in the LDS tile.  Tile bits are listed in
+// increasing global address order so that consecutive lanes touch
+// consecutive (or nearly consecutive) addresses.
+struct TileMap {
+  int32_t nbits;
+  int8_t gpos[kMaxTile];  // address bit in the operand
+  int8_t role[kMaxTile];  // 0 row (M), 1 col (N), 2 summed (K)
+  int8_t cbit[kMaxTile];  // bit inside that role's tile index
+};
+
+// One pairwise contraction C[m,n] = sum_k A[m,k] B[k,n] with every index of
+// dimension 2 and arbitrary bit layouts (the permutation is folded into the
+// tile loads and the store, Section 5.4).  `copies` independent problems run
+// side by side (slices x bitstrings of a group); copy j splits into
+// js = j % gs_c and jb = j / gs_c.
+struct StepDesc {
+  const void* A;
+  const void* B;
+  void* C;
+  // Per-copy power-of-two exponents and max-abs (reduced precision).
+  const int32_t* expA;
+  const int32_t* expB;
+  int32_t* expC;
+  const float* maxA;
+  const float* maxB;
+  float* maxC;
+  int32_t* flag;  // per slice (js) non-finite flag, may be null
+  float maxA_const, maxB_const;
+  int64_t sA_s, sA_b, sB_s, sB_b, sC_s, sC_b;  // copy strides, elements
+  int32_t eA_s, eA_b, eB_s, eB_b, eC_s, eC_b;  // copy strides, scale arrays
+  int32_t gs_c, copies;
+  int32_t rt, nt, kt;        // tile bits per role
+  int32_t n_ro, n_no, n_ko;  // outer bits per role
+  int32_t k_total;           // all summed bits
+  int32_t track;             // 1: exponents / max-abs / flags maintained
+  int32_t lp_out;            // 1: C stored in 16 bits (scaled)
+  int32_t bias;              // test hook: subtracted from the storage shift
+  int32_t dep_s_c;           // C varies with the slice (flag index js)
+  int32_t flag_n;            // slices of the group flagged when it does not
+  int32_t n_row_tiles, n_col_tiles;
+  int8_t ro_A[kMaxOuter], ro_C[kMaxOuter];
+  int8_t no_B[kMaxOuter], no_C[kMaxOuter];
+  int8_t ko_A[kMaxOuter], ko_B[kMaxOuter];
+  TileMap tA, tB, tC;
+};
+
+// Leaf instantiation (slice and bitstring binding).
+struct LeafJob {
+  int64_t src;        // element offset of the base tensor in the leaf store
+  int64_t dst;        // element offset of copy 0 in the destination
+  int32_t rank;       // bits of the instantiated tensor
+  int32_t nsel;       // selector bits
+  int8_t pos[8];      // base address bit of output bit i (LSB first)
+  int8_t sel_pos[8];  // base address bit of selector s
+  int16_t sel_src[8]; // >= 0: slice bit index; < 0: -(closed column) - 1
+  int32_t dep_s, dep_b;  // which copy dimensions the leaf varies along
+  int32_t dst_store;  // Store code of the destination
+  int32_t out_s, out_b;  // copy strides of the destination (elements)
+};
+
+// Launchers (kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_step(const StepDesc& d, int kernel, int sa, int sb, int sc, int lp_kind,
+                       hipStream_t s);
+hipError_t launch_leaves(const LeafJob* jobs_dev, int n_jobs, const void* leaf_store,
+                         void* dst_base, const uint64_t* slice_ids, const uint8_t* closed_bits,
+                         int n_closed, int gs, int gb, int max_rank, hipStream_t s);
+hipError_t launch_slice_sum(const void* root, int root_store, const int32_t* root_exp,
+                            int64_t root_s, int64_t root_b, int32_t re_s, int32_t re_b,
+                            int dep_s, int dep_b, int n_elems, int gs, int gb,
+                            const int32_t* flags, double* out, double* per_slice,
+                            int64_t ps_row0, int64_t n_batch_total, int64_t b0, int first,
+                            hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_add_f64(double* dst, const double* src, int64_t n, hipStream_t s);
+hipError_t launch_permute(const void* in, void* out, int rank, const int8_t* src_pos_of_out_bit,
+                          hipStream_t s);
+hipError_t launch_cgemm(int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
+                        hipStream_t s);
+
+}  // namespace rqc

@@ -1,0 +1,748 @@
+// HIP kernels for gfx950 (CDNA4): fused permute + complex GEMM contraction
+// steps (Section 5.4), slice / bitstring instantiation of the leaves
+// (Section 5.1), and the FP64 cross-slice reduction (Section 6.4).
+//
+// Complex arithmetic on the real matrix cores: an interleaved complex
+// A[m][k] is read as the real matrix A_r[m][2k+c] (c = 0 re, 1 im); the
+// complex B[k][n] is expanded per lane into the real 2x2 block
+//   B_r[2k+0][2n+0] = Br   B_r[2k+0][2n+1] = Bi
+//   B_r[2k+1][2n+0] = -Bi  B_r[2k+1][2n+1] = Br
+// so that A_r * B_r is exactly the interleaved complex C[m][2n+d].  The real
+// flops executed equal 8 per complex multiply-add, the algorithmic count.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace rqc {
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// Storage helpers
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ float2 load_c(const void* p, int64_t i);
+template <>
+__device__ __forceinline__ float2 load_c<ST_C64>(const void* p, int64_t i) {
+  return reinterpret_cast<const float2*>(p)[i];
+}
+template <>
+__device__ __forceinline__ float2 load_c<ST_F16>(const void* p, int64_t i) {
+  h2 v = reinterpret_cast<const h2*>(p)[i];
+  return make_float2((float)v.x, (float)v.y);
+}
+template <>
+__device__ __forceinline__ float2 load_c<ST_BF16>(const void* p, int64_t i) {
+  b2 v = reinterpret_cast<const b2*>(p)[i];
+  return make_float2((float)v.x, (float)v.y);
+}
+
+template <int S>
+__device__ __forceinline__ void store_c(void* p, int64_t i, float2 v);
+template <>
+__device__ __forceinline__ void store_c<ST_C64>(void* p, int64_t i, float2 v) {
+  reinterpret_cast<float2*>(p)[i] = v;
+}
+template <>
+__device__ __forceinline__ void store_c<ST_F16>(void* p, int64_t i, float2 v) {
+  h2 o;
+  o.x = (_Float16)v.x;
+  o.y = (_Float16)v.y;
+  reinterpret_cast<h2*>(p)[i] = o;
+}
+template <>
+__device__ __forceinline__ void store_c<ST_BF16>(void* p, int64_t i, float2 v) {
+  b2 o;
+  o.x = (__bf16)v.x;
+  o.y = (__bf16)v.y;
+  reinterpret_cast<b2*>(p)[i] = o;
+}
+
+// Smallest E with x <= 2^E, for x > 0.
+__device__ __forceinline__ int ceil_log2(float x) {
+  int e;
+  float m = frexpf(x, &e);
+  return m == 0.5f ? e - 1 : e;
+}
+
+__device__ __forceinline__ void decode(const TileMap& t, uint32_t e, int lo, int hi, int64_t& g,
+                                       int& r, int& cc, int& k) {
+  for (int b = lo; b < hi; ++b) {
+    if ((e >> (b - lo)) & 1) {
+      g += int64_t(1) << t.gpos[b];
+      const int v = 1 << t.cbit[b];
+      if (t.role[b] == 0) r += v;
+      else if (t.role[b] == 1) cc += v;
+      else k += v;
+    }
+  }
+}
+
+// Per-copy scale bookkeeping shared by both kernels' epilogues.
+struct Scale {
+  int shift;  // C_stored = acc * 2^-shift
+  int expC;
+};
+__device__ __forceinline__ Scale compute_scale(const StepDesc& d, int js, int jb) {
+  Scale s{0, 0};
+  if (!d.track) return s;
+  const int eA = d.expA ? d.expA[js * d.eA_s + jb * d.eA_b] : 0;
+  const int eB = d.expB ? d.expB[js * d.eB_s + jb * d.eB_b] : 0;
+  int t = 0;
+  if (d.lp_out) {
+    const float mA = d.maxA ? d.maxA[js * d.eA_s + jb * d.eA_b] : d.maxA_const;
+    const float mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
+    // |C_re|,|C_im| <= sum_k |A||B| <= 2^k * (sqrt2 mA)(sqrt2 mB): store so
+    // that this bound maps to 2^15, inside the binary16 range.
+    if (mA > 0.f && mB > 0.f && mA <= 3.0e38f && mB <= 3.0e38f)
+      t = d.k_total + 1 + ceil_log2(mA) + ceil_log2(mB) - 15 - d.bias;
+  }
+  s.shift = t;
+  s.expC = eA + eB + t;
+  return s;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void finish_scale(const StepDesc& d, int js, int jb, float local_max,
+                                             int bad, float* red, bool write_exp, const Scale& sc) {
+  if (!d.track) return;
+  float m = wave_max(local_max);
+  int anybad = __any(bad);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = m;
+    reinterpret_cast<int*>(red)[BLOCK / 64 + w] = anybad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float bm = 0.f;
+    int bb = 0;
+    for (int i = 0; i < BLOCK / 64; ++i) {
+      bm = fmaxf(bm, red[i]);
+      bb |= reinterpret_cast<int*>(red)[BLOCK / 64 + i];
+    }
+    const int ci = js * d.eC_s + jb * d.eC_b;
+    if (d.maxC) atomicMax(reinterpret_cast<unsigned int*>(d.maxC) + ci, __float_as_uint(bm));
+    if (write_exp && d.expC) d.expC[ci] = sc.expC;
+    if (bb && d.flag) {
+      if (d.dep_s_c) d.flag[js] = 1;
+      else
+        for (int i = 0; i < d.flag_n; ++i) d.flag[i] = 1;  // shared by every slice
+    }
+  }
+}
+
+__device__ __forceinline__ void outer_offsets(const StepDesc& d, uint64_t ro, uint64_t no, int js,
+                                              int jb, int64_t& oA, int64_t& oB, int64_t& oC) {
+  oA = js * d.sA_s + jb * d.sA_b;
+  oB = js * d.sB_s + jb * d.sB_b;
+  oC = js * d.sC_s + jb * d.sC_b;
+  for (int i = 0; i < d.n_ro; ++i)
+    if ((ro >> i) & 1) {
+      oA += int64_t(1) << d.ro_A[i];
+      oC += int64_t(1) << d.ro_C[i];
+    }
+  for (int i = 0; i < d.n_no; ++i)
+    if ((no >> i) & 1) {
+      oB += int64_t(1) << d.no_B[i];
+      oC += int64_t(1) << d.no_C[i];
+    }
+}
+
+__device__ __forceinline__ void k_offsets(const StepDesc& d, uint32_t kc, int64_t& kA, int64_t& kB) {
+  kA = 0;
+  kB = 0;
+  for (int i = 0; i < d.n_ko; ++i)
+    if ((kc >> i) & 1) {
+      kA += int64_t(1) << d.ko_A[i];
+      kB += int64_t(1) << d.ko_B[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SIMT contraction: memory-bound and small steps (row tile x all-or-part of
+// N, K in chunks).  Loads follow each operand's address order so that a
+// wavefront reads contiguous runs; results are stored in C address order.
+// ---------------------------------------------------------------------------
+constexpr int kSimtBlock = 256;
+constexpr int kSimtMaxC = 8;  // C tile <= 2048 elements
+
+template <int SA, int SB, int SC>
+__global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
+  extern __shared__ float2 smem2[];
+  const int R = 1 << d.rt, N = 1 << d.nt, K = 1 << d.kt;
+  const int ldA = K + 1, ldB = N + 1;
+  float2* As = smem2;
+  float2* Bs = As + R * ldA;
+  float* red = reinterpret_cast<float*>(Bs + K * ldB);
+  const int tid = threadIdx.x;
+  const uint64_t ro = blockIdx.x % (uint64_t)d.n_row_tiles;
+  const uint64_t no = blockIdx.x / (uint64_t)d.n_row_tiles;
+  const int nC = R * N;
+  const int cnt = (nC + kSimtBlock - 1) / kSimtBlock;
+  // Owned C elements (C address order).
+  int crow[kSimtMaxC], ccol[kSimtMaxC];
+  int64_t cg[kSimtMaxC];
+#pragma unroll
+  for (int i = 0; i < kSimtMaxC; ++i) {
+    crow[i] = 0;
+    ccol[i] = 0;
+    cg[i] = 0;
+    if (i < cnt) {
+      const uint32_t e = tid + i * kSimtBlock;
+      int kk = 0;
+      if ((int)e < nC) decode(d.tC, e, 0, d.tC.nbits, cg[i], crow[i], ccol[i], kk);
+    }
+  }
+  const int n_kc = 1 << d.n_ko;
+  const int nA = R * K, nB = K * N;
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    float2 acc[kSimtMaxC];
+#pragma unroll
+    for (int i = 0; i < kSimtMaxC; ++i) acc[i] = make_float2(0.f, 0.f);
+    for (int kc = 0; kc < n_kc; ++kc) {
+      int64_t kA, kB;
+      k_offsets(d, kc, kA, kB);
+      for (int e = tid; e < nA; e += kSimtBlock) {
+        int64_t g = 0;
+        int r = 0, c = 0, k = 0;
+        decode(d.tA, e, 0, d.tA.nbits, g, r, c, k);
+        As[r * ldA + k] = load_c<SA>(d.A, oA + kA + g);
+      }
+      for (int e = tid; e < nB; e += kSimtBlock) {
+        int64_t g = 0;
+        int r = 0, c = 0, k = 0;
+        decode(d.tB, e, 0, d.tB.nbits, g, r, c, k);
+        Bs[k * ldB + c] = load_c<SB>(d.B, oB + kB + g);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kSimtMaxC; ++i) {
+        if (i < cnt && (int)(tid + i * kSimtBlock) < nC) {
+          const float2* ar = As + crow[i] * ldA;
+          const float2* bc = Bs + ccol[i];
+          float2 s = acc[i];
+          for (int k = 0; k < K; ++k) {
+            const float2 a = ar[k], b = bc[k * ldB];
+            s.x = fmaf(a.x, b.x, s.x);
+            s.x = fmaf(-a.y, b.y, s.x);
+            s.y = fmaf(a.x, b.y, s.y);
+            s.y = fmaf(a.y, b.x, s.y);
+          }
+          acc[i] = s;
+        }
+      }
+      __syncthreads();
+    }
+    const Scale sc = compute_scale(d, js, jb);
+    float lmax = 0.f;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < kSimtMaxC; ++i) {
+      if (i < cnt && (int)(tid + i * kSimtBlock) < nC) {
+        float2 v = acc[i];
+        if (sc.shift) {
+          v.x = ldexpf(v.x, -sc.shift);
+          v.y = ldexpf(v.y, -sc.shift);
+        }
+        store_c<SC>(d.C, oC + cg[i], v);
+        if (d.track) {
+          float2 w = v;
+          if (SC != ST_C64) w = load_c<SC>(d.C, oC + cg[i]);
+          const float m = fmaxf(fabsf(w.x), fabsf(w.y));
+          if (!(m <= 3.4e38f)) bad = 1;
+          else lmax = fmaxf(lmax, m);
+        }
+      }
+    }
+    finish_scale<kSimtBlock>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA contraction (FP32 matrix cores, v_mfma_f32_32x32x2_f32): 128 rows x
+// 64 complex columns per workgroup, 16 complex k per LDS chunk, double
+// buffered; 4 waves in a 2x2 grid, each 64 rows x 64 real columns.
+// ---------------------------------------------------------------------------
+constexpr int kTM = 128, kTN = 64, kTK = 16;
+constexpr int kAPlane = kTM + 1;          // floats per (k, re/im) plane
+constexpr int kAStride = 2 * kAPlane;     // floats per k
+constexpr int kABuf = kTK * kAStride;     // floats per buffer
+constexpr int kBStride = kTN + 1;         // float2 per k
+constexpr int kBBuf = kTK * kBStride;     // float2 per buffer
+constexpr int kCStride = 2 * kTN + 4;     // floats per C row
+constexpr int kMfmaLdsFloats =
+    (2 * kABuf + 4 * kBBuf) > (kTM * kCStride) ? (2 * kABuf + 4 * kBBuf) : (kTM * kCStride);
+
+template <int SA, int SB, int SC>
+__global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
+  __shared__ float lds[kMfmaLdsFloats + 16];
+  float* Abuf = lds;                                       // [2][kTK][2][kAPlane]
+  float2* Bbuf = reinterpret_cast<float2*>(lds + 2 * kABuf);  // [2][kTK][kBStride]
+  float* red = lds + kMfmaLdsFloats;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  // XCD-aware block order: consecutive logical tiles share the row tile of A
+  // and land on the same XCD (blocks are dealt round-robin to the 8 XCDs).
+  uint64_t bid = blockIdx.x;
+  const uint64_t nblk = gridDim.x;
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const uint64_t no = bid % (uint64_t)d.n_col_tiles;
+  const uint64_t ro = bid / (uint64_t)d.n_col_tiles;
+
+  // Per-thread element offsets of the A (2048) and B (1024) chunk tiles.
+  int64_t gA[8];
+  int lA[8];
+  int64_t gB[4];
+  int lB[4];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    int64_t g = 0;
+    int r = 0, c = 0, k = 0;
+    decode(d.tA, tid + 256 * j, 0, d.tA.nbits, g, r, c, k);
+    gA[j] = g;
+    lA[j] = k * kAStride + r;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int64_t g = 0;
+    int r = 0, c = 0, k = 0;
+    decode(d.tB, tid + 256 * j, 0, d.tB.nbits, g, r, c, k);
+    gB[j] = g;
+    lB[j] = k * kBStride + c;
+  }
+  // Lane roles inside the real-expanded operands.
+  const int lrow = lane & 31;          // row inside a 32-row block
+  const int cpart = lane >> 5;         // A_r column parity: 0 re, 1 im
+  const int dpart = lane & 1;          // C_r column parity
+  const int ncol = (lane & 31) >> 1;   // complex column inside a 16-col block
+  const bool bswap = cpart != dpart;
+  const float bsign = (cpart == 1 && dpart == 0) ? -1.f : 1.f;
+
+  const int n_kc = 1 << d.n_ko;
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    float2 ra[8], rb[4];
+    {
+      int64_t kA, kB;
+      k_offsets(d, 0, kA, kB);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ra[j] = load_c<SA>(d.A, oA + kA + gA[j]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rb[j] = load_c<SB>(d.B, oB + kB + gB[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      Abuf[lA[j]] = ra[j].x;
+      Abuf[lA[j] + kAPlane] = ra[j].y;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bbuf[lB[j]] = rb[j];
+    __syncthreads();
+
+    for (int kc = 0; kc < n_kc; ++kc) {
+      const int cur = kc & 1;
+      const bool more = kc + 1 < n_kc;
+      if (more) {
+        int64_t kA, kB;
+        k_offsets(d, kc + 1, kA, kB);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ra[j] = load_c<SA>(d.A, oA + kA + gA[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rb[j] = load_c<SB>(d.B, oB + kB + gB[j]);
+      }
+      const float* As = Abuf + cur * kABuf + cpart * kAPlane + wm * 64 + lrow;
+      const float2* Bs = Bbuf + cur * kBBuf + wn * 32 + ncol;
+#pragma unroll 4
+      for (int k = 0; k < kTK; ++k) {
+        const float a0 = As[k * kAStride];
+        const float a1 = As[k * kAStride + 32];
+        const float2 b0 = Bs[k * kBStride];
+        const float2 b1 = Bs[k * kBStride + 16];
+        const float v0 = bsign * (bswap ? b0.y : b0.x);
+        const float v1 = bsign * (bswap ? b1.y : b1.x);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v1, acc[1][1], 0, 0, 0);
+      }
+      if (more) {
+        float* An = Abuf + (cur ^ 1) * kABuf;
+        float2* Bn = Bbuf + (cur ^ 1) * kBBuf;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          An[lA[j]] = ra[j].x;
+          An[lA[j] + kAPlane] = ra[j].y;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Bn[lB[j]] = rb[j];
+      }
+      __syncthreads();
+    }
+
+    // Stage the 128 x 128 real tile through LDS, then store in C order.
+    float* Cs = lds;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int col = wn * 64 + j * 32 + (lane & 31);
+          Cs[row * kCStride + col] = acc[i][j][r];
+        }
+    __syncthreads();
+    const Scale sc = compute_scale(d, js, jb);
+    float lmax = 0.f;
+    int bad = 0;
+    for (int j = 0; j < (kTM * kTN) / 256; ++j) {
+      int64_t g = 0;
+      int r = 0, c = 0, k = 0;
+      decode(d.tC, tid + 256 * j, 0, d.tC.nbits, g, r, c, k);
+      float2 v = make_float2(Cs[r * kCStride + 2 * c], Cs[r * kCStride + 2 * c + 1]);
+      if (sc.shift) {
+        v.x = ldexpf(v.x, -sc.shift);
+        v.y = ldexpf(v.y, -sc.shift);
+      }
+      store_c<SC>(d.C, oC + g, v);
+      if (d.track) {
+        float2 w = v;
+        if (SC != ST_C64) w = load_c<SC>(d.C, oC + g);
+        const float m = fmaxf(fabsf(w.x), fabsf(w.y));
+        if (!(m <= 3.4e38f)) bad = 1;
+        else lmax = fmaxf(lmax, m);
+      }
+    }
+    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch dispatch over storage types
+// ---------------------------------------------------------------------------
+#define RQC_SIMT_CASE(a, b, c)                                                         \
+  if (sa == a && sb == b && sc == c) {                                                 \
+    hipLaunchKernelGGL((k_simt<a, b, c>), grid, dim3(kSimtBlock), lds, s, d);         \
+    return hipGetLastError();                                                          \
+  }
+#define RQC_MFMA_CASE(a, b, c)                                                         \
+  if (sa == a && sb == b && sc == c) {                                                 \
+    hipLaunchKernelGGL((k_mfma32<a, b, c>), grid, dim3(256), 0, s, d);                \
+    return hipGetLastError();                                                          \
+  }
+
+hipError_t launch_step(const StepDesc& d, int kernel, int sa, int sb, int sc, int lp_kind,
+                       hipStream_t s) {
+  (void)lp_kind;
+  const uint64_t tiles = (uint64_t)d.n_row_tiles * (uint64_t)d.n_col_tiles;
+  const unsigned gy = (unsigned)(d.copies < 65535 ? d.copies : 65535);
+  dim3 grid((unsigned)tiles, gy);
+  if (kernel == 1) {
+    RQC_MFMA_CASE(ST_C64, ST_C64, ST_C64)
+    RQC_MFMA_CASE(ST_C64, ST_C64, ST_F16)
+    RQC_MFMA_CASE(ST_C64, ST_C64, ST_BF16)
+    RQC_MFMA_CASE(ST_F16, ST_C64, ST_F16)
+    RQC_MFMA_CASE(ST_F16, ST_C64, ST_C64)
+    RQC_MFMA_CASE(ST_BF16, ST_C64, ST_BF16)
+    RQC_MFMA_CASE(ST_BF16, ST_C64, ST_C64)
+    RQC_MFMA_CASE(ST_C64, ST_F16, ST_F16)
+    RQC_MFMA_CASE(ST_C64, ST_F16, ST_C64)
+    RQC_MFMA_CASE(ST_C64, ST_BF16, ST_BF16)
+    RQC_MFMA_CASE(ST_C64, ST_BF16, ST_C64)
+    RQC_MFMA_CASE(ST_F16, ST_F16, ST_F16)
+    RQC_MFMA_CASE(ST_F16, ST_F16, ST_C64)
+    RQC_MFMA_CASE(ST_BF16, ST_BF16, ST_BF16)
+    RQC_MFMA_CASE(ST_BF16, ST_BF16, ST_C64)
+    return hipErrorInvalidValue;
+  }
+  const size_t lds = sizeof(float2) * ((size_t)(1 << d.rt) * ((1 << d.kt) + 1) +
+                                       (size_t)(1 << d.kt) * ((1 << d.nt) + 1)) +
+                     64;
+  RQC_SIMT_CASE(ST_C64, ST_C64, ST_C64)
+  RQC_SIMT_CASE(ST_C64, ST_C64, ST_F16)
+  RQC_SIMT_CASE(ST_C64, ST_C64, ST_BF16)
+  RQC_SIMT_CASE(ST_F16, ST_C64, ST_F16)
+  RQC_SIMT_CASE(ST_F16, ST_C64, ST_C64)
+  RQC_SIMT_CASE(ST_BF16, ST_C64, ST_BF16)
+  RQC_SIMT_CASE(ST_BF16, ST_C64, ST_C64)
+  RQC_SIMT_CASE(ST_C64, ST_F16, ST_F16)
+  RQC_SIMT_CASE(ST_C64, ST_F16, ST_C64)
+  RQC_SIMT_CASE(ST_C64, ST_BF16, ST_BF16)
+  RQC_SIMT_CASE(ST_C64, ST_BF16, ST_C64)
+  RQC_SIMT_CASE(ST_F16, ST_F16, ST_F16)
+  RQC_SIMT_CASE(ST_F16, ST_F16, ST_C64)
+  RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_BF16)
+  RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_C64)
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Leaf instantiation: fix sliced wires to the bits of the slice id and closed
+// selectors to the requested bits (Section 5.1), producing one copy per
+// (slice, bitstring) of the group that the leaf depends on.
+// ---------------------------------------------------------------------------
+__global__ void k_leaves(const LeafJob* jobs, const float2* store, float2* dst,
+                         const uint64_t* slice_ids, const uint8_t* closed, int n_closed, int gs,
+                         int gb) {
+  const LeafJob& J = jobs[blockIdx.x];
+  const int ne = 1 << J.rank;
+  const int cs = J.dep_s ? gs : 1;
+  const int cb = J.dep_b ? gb : 1;
+  const int total = ne * cs * cb;
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int e = t % ne;
+    const int cp = t / ne;
+    const int js = cp % cs, jb = cp / cs;
+    int64_t src = J.src;
+    for (int i = 0; i < J.rank; ++i)
+      if ((e >> i) & 1) src += int64_t(1) << J.pos[i];
+    for (int s = 0; s < J.nsel; ++s) {
+      int v;
+      if (J.sel_src[s] >= 0) v = (int)((slice_ids[js] >> J.sel_src[s]) & 1ull);
+      else v = closed[(int64_t)jb * n_closed + (-J.sel_src[s] - 1)] & 1;
+      if (v) src += int64_t(1) << J.sel_pos[s];
+    }
+    dst[J.dst + (int64_t)js * J.out_s + (int64_t)jb * J.out_b + e] = store[src];
+  }
+}
+
+hipError_t launch_leaves(const LeafJob* jobs_dev, int n_jobs, const void* leaf_store,
+                         void* dst_base, const uint64_t* slice_ids, const uint8_t* closed_bits,
+                         int n_closed, int gs, int gb, int max_rank, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  (void)max_rank;
+  hipLaunchKernelGGL(k_leaves, dim3(n_jobs), dim3(256), 0, s, jobs_dev,
+                     reinterpret_cast<const float2*>(leaf_store), reinterpret_cast<float2*>(dst_base),
+                     slice_ids, closed_bits, n_closed, gs, gb);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cross-slice sum in FP64, fixed order (slice 0, 1, ... of the group; groups
+// in call order), skipping slices flagged for an FP32 re-run.
+// ---------------------------------------------------------------------------
+template <int S>
+__global__ void k_slice_sum(const void* root, const int32_t* rexp, int64_t rs, int64_t rb,
+                            int32_t res, int32_t reb, int n_elems, int gs, int gb, int dep_s,
+                            int dep_b, const int32_t* flags, double* out, double* per_slice,
+                            int64_t ps_row0, int64_t n_batch_total, int64_t b0, int first) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n_elems * gb) return;
+  const int e = (int)(t % n_elems);
+  const int jb = (int)(t / n_elems);
+  const int jbs = dep_b ? jb : 0;
+  double sr = 0.0, si = 0.0;
+  for (int js = 0; js < gs; ++js) {
+    const int jss = dep_s ? js : 0;
+    double vr = 0.0, vi = 0.0;
+    if (!(flags && flags[js])) {
+      const float2 v = load_c<S>(root, jss * rs + jbs * rb + e);
+      const int ex = rexp ? rexp[jss * res + jbs * reb] : 0;
+      vr = ldexp((double)v.x, ex);
+      vi = ldexp((double)v.y, ex);
+    }
+    sr += vr;
+    si += vi;
+    if (per_slice && !(flags && flags[js])) {
+      const int64_t o = (((ps_row0 + js) * n_batch_total + (b0 + jb)) * n_elems + e) * 2;
+      per_slice[o] = vr;
+      per_slice[o + 1] = vi;
+    }
+  }
+  const int64_t o = ((b0 + jb) * (int64_t)n_elems + e) * 2;
+  if (first) {
+    out[o] = sr;
+    out[o + 1] = si;
+  } else {
+    out[o] += sr;
+    out[o + 1] += si;
+  }
+}
+
+hipError_t launch_slice_sum(const void* root, int root_store, const int32_t* root_exp,
+                            int64_t root_s, int64_t root_b, int32_t re_s, int32_t re_b, int dep_s,
+                            int dep_b, int n_elems, int gs, int gb, const int32_t* flags,
+                            double* out, double* per_slice, int64_t ps_row0,
+                            int64_t n_batch_total, int64_t b0, int first, hipStream_t s) {
+  const int64_t n = (int64_t)n_elems * gb;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (root_store == ST_C64)
+    hipLaunchKernelGGL(k_slice_sum<ST_C64>, grid, dim3(256), 0, s, root, root_exp, root_s, root_b,
+                       re_s, re_b, n_elems, gs, gb, dep_s, dep_b, flags, out, per_slice, ps_row0,
+                       n_batch_total, b0, first);
+  else if (root_store == ST_F16)
+    hipLaunchKernelGGL(k_slice_sum<ST_F16>, grid, dim3(256), 0, s, root, root_exp, root_s, root_b,
+                       re_s, re_b, n_elems, gs, gb, dep_s, dep_b, flags, out, per_slice, ps_row0,
+                       n_batch_total, b0, first);
+  else
+    hipLaunchKernelGGL(k_slice_sum<ST_BF16>, grid, dim3(256), 0, s, root, root_exp, root_s, root_b,
+                       re_s, re_b, n_elems, gs, gb, dep_s, dep_b, flags, out, per_slice, ps_row0,
+                       n_batch_total, b0, first);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Small utility kernels (fills instead of memsets so that graphs replay them)
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_f64(double* p, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_add_f64(double* d, const double* s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] += s[i];
+}
+
+static dim3 fill_grid(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return dim3((unsigned)b);
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, fill_grid(n), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, fill_grid(n), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_add_f64(double* dst, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_f64, fill_grid(n), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stand-alone bit permutation (the separate-permutation baseline): tiles of
+// 2^5 x 2^5 elements staged through LDS so that both the reads (low input
+// bits) and the writes (low output bits) are contiguous.
+// ---------------------------------------------------------------------------
+struct PermDesc {
+  int32_t rank;
+  int8_t src_of_out[48];  // input bit feeding output bit i
+};
+
+__global__ __launch_bounds__(256) void k_permute(const float2* in, float2* out, PermDesc p,
+                                                 int lo_in, int lo_out, uint32_t lo_in_mask,
+                                                 uint32_t lo_out_mask) {
+  // Tile = the lowest `lo_in` input bits  U  the lowest `lo_out` output bits.
+  __shared__ float2 tile[1024 + 32];
+  (void)lo_in_mask;
+  (void)lo_out_mask;
+  const int r = p.rank;
+  int out_of_in[48];
+  for (int i = 0; i < r; ++i) out_of_in[p.src_of_out[i]] = i;
+  // Tile bits, as output bit indices: the low output bits plus the output
+  // bits fed by the low input bits.
+  uint64_t tmask = 0;
+  for (int i = 0; i < lo_out && i < r; ++i) tmask |= 1ull << i;
+  for (int i = 0; i < lo_in && i < r; ++i) tmask |= 1ull << out_of_in[i];
+  int tb[20], nt = 0;
+  for (int i = 0; i < r; ++i)
+    if ((tmask >> i) & 1) tb[nt++] = i;
+  int ob[48], no = 0;
+  for (int i = 0; i < r; ++i)
+    if (!((tmask >> i) & 1)) ob[no++] = i;
+  // Block base in output index space.
+  uint64_t base_out = 0;
+  for (int i = 0; i < no; ++i)
+    if ((blockIdx.x >> i) & 1) base_out |= 1ull << ob[i];
+  const int nte = 1 << nt;
+  // Read phase: element t of the tile in input order (input bits ascending).
+  int tin[20], nti = 0;
+  {
+    // tile bits sorted by their input bit
+    int tmp_in[20];
+    for (int i = 0; i < nt; ++i) tmp_in[i] = p.src_of_out[tb[i]];
+    // selection sort by input bit
+    for (int i = 0; i < nt; ++i) {
+      int best = i;
+      for (int j = i + 1; j < nt; ++j)
+        if (tmp_in[j] < tmp_in[best]) best = j;
+      int x = tmp_in[i]; tmp_in[i] = tmp_in[best]; tmp_in[best] = x;
+    }
+    for (int i = 0; i < nt; ++i) tin[nti++] = tmp_in[i];
+  }
+  uint64_t base_in = 0;
+  for (int i = 0; i < r; ++i)
+    if ((base_out >> i) & 1) base_in |= 1ull << p.src_of_out[i];
+  for (int t = threadIdx.x; t < nte; t += blockDim.x) {
+    uint64_t a = base_in;
+    int slot = 0;
+    for (int i = 0; i < nti; ++i)
+      if ((t >> i) & 1) {
+        a |= 1ull << tin[i];
+        // slot index: position of the output bit inside tb[]
+        const int ob_i = out_of_in[tin[i]];
+        for (int j = 0; j < nt; ++j)
+          if (tb[j] == ob_i) slot |= 1 << j;
+      }
+    tile[slot + (slot >> 5)] = in[a];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nte; t += blockDim.x) {
+    uint64_t a = base_out;
+    for (int j = 0; j < nt; ++j)
+      if ((t >> j) & 1) a |= 1ull << tb[j];
+    out[a] = tile[t + (t >> 5)];
+  }
+}
+
+hipError_t launch_permute(const void* in, void* out, int rank, const int8_t* src_pos_of_out_bit,
+                          hipStream_t s) {
+  PermDesc p;
+  p.rank = rank;
+  for (int i = 0; i < rank; ++i) p.src_of_out[i] = src_pos_of_out_bit[i];
+  // Up to 10 tile bits: 5 lowest input bits and 5 lowest output bits.
+  int lo_in = rank < 5 ? rank : 5, lo_out = rank < 5 ? rank : 5;
+  // Count tile bits (overlap shrinks the tile).
+  uint64_t tmask = 0;
+  int out_of_in[48];
+  for (int i = 0; i < rank; ++i) out_of_in[(int)p.src_of_out[i]] = i;
+  for (int i = 0; i < lo_out; ++i) tmask |= 1ull << i;
+  for (int i = 0; i < lo_in; ++i) tmask |= 1ull << out_of_in[i];
+  const int nt = __builtin_popcountll(tmask);
+  const uint64_t blocks = 1ull << (rank - nt);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<const float2*>(in), reinterpret_cast<float2*>(out), p, lo_in,
+                     lo_out, 0u, 0u);
+  return hipGetLastError();
+}
+
+}  // namespace rqc

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances (FP32 path): amplitudes normalised by the RMS amplitude
+2^(-n/2) must agree to 1e-4; single contraction steps to 2e-5 relative to
+the RMS of the reference (FP32 unit roundoff 6e-8 times a K-term sum with
+K <= 2^16 and random signs gives ~1.5e-5 in the worst accumulation order).
+Reduced precision: normalised error <= 2e-2 and linear fidelity >= 0.99.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import rqcgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2110_14502_amd")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev_c64(x):
+    return torch.from_numpy(np.ascontiguousarray(x.astype(np.complex64))).cuda()
+
+
+def _rel_rms(got, ref):
+    ref = np.asarray(ref)
+    return float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2)))
+
+
+# ---------------------------------------------------------------- single steps
+STEP_CASES = [
+    # (rank_a, rank_b, shared, seed, kernel)
+    (12, 10, 5, 1, 0),
+    (9, 4, 2, 2, 0),     # imbalanced: big A, small B
+    (14, 12, 5, 3, 1),   # MFMA: m=9, n=7, k=5
+    (16, 13, 7, 4, 1),
+    (15, 15, 4, 5, -1),
+    (6, 6, 6, 6, 0),     # full contraction to a scalar
+    (5, 3, 0, 7, 0),     # outer product
+]
+
+
+@pytest.mark.parametrize("ra,rb,s,seed,kernel", STEP_CASES)
+def test_pair_contract_vs_einsum(ra, rb, s, seed, kernel):
+    _say("pair", ra, rb, s, seed, kernel)
+    st = rqcgen.synthetic_step(ra, rb, s, seed)
+    a = rqcgen.random_complex(1 << ra, seed + 100)
+    b = rqcgen.random_complex(1 << rb, seed + 200)
+    ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
+    c = R.pair_contract(_dev_c64(a), _dev_c64(b), st.labels_a, st.labels_b, st.labels_c,
+                        kernel=kernel)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy().astype(np.complex128)
+    assert _rel_rms(got, ref) < 2e-5
+
+
+def test_pair_contract_batched_and_shared_operand():
+    _say("pair batched")
+    st = rqcgen.synthetic_step(13, 11, 5, 9)
+    nb = 3
+    a = rqcgen.random_complex((nb, 1 << 13), 11)
+    b = rqcgen.random_complex(1 << 11, 12)  # shared by every batch entry
+    c = R.pair_contract(_dev_c64(a), _dev_c64(b), st.labels_a, st.labels_b, st.labels_c,
+                        batch=nb, stride_a=1 << 13, stride_b=0, kernel=1)
+    torch.cuda.synchronize()
+    got = c.cpu().numpy().reshape(nb, -1)
+    for i in range(nb):
+        ref = oracle.einsum_step(a[i], b, st.labels_a, st.labels_b, st.labels_c)
+        assert _rel_rms(got[i], ref) < 2e-5
+
+
+def test_permute_and_cgemm():
+    _say("permute cgemm")
+    rng = np.random.default_rng(3)
+    r = 14
+    lin = list(range(r))
+    lout = [lin[i] for i in rng.permutation(r)]
+    x = rqcgen.random_complex(1 << r, 4)
+    y = R.permute(_dev_c64(x), lin, lout)
+    torch.cuda.synchronize()
+    ref = oracle.einsum_step(x, np.ones(1), lin, [], lout)
+    assert np.array_equal(y.cpu().numpy(), ref.astype(np.complex64))
+    M, N, K = 256, 128, 64
+    A = rqcgen.random_complex(M * K, 5)
+    B = rqcgen.random_complex(K * N, 6)
+    Cg = R.cgemm(_dev_c64(A), _dev_c64(B), M, N, K)
+    torch.cuda.synchronize()
+    ref = A.reshape(M, K) @ B.reshape(K, N)
+    assert _rel_rms(Cg.cpu().numpy().reshape(M, N), ref) < 2e-5
+
+
+# ---------------------------------------------------------------- amplitudes
+def _setup(rows, cols, depth, cseed, n_open, **kw):
+    c = rqcgen.grid_rqc(rows, cols, depth, cseed)
+    n = rows * cols
+    openq = list(range(n - n_open, n))
+    P = R.Plan(R.Network(R.Circuit.from_rqcgen(c), openq), **kw).bind()
+    return c, openq, P
+
+
+def test_config1_single_amplitude_vs_statevector():
+    """4x4 grid, depth 1+8+1, greedy path, no slicing, one bitstring."""
+    _say("config1")
+    c, openq, P = _setup(4, 4, 8, 1, 0, seed=1)
+    bits = rqcgen.random_bits(16, 1)
+    got = R.to_complex(P.contract(bits))[0]
+    ref = oracle.amplitudes_sv(c, [], bits)
+    assert oracle.normalized_error(got, ref, 16) < 1e-4
+    # and with four open qubits (a batch of 16 amplitudes)
+    c, openq, P = _setup(4, 4, 8, 1, 4, seed=1)
+    got = R.to_complex(P.contract(bits[:12]))[0]
+    ref = oracle.amplitudes_sv(c, openq, bits[:12])
+    assert oracle.normalized_error(got, ref, 16) < 1e-4
+    assert oracle.linear_fidelity(got, ref) > 0.999999
+
+
+def test_all_qubits_open_is_normalised():
+    _say("all open")
+    c, openq, P = _setup(3, 4, 6, 2, 12, seed=3)
+    got = R.to_complex(P.contract(np.zeros(0, np.uint8)))[0]
+    assert abs(np.sum(np.abs(got) ** 2) - 1.0) < 1e-5
+    ref = oracle.amplitudes_sv(c, openq, [])
+    assert oracle.normalized_error(got, ref, 12) < 1e-4
+
+
+def _sliced_case(prec, n_sliced=5, depth=8, cseed=3):
+    c, openq, P = _setup(5, 5, depth, cseed, 4, n_sliced=n_sliced, seed=5, path_trials=64)
+    bits = rqcgen.random_bits(21, 9)
+    wires = P.sliced_wires()
+    amps, per = P.contract(bits, prec=prec, per_slice=True)
+    ref_slices = oracle.slice_values_tn(c, openq, bits, wires, range(1 << n_sliced))
+    return c, P, bits, R.to_complex(amps)[0], R.to_complex(per)[:, 0], ref_slices
+
+
+def test_sliced_per_slice_and_sum_fp32():
+    _say("sliced fp32")
+    c, P, bits, amps, per, ref = _sliced_case(R.F32)
+    assert per.shape == ref.shape
+    err = oracle.per_slice_error(per, ref)
+    assert err < 1e-4
+    full = oracle.amplitudes_sv(c, list(range(21, 25)), bits)
+    assert np.max(np.abs(ref.sum(0) - full)) < 1e-13  # oracle self-consistency
+    assert oracle.normalized_error(amps, full, 25) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_sliced_reduced_precision(prec):
+    _say("sliced", prec)
+    c, P, bits, amps, per, ref = _sliced_case(R.PRECISIONS[prec])
+    full = ref.sum(0)
+    assert oracle.normalized_error(amps, full, 25) < 2e-2
+    assert oracle.linear_fidelity(amps, full) > 0.99
+    assert P.last_report["fp32_reruns"] == 0
+
+
+def test_overflow_filter_reruns_in_fp32():
+    """Section 5.5 filter: a forced overflow flags every slice, which is then
+    recomputed in FP32 (the host forces it through a storage-exponent bias;
+    the kernels themselves run normally)."""
+    _say("rerun")
+    c, openq, P = _setup(5, 5, 8, 3, 4, n_sliced=3, seed=5, path_trials=32, lp_min_log2=4)
+    bits = rqcgen.random_bits(21, 9)
+    P.set_scale_bias(40)
+    amps = R.to_complex(P.contract(bits, prec=R.F16))[0]
+    assert P.last_report["fp32_reruns"] == 8
+    full = oracle.amplitudes_sv(c, openq, bits)
+    assert oracle.normalized_error(amps, full, 25) < 1e-4
+    P.set_scale_bias(0)
+
+
+def test_graph_replay_is_bitwise_identical():
+    _say("graph replay")
+    c, openq, P = _setup(5, 5, 8, 3, 4, n_sliced=4, seed=5, path_trials=32)
+    bits = rqcgen.random_bits(21, 9)
+    a1 = P.contract(bits).clone()
+    r1 = P.last_report
+    a2 = P.contract(bits).clone()
+    r2 = P.last_report
+    assert r1["graph_reused"] == 0 and r2["graph_reused"] == 1
+    assert torch.equal(a1, a2)
+    # different closed bits through the same graph
+    bits2 = rqcgen.random_bits(21, 10)
+    a3 = R.to_complex(P.contract(bits2))[0]
+    assert P.last_report["graph_reused"] == 1
+    ref = oracle.amplitudes_sv(c, openq, bits2)
+    assert oracle.normalized_error(a3, ref, 25) < 1e-4
+
+
+def test_bitstring_batch_and_slice_subsets_and_small_workspace():
+    _say("batch subsets")
+    c, openq, P = _setup(5, 5, 8, 3, 4, n_sliced=4, seed=5, path_trials=32)
+    bits = np.stack([rqcgen.random_bits(21, s) for s in (1, 2, 3)])
+    batch = R.to_complex(P.contract(bits))
+    for i in range(3):
+        ref = oracle.amplitudes_sv(c, openq, bits[i])
+        assert oracle.normalized_error(batch[i], ref, 25) < 1e-4
+    # a subset of slices, with a workspace that forces ragged groups
+    ids = [0, 3, 5, 6, 9, 12, 15]
+    lo, pref = P.workspace_bytes(len(ids), 1, R.F32)
+    ws = torch.empty(lo + (pref - lo) // 3, dtype=torch.uint8, device="cuda")
+    sub, per = P.contract(bits[0], slice_ids=ids, workspace=ws, per_slice=True)
+    assert P.last_report["slices_per_group"] < len(ids)
+    wires = P.sliced_wires()
+    ref = oracle.slice_values_tn(c, openq, bits[0], wires, ids)
+    assert oracle.per_slice_error(R.to_complex(per)[:, 0], ref) < 1e-4
+    assert oracle.normalized_error(R.to_complex(sub)[0], ref.sum(0), 25) < 1e-4

@@ -1,0 +1,132 @@
+"""Host-side logic of the native library (no GPU needed): symbol exports,
+argument validation, plan structure, cost accounting, slicing options."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import rqcgen
+
+R = pytest.importorskip("paper_2110_14502_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _plan(rows, cols, depth, cseed, n_open, **kw):
+    c = rqcgen.grid_rqc(rows, cols, depth, cseed)
+    n = rows * cols
+    C = R.Circuit.from_rqcgen(c)
+    N = R.Network(C, list(range(n - n_open, n)))
+    return c, R.Plan(N, **kw)
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "rqc.h")).read()
+    declared = set(re.findall(r"^\s*(?:rqc_status|void|const char\*)\s+(rqc_\w+)\s*\(", header, re.M))
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(R._lib, name), name
+    assert declared == set(R.EXPORTED)
+    assert "gfx950" in R.version()
+
+
+def test_invalid_arguments_are_rejected():
+    with pytest.raises(R.RqcError) as e:
+        R.Circuit(2, [rqcgen.Gate(rqcgen.FSIM, 0, 0, 1.0, 0.5)])
+    assert e.value.code == R.EINVAL
+    with pytest.raises(R.RqcError):
+        R.Circuit(2, [rqcgen.Gate(rqcgen.H, 5)])
+    C = R.Circuit.from_rqcgen(rqcgen.grid_rqc(2, 2, 2, 1))
+    with pytest.raises(R.RqcError):
+        R.Network(C, [0, 0])
+    with pytest.raises(R.RqcError):
+        R.Network(C, [7])
+    N = R.Network(C, [])
+    with pytest.raises(R.RqcError):
+        R.Plan(N, forced_wires=[(0, 99)])
+
+
+def _check_tree(plan, n_open):
+    e = plan.export()
+    labels = e["labels"]
+    n_leaves = len(e["leaves"])
+    produced = set()
+    consumed = []
+    for st in e["steps"]:
+        la, lb, lc = set(st["la"]), set(st["lb"]), set(st["lc"])
+        # C = A xor B (summed labels are the shared ones)
+        assert lc == la ^ lb
+        assert len(la & lb) == st["k"]
+        assert len(la) == st["m"] + st["k"] and len(lb) == st["n"] + st["k"]
+        consumed += [st["a"], st["b"]]
+        produced.add(st["node"])
+    # every leaf and every intermediate except the root is consumed once
+    assert sorted(consumed) == sorted(list(range(n_leaves)) + sorted(produced - {e["root"]}))
+    root = e["steps"][-1]
+    assert root["node"] == e["root"]
+    # root layout: open qubits, the first open qubit least significant
+    want = []
+    for q in reversed(e["open"]):
+        want += [i for i, L in enumerate(labels) if L[0] == 1 and L[1] == q]
+    assert root["lc"] == want
+    # each operand's summed labels are its lowest address bits
+    for st in e["steps"]:
+        for lx, ly in ((st["la"], st["lb"]), (st["lb"], st["la"])):
+            k = len(set(lx) & set(ly))
+            if k:
+                assert set(lx[len(lx) - k:]) == set(lx) & set(ly)
+    return e
+
+
+def test_plan_structure_4x4():
+    _, P = _plan(4, 4, 8, 1, 4, seed=1)
+    e = _check_tree(P, 4)
+    info = P.info()
+    assert info["n_leaves"] == 48 and info["n_steps"] == 47 and info["n_sliced"] == 0
+    # cost accounting vs a recount from the exported steps
+    fl = sum(8.0 * 2 ** (s["m"] + s["n"] + s["k"]) for s in e["steps"] if s["dep_s"] or s["dep_b"])
+    assert fl == info["flops_per_slice"]
+    assert info["max_log2_elems"] == max(len(s["lc"]) for s in e["steps"])
+
+
+def test_plan_is_deterministic_under_seed():
+    _, P1 = _plan(4, 4, 8, 2, 2, seed=7, path_trials=32)
+    _, P2 = _plan(4, 4, 8, 2, 2, seed=7, path_trials=32)
+    assert P1.export() == P2.export()
+
+
+def test_slicing_options():
+    _, P = _plan(5, 5, 8, 3, 3, n_sliced=5, path_trials=32, seed=1)
+    assert P.info()["n_sliced"] == 5 and P.info()["n_slices"] == 32
+    _check_tree(P, 3)
+    # every sliced wire is a canonical (qubit, segment) wire
+    for q, s in P.sliced_wires():
+        assert 0 <= q < 25 and s >= 1
+    # forced wires come first in slice order
+    w = P.sliced_wires()[:2]
+    _, Pf = _plan(5, 5, 8, 3, 3, n_sliced=4, forced_wires=w, path_trials=16, seed=2)
+    assert Pf.sliced_wires()[:2] == w
+    # a width bound is met by slicing
+    _, Pb = _plan(5, 5, 10, 3, 0, max_log2_elems=12, path_trials=32, seed=3)
+    assert Pb.info()["max_log2_elems"] <= 12
+
+
+def test_slicing_bounds_per_slice_width_6x6():
+    _, P = _plan(6, 6, 14, 2, 6, n_sliced=8, path_trials=64, seed=2)
+    info = P.info()
+    assert info["n_slices"] == 256
+    _, P0 = _plan(6, 6, 14, 2, 6, n_sliced=0, path_trials=64, seed=2)
+    assert info["max_log2_elems"] < P0.info()["max_log2_elems"]
+
+
+def test_workspace_sizes_scale_with_group():
+    _, P = _plan(5, 5, 8, 3, 3, n_sliced=4, path_trials=16, seed=1)
+    lo, pref = P.workspace_bytes(0, 1, R.F32)
+    assert 0 < lo <= pref
+    # reduced precision stores large intermediates in 4 bytes per element
+    _, P6 = _plan(6, 6, 14, 2, 6, n_sliced=8, path_trials=16, seed=2)
+    assert P6.workspace_bytes(0, 1, R.F16)[0] < P6.workspace_bytes(0, 1, R.F32)[0]
+    lo2, _ = P.workspace_bytes(0, 4, R.F32)
+    assert lo2 >= lo
