@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the sliced tensor-network amplitude path on one MI355X.
+
+Workload (default): 6x6-qubit grid random circuit of depth (1+14+1), the
+contraction sliced on 8 wires (256 slices), a batch of 64 amplitudes (the
+six qubits of the bottom row open, the other 30 bits seeded), complex64
+arithmetic on FP32 matrix cores, FP64 slice sum.  One step = every slice of
+the batch contracted and summed (one graph launch).
+
+Prints one JSON line.  `value` is amplitudes per second with the circuit's
+leaves and plan resident in HBM before the timed region starts.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "amplitudes/s + contraction TFLOP/s vs plain FP32 path at stated error; p99 latency"
+PEAK_MFMA_FP32 = 157.3   # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0        # GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--rows", type=int, default=6)
+    ap.add_argument("--cols", type=int, default=6)
+    ap.add_argument("--depth", type=int, default=14)
+    ap.add_argument("--open", type=int, default=6)
+    ap.add_argument("--sliced", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--trials", type=int, default=2048)
+    ap.add_argument("--plan-seed", type=int, default=2)
+    ap.add_argument("--ws-fraction", type=float, default=0.85)
+    ap.add_argument("--slices", type=int, default=0,
+                    help="contract only the first N slice ids (profiling); 0 = all")
+    ap.add_argument("--graph-steps", type=int, default=1)
+    ap.add_argument("--lp-steps", type=int, default=1,
+                    help="timed steps of the reduced-precision (f16) comparison, 0 = skip")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget of the oracle CPU baseline sample, 0 = skip")
+    return ap.parse_args()
+
+
+def cpu_baseline(circ, openq, bits, n_fixed, budget_s, plan_seed, base_wires):
+    """The oracle timed on a bounded sample of the same amplitude sum: with
+    n_fixed wires fixed, the batch is the sum of 2^n_fixed sub-slices; time
+    as many sub-slices as fit the budget and extrapolate to the full sum."""
+    import numpy as np
+    import oracle
+    import paper_2110_14502_amd as R
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    P = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), openq), n_sliced=n_fixed,
+               path_trials=64, seed=plan_seed, forced_wires=base_wires)
+    wires = P.sliced_wires()
+    rng = np.random.default_rng(0)
+    ids = rng.choice(1 << n_fixed, size=64, replace=False)
+    t0 = time.perf_counter()
+    done = 0
+    for sid in ids:
+        oracle.slice_values_tn(circ, openq, bits, wires, [int(sid)])
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    per_sub = dt / done
+    full = per_sub * (1 << n_fixed)
+    n_amp = 1 << len(openq)
+    return {"value": n_amp / full, "unit": "amplitudes/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} of the 2^{n_fixed} sub-slices (wires fixed: the 8-wire slicing refined "
+                      f"to {n_fixed}) of the same 64-amplitude sum, complex128 numpy, "
+                      f"{dt:.1f} s, extrapolated to the full sum ({full:.3g} s)"}
+
+
+def log(*msg):
+    print("[bench]", *msg, file=sys.stderr, flush=True)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported "
+              "(the slices would shard across GPUs with one final reduction, not built here)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import rqcgen
+    import paper_2110_14502_amd as R
+
+    torch.cuda.set_device(0)
+    n = a.rows * a.cols
+    circ = rqcgen.grid_rqc(a.rows, a.cols, a.depth, a.seed)
+    openq = list(range(n - a.open, n))
+    bits = rqcgen.random_bits(n - a.open, a.seed)
+    t = time.perf_counter()
+    plan = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), openq), n_sliced=a.sliced,
+                  path_trials=a.trials, seed=a.plan_seed)
+    t_plan = time.perf_counter() - t
+    info = plan.info()
+    log(f"plan: {t_plan:.1f}s, log2 flops/slice {math.log2(info['flops_per_slice']):.2f}, "
+        f"width {info['max_log2_elems']}, {info['n_slices']} slices")
+    ids = None
+    frac = 1.0
+    if a.slices > 0:
+        ids = list(range(min(a.slices, info["n_slices"])))
+        frac = len(ids) / info["n_slices"]
+    plan.bind("cuda:0")
+    prec = R.PRECISIONS[a.prec]
+    free, _ = torch.cuda.mem_get_info()
+    lo, pref = plan.workspace_bytes(len(ids) if ids else 0, 1, prec)
+    ws_bytes = int(min(pref, max(lo, a.ws_fraction * free)))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda:0")
+    out = torch.empty(2 << a.open, dtype=torch.float64, device="cuda:0")
+    # Timed region: direct launches with HIP events around every MFMA launch.
+    plan.set_timing(1)
+
+    def step(p, tag):
+        ts = time.perf_counter()
+        plan.contract(bits, slice_ids=ids, prec=p, workspace=ws, out=out, sync=False)
+        r = plan.report()
+        log(f"{tag}: {time.perf_counter() - ts:.2f}s (groups of {r['slices_per_group']} slices)")
+        return r
+
+    for _ in range(a.warmup):
+        step(prec, "warmup")
+    torch.cuda.synchronize()
+    lat = []
+    tim = {"launches": 0, "total_ms": 0.0, "flops": 0.0, "bytes": 0.0}
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        rep = step(prec, "timed")
+        lat.append(time.perf_counter() - ts)
+        for k, v in plan.timing().items():
+            tim[k] += v
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1000.0 * elapsed / a.steps / frac
+    n_amp = 1 << a.open
+    amps_s = n_amp / (ms / 1000.0)
+    step_flops = info["flops_per_slice"] * info["n_slices"]
+    lat = [x / frac for x in lat]
+    achieved = tim["flops"] / (tim["total_ms"] / 1000.0) / 1e12 if tim["total_ms"] > 0 else 0.0
+    res = {
+        "metric": METRIC,
+        "value": amps_s,
+        "unit": "amplitudes/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.prec,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{a.rows}x{a.cols} grid RQC depth 1+{a.depth}+1, fSim(pi/2,pi/6) ABCDCDAB, "
+                        f"{a.sliced} sliced wires ({info['n_slices']} slices), {n_amp} amplitudes "
+                        f"({a.open} open qubits), circuit seed {a.seed}",
+            "n_slices": info["n_slices"],
+            "slices_run": len(ids) if ids else info["n_slices"],
+            "slices_per_group": rep["slices_per_group"],
+            "plan_log2_flops": math.log2(step_flops),
+            "plan_max_log2_elems": info["max_log2_elems"],
+            "plan_steps": info["n_steps"],
+            "plan_seconds": round(t_plan, 2),
+        },
+        "tflops": step_flops / (ms / 1000.0) / 1e12,
+        "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),
+                       "p99": 1000 * float(np.percentile(lat, 99))},
+        "roofline": {
+            "bound": "mfma",
+            "kernel": "k_mfma32 (fused permute + complex GEMM, FP32 MFMA 32x32x2)",
+            "achieved": achieved,
+            "peak": PEAK_MFMA_FP32,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_MFMA_FP32,
+            "traffic": None,
+            "launches": tim["launches"],
+            "avg_launch_ms": tim["total_ms"] / max(1, tim["launches"]),
+            "flops_per_launch": tim["flops"] / max(1, tim["launches"]),
+            "share_of_step_flops": tim["flops"] / (step_flops * frac * a.steps),
+        },
+    }
+    # The same call replayed as one captured graph launch (probe off).
+    if a.graph_steps > 0:
+        plan.set_timing(-1)
+        step(prec, "graph capture")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.graph_steps):
+            step(prec, "graph")
+        torch.cuda.synchronize()
+        res["graph_ms_per_step"] = 1000.0 * (time.perf_counter() - t0) / a.graph_steps / frac
+    if a.lp_steps > 0 and a.prec == "f32":
+        step(R.F16, "f16 warmup")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.lp_steps):
+            rep16 = step(R.F16, "f16")
+        torch.cuda.synchronize()
+        ms16 = 1000.0 * (time.perf_counter() - t0) / a.lp_steps / frac
+        res["reduced_precision"] = {"dtype": "f16 storage, fp32 accumulate", "ms_per_step": ms16,
+                                    "value": n_amp / (ms16 / 1000.0), "speedup_vs_f32": ms / ms16,
+                                    "fp32_reruns": rep16["fp32_reruns"]}
+    if a.cpu_seconds > 0:
+        log("cpu baseline")
+        res["cpu_baseline"] = cpu_baseline(circ, openq, bits, a.sliced + 16, a.cpu_seconds,
+                                           a.plan_seed, plan.sliced_wires())
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -146,7 +146,8 @@ typedef struct rqc_plan_info {
 rqc_status rqc_plan_get_info(const rqc_plan* p, rqc_plan_info* out);
 
 /* Per-step shape: m, n, k are the numbers of row, column and summed index
- * bits of C[m,n] = A[m,k] B[k,n]; kernel 0 = SIMT streaming, 1 = MFMA. */
+ * bits of C[m,n] = A[m,k] B[k,n]; kernel 0 = generic SIMT, 1 = MFMA,
+ * 2 = row streaming. */
 typedef struct rqc_step_info {
   int32_t m, n, k;
   int32_t kernel;
@@ -224,7 +225,10 @@ rqc_status rqc_contract_report(rqc_plan* p, rqc_stream stream,
  * label in A and B but not in C is summed; labels_c must be exactly the
  * other labels.  A, B, C are device complex64 arrays (float2); batch_count
  * independent problems lie at strides (elements) stride_a, stride_b,
- * stride_c (0 = shared).  Ranks up to 40.  kernel: -1 auto, 0 SIMT, 1 MFMA. */
+ * stride_c (0 = shared).  Ranks up to 40.  kernel: -1 auto, 0 generic SIMT,
+ * 1 MFMA (needs m >= 7, n >= 6, k >= 4), 2 row streaming (needs the summed
+ * labels to be the lowest bits of A and of B in the same order, k <= 5,
+ * n <= 6); an unmet condition falls back to the generic kernel. */
 rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a,
                              const int32_t* labels_b, int32_t rank_b,
                              const int32_t* labels_c, int32_t rank_c,
@@ -301,6 +305,26 @@ typedef struct rqc_server_stats {
 } rqc_server_stats;
 rqc_status rqc_server_get_stats(rqc_server* s, rqc_server_stats* out);
 void rqc_server_destroy(rqc_server* s);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+/* Timing probe.  With kernel 0 (SIMT), 1 (MFMA) or 2 (rows), later rqc_contract calls
+ * of this plan launch their kernels directly on the caller's stream instead
+ * of replaying a graph, and every launch of that kernel is bracketed by a
+ * pair of HIP events recorded on that stream; -1 turns the probe off and
+ * restores graph launches. */
+rqc_status rqc_plan_set_timing(rqc_plan* p, int32_t kernel);
+
+typedef struct rqc_timing {
+  uint64_t launches;    /* probed launches in the last reported call */
+  double total_ms;      /* their summed event-measured duration */
+  double flops;         /* their summed algorithmic flops (8 per complex MAC) */
+  double bytes;         /* their summed algorithmic bytes: each operand read
+                           once and the output written once, per copy */
+} rqc_timing;
+
+/* Valid after rqc_contract_report of the call. */
+rqc_status rqc_plan_get_timing(const rqc_plan* p, rqc_timing* out);
 
 /* ---- misc --------------------------------------------------------------- */
 

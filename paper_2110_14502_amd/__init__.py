@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "librqc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_2110_14502_amd.build`")
+        f"{LIB_PATH} is missing: build it with `python paper_2110_14502_amd/build.py`")
 
 _lib = C.CDLL(LIB_PATH)
 
@@ -69,6 +69,11 @@ class rqc_run_report(C.Structure):
     _fields_ = [("n_slices", C.c_uint64), ("fp32_reruns", C.c_uint64),
                 ("slices_per_group", C.c_int32), ("bits_per_group", C.c_int32),
                 ("graph_reused", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double)]
+
+
+class rqc_timing(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
 
 
 class rqc_server_opts(C.Structure):
@@ -133,6 +138,8 @@ _PROTOS = {
     "rqc_last_error": (C.c_char_p, []),
     "rqc_version": (C.c_char_p, []),
     "rqc_plan_set_scale_bias": (_S, [_P, C.c_int32]),
+    "rqc_plan_set_timing": (_S, [_P, C.c_int32]),
+    "rqc_plan_get_timing": (_S, [_P, C.POINTER(rqc_timing)]),
 }
 for _name, (_res, _args) in _PROTOS.items():
     _f = getattr(_lib, _name)
@@ -333,6 +340,15 @@ class Plan:
         if per_slice:
             return amps, ps.view(-1, n_batch, 1 << len(self.open), 2)
         return amps
+
+    def set_timing(self, kernel: int):
+        """Bracket launches of kernel kind (0 SIMT, 1 MFMA, -1 off) with events."""
+        _check(_lib.rqc_plan_set_timing(self.h, int(kernel)))
+
+    def timing(self) -> dict:
+        t = rqc_timing()
+        _check(_lib.rqc_plan_get_timing(self.h, C.byref(t)))
+        return {f: getattr(t, f) for f, _ in rqc_timing._fields_}
 
     def report(self, stream=None) -> dict:
         r = rqc_run_report()

@@ -1,6 +1,8 @@
 """Build librqc.so (HIP for gfx950) in-tree.
 
-    python -m paper_2110_14502_amd.build        # or build() from Python
+    python paper_2110_14502_amd/build.py
+
+(run as a file: importing the package itself needs the built library).
 
 Every source is compiled with hipcc for gfx950 only; packed FP32 vector
 instructions are disabled for device code.

@@ -178,7 +178,7 @@ rqc_status rqc_plan_get_step(const rqc_plan* p, int32_t i, rqc_step_info* out) {
   out->m = st.m;
   out->n = st.n;
   out->k = st.k;
-  out->kernel = (st.kernel == 1 && st.m >= 7 && st.n >= 6 && st.k >= 4) ? 1 : 0;
+  out->kernel = i < (int)p->kern.size() ? p->kern[i] : -1;
   out->depends_on_slice = st.dep_s;
   out->depends_on_bits = st.dep_b;
   out->lp_output = st.lp;
@@ -268,6 +268,25 @@ rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias) {
   RQC_CATCH
 }
 
+rqc_status rqc_plan_set_timing(rqc_plan* p, int32_t kernel) {
+  RQC_TRY
+  if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
+  if (kernel < -1 || kernel > 2) throw rqc::Error{RQC_EINVAL, "kernel must be -1, 0, 1 or 2"};
+  p->timing_kernel = kernel;
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_get_timing(const rqc_plan* p, rqc_timing* out) {
+  RQC_TRY
+  if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  *out = p->last_timing;
+  return RQC_OK;
+  RQC_CATCH
+}
+
 // ---- single pairwise contraction, permutation, GEMM ---------------------
 
 rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int32_t* labels_b,
@@ -281,7 +300,7 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
   if ((rank_a && !labels_a) || (rank_b && !labels_b) || (rank_c && !labels_c))
     throw rqc::Error{RQC_EINVAL, "NULL labels"};
   if (batch_count < 1 || batch_count > 65535) throw rqc::Error{RQC_EINVAL, "batch_count out of range"};
-  if (kernel < -1 || kernel > 1) throw rqc::Error{RQC_EINVAL, "kernel must be -1, 0 or 1"};
+  if (kernel < -1 || kernel > 2) throw rqc::Error{RQC_EINVAL, "kernel must be -1, 0, 1 or 2"};
   std::vector<int> la(labels_a, labels_a + rank_a), lb(labels_b, labels_b + rank_b),
       lc(labels_c, labels_c + rank_c);
   for (auto* l : {&la, &lb}) {
@@ -289,10 +308,7 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
     std::sort(s.begin(), s.end());
     if (std::adjacent_find(s.begin(), s.end()) != s.end()) throw rqc::Error{RQC_EINVAL, "repeated label"};
   }
-  int m = 0, n = 0, k = 0;
-  for (int x : la) (std::find(lb.begin(), lb.end(), x) != lb.end() ? k : m)++;
-  n = rank_b - k;
-  const int kern = kernel >= 0 ? kernel : rqc::choose_kernel(m, n, k);
+  int kern = kernel;
   rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, kern);
   d.A = A;
   d.B = B;
@@ -302,8 +318,7 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
   d.sC_s = stride_c;
   d.gs_c = batch_count;
   d.copies = batch_count;
-  const int use = (kern == 1 && d.rt == 7 && d.nt == 6 && d.kt == 4) ? 1 : 0;
-  rqc::hip_check(rqc::launch_step(d, use, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, 0,
+  rqc::hip_check(rqc::launch_step(d, kern, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, 0,
                                   static_cast<hipStream_t>(stream)),
                  "pair contract");
   return RQC_OK;
@@ -356,11 +371,11 @@ rqc_status rqc_cgemm(int64_t M, int64_t N, int64_t K, const void* A, const void*
   for (int i = 0; i < n; ++i) lb.push_back(200 + i);
   for (int i = 0; i < m; ++i) lc.push_back(i);
   for (int i = 0; i < n; ++i) lc.push_back(200 + i);
-  rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, 1);
+  int use = -1;
+  rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, use);
   d.A = A;
   d.B = B;
   d.C = C;
-  const int use = (d.rt == 7 && d.nt == 6 && d.kt == 4) ? 1 : 0;
   rqc::hip_check(rqc::launch_step(d, use, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, 0,
                                   static_cast<hipStream_t>(stream)),
                  "cgemm");

@@ -33,7 +33,7 @@ static int pos_in(const std::vector<int>& l, int x) {
 // Tile selection for one step (the permutation folded into the tiles)
 // ---------------------------------------------------------------------------
 StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
-                        const std::vector<int>& lc, int kernel) {
+                        const std::vector<int>& lc, int& kernel) {
   StepDesc d;
   std::memset(&d, 0, sizeof d);
   std::vector<int> M, N, K;
@@ -57,27 +57,56 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   }
   const int m = (int)M.size(), n = (int)N.size(), k = (int)K.size();
   if (m + k > 40 || n + k > 40 || m + n > 40) throw Error{RQC_EUNSUPPORTED, "rank above 40"};
+  auto pa = [&](int x) { return pos_in(la, x); };
+  auto pb = [&](int x) { return pos_in(lb, x); };
+  auto pc = [&](int x) { return pos_in(lc, x); };
+  // Row-streaming kernel: K is the lowest k address bits of both A and B, in
+  // the same order; B small.
+  bool rows_ok = k <= 5 && n <= 6;
+  for (int p = 0; p < k && rows_ok; ++p) {
+    const int xa = la[la.size() - 1 - p];
+    rows_ok = pos_in(lb, xa) == p;
+  }
+  const bool mfma_ok = m >= 7 && n >= 6 && k >= 4;
+  if (kernel < 0) kernel = mfma_ok ? KERN_MFMA : (rows_ok ? KERN_ROWS : KERN_SIMT);
+  if (kernel == KERN_MFMA && !mfma_ok) kernel = KERN_SIMT;
+  if (kernel == KERN_ROWS && !rows_ok) kernel = KERN_SIMT;
   int rt, nt, kt;
-  if (kernel == 1 && !(m >= 7 && n >= 6 && k >= 4)) kernel = 0;
-  if (kernel == 1) {
+  if (kernel == KERN_MFMA) {
     rt = 7;
     nt = 6;
     kt = 4;
+  } else if (kernel == KERN_ROWS) {
+    kt = k;
+    nt = n;
+    rt = std::min(m, 11 - n);
+    // LDS capacity of the row kernel: B (N*K) and the padded C tile.
+    const int64_t ldc = n == 0 ? 1 : (int64_t(1) << n) + 1;
+    if ((int64_t(1) << (n + k)) > 2048 || (int64_t(1) << rt) * ldc > 3072 || (rt + n) > 11)
+      throw Error{RQC_EINVAL, "internal: row kernel tile exceeds LDS capacity"};
   } else {
     kt = std::min(k, 4);
     nt = std::min(n, 4);
     rt = std::min(m, std::min(11 - nt, 12 - kt));
+    // Generic kernel: <= 8 owned C elements per thread, tables of <= 12 bits.
+    if (rt + nt > 11 || rt + kt > 12 || kt + nt > 12)
+      throw Error{RQC_EINVAL, "internal: generic tile too large"};
   }
-  auto pa = [&](int x) { return pos_in(la, x); };
-  auto pb = [&](int x) { return pos_in(lb, x); };
-  auto pc = [&](int x) { return pos_in(lc, x); };
   auto by = [](std::vector<int> v, auto key) {
     std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return key(x) < key(y); });
     return v;
   };
-  std::vector<int> Ms = by(M, [&](int x) { return std::min(pa(x), pc(x)); });
-  std::vector<int> Ns = by(N, [&](int x) { return std::min(pb(x), pc(x)); });
-  std::vector<int> Ks = by(K, [&](int x) { return std::min(pa(x), pb(x)); });
+  std::vector<int> Ms, Ns, Ks;
+  if (kernel == KERN_ROWS) {
+    // Rows: the lowest M bits of A (just above K), columns in B's order.
+    Ms = by(M, pa);
+    Ns = by(N, pb);
+    Ks = by(K, pa);
+  } else {
+    Ms = by(M, [&](int x) { return std::min(pa(x), pc(x)); });
+    Ns = by(N, [&](int x) { return std::min(pb(x), pc(x)); });
+    Ks = by(K, [&](int x) { return std::min(pa(x), pb(x)); });
+  }
   std::vector<int> Rt(Ms.begin(), Ms.begin() + rt), Ro(Ms.begin() + rt, Ms.end());
   std::vector<int> Nt(Ns.begin(), Ns.begin() + nt), No(Ns.begin() + nt, Ns.end());
   std::vector<int> Kt(Ks.begin(), Ks.begin() + kt), Ko(Ks.begin() + kt, Ks.end());
@@ -107,8 +136,10 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   for (int x : Rt) ba.push_back({x, 0}), bc.push_back({x, 0});
   for (int x : Kt) ba.push_back({x, 2}), bb.push_back({x, 2});
   for (int x : Nt) bb.push_back({x, 1}), bc.push_back({x, 1});
-  tile(d.tA, ba, pa);
-  tile(d.tB, bb, pb);
+  if (kernel != KERN_ROWS) {
+    tile(d.tA, ba, pa);
+    tile(d.tB, bb, pb);
+  }
   tile(d.tC, bc, pc);
   d.rt = rt;
   d.nt = nt;
@@ -126,11 +157,6 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   d.copies = 1;
   d.flag_n = 1;
   return d;
-}
-
-// MFMA tiles are exactly 128 x 64 x 16; anything else runs on the SIMT kernel.
-static int desc_kernel(const StepDesc& d, int requested) {
-  return (requested == 1 && d.rt == 7 && d.nt == 6 && d.kt == 4) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -178,11 +204,14 @@ size_t resident_bytes(rqc_plan* p) {
   p->inv_max_off = off;
   off = align256(off + 4 * (int64_t)nn);
   p->inv_bytes = off;
+  p->tmpl.clear();
+  p->kern.clear();
+  for (const Step& st : pd.steps) {
+    int k = -1;
+    p->tmpl.push_back(make_pair_desc(st.la, st.lb, st.lc, k));
+    p->kern.push_back(k);
+  }
   return (size_t)off;
-}
-
-static StepDesc step_desc_template(const Step& st) {
-  return make_pair_desc(st.la, st.lb, st.lc, st.kernel);
 }
 
 void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
@@ -222,7 +251,9 @@ void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
   // Slice-invariant subtrees: contracted once, kept resident.
   for (const Step& st : pd.steps) {
     if (!st.invariant) continue;
-    StepDesc d = step_desc_template(st);
+    const size_t si = &st - &pd.steps[0];
+    const int kern = p->kern[si];
+    StepDesc d = p->tmpl[si];
     d.A = base + p->inv_off[st.a];
     d.B = base + p->inv_off[st.b];
     d.C = base + p->inv_off[st.node];
@@ -234,7 +265,7 @@ void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
     d.lp_out = 0;
     d.copies = 1;
     d.gs_c = 1;
-    hip_check(launch_step(d, desc_kernel(d, st.kernel), ST_C64, ST_C64, ST_C64, 0, s), "invariant step");
+    hip_check(launch_step(d, kern, ST_C64, ST_C64, ST_C64, 0, s), "invariant step");
   }
   hip_check(hipStreamSynchronize(s), "bind");
   p->res = base;
@@ -310,14 +341,32 @@ static GroupLayout compute_layout(rqc_plan* p, int prec, int gs, int gb) {
   };
   for (int v = 0; v < nl; ++v)
     if (!L.place[v].resident) L.place[v].off = alloc(bytes[v]);
-  const int root = pd.tree.root;
-  for (const Step& st : pd.steps) {
+  L.ksplit.assign(pd.steps.size(), 0);
+  L.p_off.assign(pd.steps.size(), -1);
+  for (size_t i = 0; i < pd.steps.size(); ++i) {
+    const Step& st = pd.steps[i];
     if (st.invariant) continue;
     L.place[st.node].off = alloc(bytes[st.node]);
+    // Split-K for generic steps whose output tiles cannot fill the GPU.
+    const StepDesc& t = p->tmpl[i];
+    if (p->kern[i] == KERN_SIMT && t.n_ko >= 2) {
+      const Placement& C = L.place[st.node];
+      const int64_t copies = (int64_t)(C.dep_s ? gs : 1) * (C.dep_b ? gb : 1);
+      const int64_t work = (int64_t)t.n_row_tiles * t.n_col_tiles * copies;
+      int ks = 0;
+      while (ks < t.n_ko && (work << ks) < 1024) ++ks;
+      const int64_t cbytes = (int64_t(8) << pd.node_labels[st.node].size()) *
+                             (C.dep_s ? gs : 1) * (C.dep_b ? gb : 1);
+      while (ks > 0 && (cbytes << ks) > (int64_t(1) << 30)) --ks;
+      if (ks > 0) {
+        L.ksplit[i] = ks;
+        L.p_off[i] = alloc(align256(cbytes << ks));
+        release(L.p_off[i]);
+      }
+    }
     for (int x : {st.a, st.b})
       if (!L.place[x].resident) release(L.place[x].off);
   }
-  (void)root;
   L.arena_bytes = align256(peak);
   // Leaf jobs.
   std::vector<char> sliced(pd.net.labels.size(), 0);
@@ -411,8 +460,9 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
     return reinterpret_cast<float*>(P.resident ? p->res + P.m_off : scale + P.m_off);
   };
   hip_check(launch_fill_i32(flags, 0, (int64_t)n_ids, s), "clear flags");
-  std::vector<StepDesc> tmpl;
-  for (const Step& st : pd.steps) tmpl.push_back(step_desc_template(st));
+  size_t probe = 0;
+  p->tflops.clear();
+  p->tbytes.clear();
   for (uint64_t b0 = 0; b0 < n_batch; b0 += L.gb) {
     const int gbc = (int)std::min<uint64_t>(L.gb, n_batch - b0);
     for (uint64_t g0 = 0; g0 < n_ids; g0 += L.gs) {
@@ -427,7 +477,7 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
       for (size_t i = 0; i < pd.steps.size(); ++i) {
         const Step& st = pd.steps[i];
         if (st.invariant) continue;
-        StepDesc d = tmpl[i];
+        StepDesc d = p->tmpl[i];
         const Placement &A = L.place[st.a], &B = L.place[st.b], &C = L.place[st.node];
         d.A = ptr(A);
         d.B = ptr(B);
@@ -449,7 +499,36 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
           d.dep_s_c = C.dep_s;
           d.flag_n = gsc;
         }
-        hip_check(launch_step(d, desc_kernel(d, st.kernel), A.store, B.store, C.store, 0, s), "step");
+        const int kern = p->kern[i];
+        if (L.ksplit[i]) {
+          d.ksplit = L.ksplit[i];
+          d.P = reinterpret_cast<float2*>(arena + L.p_off[i]);
+          d.p_stride = (int64_t(1) << pd.node_labels[st.node].size()) * (C.dep_s ? L.gs : 1) *
+                       (C.dep_b ? L.gb : 1);
+        }
+        const bool timed = kern == p->timing_kernel;
+        if (timed) {
+          if (p->tev.size() < 2 * (probe + 1)) {
+            hipEvent_t a, b;
+            hip_check(hipEventCreate(&a), "event");
+            hip_check(hipEventCreate(&b), "event");
+            p->tev.push_back(a);
+            p->tev.push_back(b);
+          }
+          hip_check(hipEventRecord(p->tev[2 * probe], s), "event record");
+        }
+        hip_check(launch_step(d, kern, A.store, B.store, C.store, 0, s), "step");
+        if (timed) {
+          hip_check(hipEventRecord(p->tev[2 * probe + 1], s), "event record");
+          ++probe;
+          const double cp = (double)d.copies;
+          const int ca = (A.dep_s ? (C.dep_s ? gsc : 1) : 1) * (A.dep_b ? (C.dep_b ? gbc : 1) : 1);
+          const int cb = (B.dep_s ? (C.dep_s ? gsc : 1) : 1) * (B.dep_b ? (C.dep_b ? gbc : 1) : 1);
+          p->tflops.push_back(8.0 * std::ldexp(1.0, st.m + st.n + st.k) * cp);
+          p->tbytes.push_back(elsize(A.store) * std::ldexp(1.0, st.m + st.k) * ca +
+                              elsize(B.store) * std::ldexp(1.0, st.n + st.k) * cb +
+                              elsize(C.store) * std::ldexp(1.0, st.m + st.n) * cp);
+        }
       }
       const int root = pd.tree.root;
       const Placement& R = L.place[root];
@@ -534,7 +613,11 @@ void contract(rqc_plan* p, const uint64_t* ids_in, uint64_t n_ids, const uint8_t
   GraphKey key{prec, gs, gb, n_ids, n_batch, ws_v, out, per_slice};
   auto it = p->graphs.find(key);
   int reused = 0;
-  if (it != p->graphs.end()) {
+  if (p->timing_kernel >= 0) {
+    // Timing probe: direct launches so that each probed launch is bracketed
+    // by events recorded on `s` itself.
+    record_call(p, L, W, n_ids, n_batch, ws, out, per_slice, 0, s);
+  } else if (it != p->graphs.end()) {
     hip_check(hipGraphLaunch(it->second, s), "graph launch");
     reused = 1;
   } else {
@@ -581,6 +664,15 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
   std::memset(rep, 0, sizeof *rep);
   hip_check(hipStreamSynchronize(s), "synchronize");
   if (!r.active) return;
+  p->last_timing = rqc_timing{};
+  for (size_t i = 0; i < p->tflops.size() && p->timing_kernel >= 0; ++i) {
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, p->tev[2 * i], p->tev[2 * i + 1]), "event time");
+    p->last_timing.launches++;
+    p->last_timing.total_ms += ms;
+    p->last_timing.flops += p->tflops[i];
+    p->last_timing.bytes += p->tbytes[i];
+  }
   rep->n_slices = r.n_ids;
   rep->slices_per_group = r.gs;
   rep->bits_per_group = r.gb;
@@ -628,5 +720,6 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
 
 rqc_plan::~rqc_plan() {
   for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto e : tev) (void)hipEventDestroy(e);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }

@@ -33,6 +33,8 @@ struct GroupLayout {
   int64_t scale_bytes = 0;       // exponent / max arrays
   std::vector<LeafJob> jobs;     // variable leaves
   int max_leaf_rank = 0;
+  std::vector<int> ksplit;       // per step: split-K bits (generic kernel)
+  std::vector<int64_t> p_off;    // per step: partial buffer in the arena
 };
 
 struct GraphKey {
@@ -81,6 +83,14 @@ struct rqc_plan {
   int64_t inv_max_off = 0;              // bytes: float per node
   int64_t inv_bytes = 0;
   int scale_bias = 0;
+  // Per-step descriptor templates (layout only) and chosen kernels.
+  std::vector<rqc::StepDesc> tmpl;
+  std::vector<int> kern;
+  // Timing probe: events around launches of one kernel kind.
+  int timing_kernel = -1;
+  std::vector<hipEvent_t> tev;          // pairs (start, stop)
+  std::vector<double> tflops, tbytes;   // per probed launch
+  rqc_timing last_timing{};
   // Caches.
   std::map<std::tuple<int, int, int>, rqc::GroupLayout> layouts;
   std::map<rqc::GraphKey, hipGraphExec_t> graphs;
@@ -104,9 +114,10 @@ void contract(rqc_plan* p, const uint64_t* ids, uint64_t n_ids, const uint8_t* b
 void report(rqc_plan* p, PendingRun& run, hipStream_t s, rqc_run_report* r);
 
 // Build the descriptor of one pairwise contraction given operand labels
-// (MSB first), the kernel and copy strides.
+// (MSB first).  `kernel` is the requested kind (-1: choose) and returns the
+// kind actually used (MFMA and row-streaming need their shape conditions).
 StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
-                        const std::vector<int>& lc, int kernel);
+                        const std::vector<int>& lc, int& kernel);
 
 void hip_check(hipError_t e, const char* what);
 

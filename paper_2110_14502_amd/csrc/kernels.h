@@ -53,6 +53,13 @@ struct StepDesc {
   int32_t dep_s_c;           // C varies with the slice (flag index js)
   int32_t flag_n;            // slices of the group flagged when it does not
   int32_t n_row_tiles, n_col_tiles;
+  // Split-K: 2^ksplit blocks share one output tile, each summing a slice of
+  // the K range into its own partial buffer P + split * p_stride (complex64,
+  // laid out like C); a reduction kernel then forms C in fixed order.
+  int32_t ksplit;
+  float2* P;
+  int64_t p_stride;
+  int32_t sb_store, sc_store;  // storage codes of B and C (runtime copies)
   int8_t ro_A[kMaxOuter], ro_C[kMaxOuter];
   int8_t no_B[kMaxOuter], no_C[kMaxOuter];
   int8_t ko_A[kMaxOuter], ko_B[kMaxOuter];
@@ -72,6 +79,9 @@ struct LeafJob {
   int32_t dst_store;  // Store code of the destination
   int32_t out_s, out_b;  // copy strides of the destination (elements)
 };
+
+// Kernel kinds of a step.
+enum Kernel : int { KERN_SIMT = 0, KERN_MFMA = 1, KERN_ROWS = 2 };
 
 // Launchers (kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_step(const StepDesc& d, int kernel, int sa, int sb, int sc, int lp_kind,

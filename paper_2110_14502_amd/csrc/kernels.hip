@@ -168,9 +168,139 @@ __device__ __forceinline__ void k_offsets(const StepDesc& d, uint32_t kc, int64_
 }
 
 // ---------------------------------------------------------------------------
-// SIMT contraction: memory-bound and small steps (row tile x all-or-part of
-// N, K in chunks).  Loads follow each operand's address order so that a
-// wavefront reads contiguous runs; results are stored in C address order.
+// Offset tables of a tile: element e (bits in increasing address order) sits
+// at global offset g_lo[e & 63] + g_hi[e >> 6] and at LDS coordinate
+// c_lo[e & 63] + c_hi[e >> 6], where the coordinate of a tile bit is its
+// weight inside the LDS array (row bits scaled by the row stride).  Built
+// once per workgroup into LDS, so the per-element cost is two lookups.
+// ---------------------------------------------------------------------------
+struct TileTab {
+  int64_t g[128];  // [0, 64) low six bits, [64, 128) the high bits
+  int32_t c[128];
+};
+
+__device__ __forceinline__ void build_tab(const TileMap& t, int row_stride, int col_stride,
+                                          int k_stride, TileTab& tab) {
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+    const int hi = i >= 64;
+    const int v = hi ? i - 64 : i;
+    const int b0 = hi ? 6 : 0;
+    const int b1 = hi ? t.nbits : (t.nbits < 6 ? t.nbits : 6);
+    int64_t g = 0;
+    int32_t c = 0;
+    for (int b = b0; b < b1; ++b) {
+      if ((v >> (b - b0)) & 1) {
+        g += int64_t(1) << t.gpos[b];
+        const int w = 1 << t.cbit[b];
+        c += t.role[b] == 0 ? w * row_stride : (t.role[b] == 1 ? w * col_stride : w * k_stride);
+      }
+    }
+    tab.g[i] = g;
+    tab.c[i] = c;
+  }
+}
+
+// Epilogue shared by the SIMT kernels: scale, convert, store, track.
+template <int SC>
+__device__ __forceinline__ void store_out(const StepDesc& d, int64_t at, float2 v, const Scale& sc,
+                                          float& lmax, int& bad) {
+  if (sc.shift) {
+    v.x = ldexpf(v.x, -sc.shift);
+    v.y = ldexpf(v.y, -sc.shift);
+  }
+  store_c<SC>(d.C, at, v);
+  if (d.track) {
+    float2 w = v;
+    if (SC != ST_C64) w = load_c<SC>(d.C, at);
+    const float m = fmaxf(fabsf(w.x), fabsf(w.y));
+    if (!(m <= 3.4e38f)) bad = 1;
+    else lmax = fmaxf(lmax, m);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row-streaming contraction for plan steps (the memory-bound "stem" steps of
+// Section 5.4's imbalanced case): A is a row-major [M][K] matrix whose K
+// summed bits are its lowest address bits, B is [N][K] with the same K order
+// and small enough for LDS.  Each thread streams whole rows of A (K
+// contiguous values, vector loads), multiplies them by B read as LDS
+// broadcasts, and parks the row's N outputs in LDS; the tile is then written
+// out in C's own address order through the offset tables.
+// ---------------------------------------------------------------------------
+constexpr int kRowsMaxB = 2048;  // N*K
+constexpr int kRowsMaxC = 2048;  // R*N
+// C tile with a padded row stride ldc = N + 1 (N >= 2) or 1 (N == 1):
+// R * ldc <= R*N + R <= 2048 + 1024.
+constexpr int kRowsCs = kRowsMaxC + kRowsMaxC / 2;
+
+template <int KB, int SA>
+__global__ __launch_bounds__(256) void k_rows(StepDesc d) {
+  constexpr int K = 1 << KB;
+  __shared__ float2 Bs[kRowsMaxB];
+  __shared__ float2 Cs[kRowsCs];
+  __shared__ TileTab tc;
+  __shared__ float red[16];
+  const int tid = threadIdx.x;
+  const int N = 1 << d.nt, R = 1 << d.rt;
+  const int ldc = N == 1 ? 1 : N + 1;
+  build_tab(d.tC, ldc, 1, 0, tc);
+  const uint64_t ro = blockIdx.x;
+  const int nC = R * N;
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ro, 0, js, jb, oA, oB, oC);
+    __syncthreads();
+    // B is [N][K] and contiguous (it is the whole operand).
+    for (int i = tid; i < N * K; i += 256) {
+      float2 v;
+      if (d.sb_store == ST_F16) v = load_c<ST_F16>(d.B, oB + i);
+      else if (d.sb_store == ST_BF16) v = load_c<ST_BF16>(d.B, oB + i);
+      else v = load_c<ST_C64>(d.B, oB + i);
+      Bs[i] = v;
+    }
+    __syncthreads();
+    for (int r = tid; r < R; r += 256) {
+      float2 a[K];
+      const int64_t base = oA + (int64_t)r * K;
+#pragma unroll
+      for (int k = 0; k < K; ++k) a[k] = load_c<SA>(d.A, base + k);
+      for (int n = 0; n < N; ++n) {
+        const float2* b = Bs + n * K;
+        float sx = 0.f, sy = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float2 bv = b[k];
+          sx = fmaf(a[k].x, bv.x, sx);
+          sx = fmaf(-a[k].y, bv.y, sx);
+          sy = fmaf(a[k].x, bv.y, sy);
+          sy = fmaf(a[k].y, bv.x, sy);
+        }
+        Cs[r * ldc + n] = make_float2(sx, sy);
+      }
+    }
+    __syncthreads();
+    const Scale sc = compute_scale(d, js, jb);
+    float lmax = 0.f;
+    int bad = 0;
+    const int64_t glo = tc.g[tid & 63];
+    const int32_t clo = tc.c[tid & 63];
+    for (int e = tid; e < nC; e += 256) {
+      const int hi = 64 + (e >> 6);
+      const float2 v = Cs[clo + tc.c[hi]];
+      const int64_t at = oC + glo + tc.g[hi];
+      if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, v, sc, lmax, bad);
+      else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, v, sc, lmax, bad);
+      else store_out<ST_C64>(d, at, v, sc, lmax, bad);
+    }
+    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0, sc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic SIMT contraction (any layouts, any sizes): tiles of R rows x N
+// columns, K in chunks; loads follow each operand's address order through
+// the offset tables; optional split-K into partial buffers.
 // ---------------------------------------------------------------------------
 constexpr int kSimtBlock = 256;
 constexpr int kSimtMaxC = 8;  // C tile <= 2048 elements
@@ -178,32 +308,44 @@ constexpr int kSimtMaxC = 8;  // C tile <= 2048 elements
 template <int SA, int SB, int SC>
 __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
   extern __shared__ float2 smem2[];
+  __shared__ TileTab ta, tb, tcc;
+  __shared__ float red[16];
   const int R = 1 << d.rt, N = 1 << d.nt, K = 1 << d.kt;
   const int ldA = K + 1, ldB = N + 1;
   float2* As = smem2;
   float2* Bs = As + R * ldA;
-  float* red = reinterpret_cast<float*>(Bs + K * ldB);
-  const int tid = threadIdx.x;
-  const uint64_t ro = blockIdx.x % (uint64_t)d.n_row_tiles;
-  const uint64_t no = blockIdx.x / (uint64_t)d.n_row_tiles;
+  const int tid = threadIdx.x, lane = tid & 63;
+  build_tab(d.tA, ldA, 0, 1, ta);
+  build_tab(d.tB, 0, 1, ldB, tb);
+  build_tab(d.tC, 4096, 1, 0, tcc);  // coordinate = row * 4096 + col
+  const uint64_t tiles = (uint64_t)d.n_row_tiles * (uint64_t)d.n_col_tiles;
+  const uint64_t split = blockIdx.x / tiles;
+  const uint64_t tile = blockIdx.x % tiles;
+  const uint64_t ro = tile % (uint64_t)d.n_row_tiles;
+  const uint64_t no = tile / (uint64_t)d.n_row_tiles;
   const int nC = R * N;
-  const int cnt = (nC + kSimtBlock - 1) / kSimtBlock;
-  // Owned C elements (C address order).
-  int crow[kSimtMaxC], ccol[kSimtMaxC];
+  const int nA = R * K, nB = K * N;
+  const int n_kc_all = 1 << d.n_ko;
+  const int n_kc = n_kc_all >> d.ksplit;
+  const int kc0 = (int)split * n_kc;
+  __syncthreads();
+  // Owned C elements, C address order: global offset and (row, col).
   int64_t cg[kSimtMaxC];
+  int crow[kSimtMaxC], ccol[kSimtMaxC];
+  const int64_t glo = tcc.g[lane];
+  const int32_t clo = tcc.c[lane];
 #pragma unroll
   for (int i = 0; i < kSimtMaxC; ++i) {
-    crow[i] = 0;
-    ccol[i] = 0;
-    cg[i] = 0;
-    if (i < cnt) {
-      const uint32_t e = tid + i * kSimtBlock;
-      int kk = 0;
-      if ((int)e < nC) decode(d.tC, e, 0, d.tC.nbits, cg[i], crow[i], ccol[i], kk);
-    }
+    const int e = tid + i * kSimtBlock;
+    const int hi = 64 + (e >> 6);
+    const int ee = e < nC ? hi : 64;
+    cg[i] = glo + tcc.g[ee];
+    const int c = clo + tcc.c[ee];
+    crow[i] = c >> 12;
+    ccol[i] = c & 4095;
   }
-  const int n_kc = 1 << d.n_ko;
-  const int nA = R * K, nB = K * N;
+  const int64_t gAlo = ta.g[lane], gBlo = tb.g[lane];
+  const int32_t cAlo = ta.c[lane], cBlo = tb.c[lane];
   for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     int64_t oA, oB, oC;
@@ -211,62 +353,86 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
     float2 acc[kSimtMaxC];
 #pragma unroll
     for (int i = 0; i < kSimtMaxC; ++i) acc[i] = make_float2(0.f, 0.f);
-    for (int kc = 0; kc < n_kc; ++kc) {
+    for (int kc = kc0; kc < kc0 + n_kc; ++kc) {
       int64_t kA, kB;
       k_offsets(d, kc, kA, kB);
       for (int e = tid; e < nA; e += kSimtBlock) {
-        int64_t g = 0;
-        int r = 0, c = 0, k = 0;
-        decode(d.tA, e, 0, d.tA.nbits, g, r, c, k);
-        As[r * ldA + k] = load_c<SA>(d.A, oA + kA + g);
+        const int hi = 64 + (e >> 6);
+        As[cAlo + ta.c[hi]] = load_c<SA>(d.A, oA + kA + gAlo + ta.g[hi]);
       }
       for (int e = tid; e < nB; e += kSimtBlock) {
-        int64_t g = 0;
-        int r = 0, c = 0, k = 0;
-        decode(d.tB, e, 0, d.tB.nbits, g, r, c, k);
-        Bs[k * ldB + c] = load_c<SB>(d.B, oB + kB + g);
+        const int hi = 64 + (e >> 6);
+        Bs[cBlo + tb.c[hi]] = load_c<SB>(d.B, oB + kB + gBlo + tb.g[hi]);
       }
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < kSimtMaxC; ++i) {
-        if (i < cnt && (int)(tid + i * kSimtBlock) < nC) {
+        if (tid + i * kSimtBlock < nC) {
           const float2* ar = As + crow[i] * ldA;
           const float2* bc = Bs + ccol[i];
-          float2 s = acc[i];
+          float sx = acc[i].x, sy = acc[i].y;
           for (int k = 0; k < K; ++k) {
             const float2 a = ar[k], b = bc[k * ldB];
-            s.x = fmaf(a.x, b.x, s.x);
-            s.x = fmaf(-a.y, b.y, s.x);
-            s.y = fmaf(a.x, b.y, s.y);
-            s.y = fmaf(a.y, b.x, s.y);
+            sx = fmaf(a.x, b.x, sx);
+            sx = fmaf(-a.y, b.y, sx);
+            sy = fmaf(a.x, b.y, sy);
+            sy = fmaf(a.y, b.x, sy);
           }
-          acc[i] = s;
+          acc[i] = make_float2(sx, sy);
         }
       }
       __syncthreads();
+    }
+    if (d.ksplit) {
+      // Partial sums: plain complex64, reduced by k_splitk_reduce.
+      float2* P = d.P + (int64_t)split * d.p_stride;
+#pragma unroll
+      for (int i = 0; i < kSimtMaxC; ++i)
+        if (tid + i * kSimtBlock < nC) P[oC + cg[i]] = acc[i];
+      continue;
     }
     const Scale sc = compute_scale(d, js, jb);
     float lmax = 0.f;
     int bad = 0;
 #pragma unroll
-    for (int i = 0; i < kSimtMaxC; ++i) {
-      if (i < cnt && (int)(tid + i * kSimtBlock) < nC) {
-        float2 v = acc[i];
-        if (sc.shift) {
-          v.x = ldexpf(v.x, -sc.shift);
-          v.y = ldexpf(v.y, -sc.shift);
-        }
-        store_c<SC>(d.C, oC + cg[i], v);
-        if (d.track) {
-          float2 w = v;
-          if (SC != ST_C64) w = load_c<SC>(d.C, oC + cg[i]);
-          const float m = fmaxf(fabsf(w.x), fabsf(w.y));
-          if (!(m <= 3.4e38f)) bad = 1;
-          else lmax = fmaxf(lmax, m);
-        }
-      }
-    }
+    for (int i = 0; i < kSimtMaxC; ++i)
+      if (tid + i * kSimtBlock < nC) store_out<SC>(d, oC + cg[i], acc[i], sc, lmax, bad);
     finish_scale<kSimtBlock>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
+  }
+}
+
+// Split-K reduction: C = sum over splits of the partial buffers, in split
+// order, then the usual scale / store / tracking epilogue.  One workgroup
+// per (row tile, column tile) of C and copy, elements in C address order.
+template <int SC>
+__global__ __launch_bounds__(256) void k_splitk_reduce(StepDesc d) {
+  __shared__ TileTab tcc;
+  __shared__ float red[16];
+  const int tid = threadIdx.x;
+  build_tab(d.tC, 0, 0, 0, tcc);
+  const uint64_t ro = blockIdx.x % (uint64_t)d.n_row_tiles;
+  const uint64_t no = blockIdx.x / (uint64_t)d.n_row_tiles;
+  const int nC = 1 << (d.rt + d.nt);
+  const int ns = 1 << d.ksplit;
+  __syncthreads();
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    const Scale sc = compute_scale(d, js, jb);
+    float lmax = 0.f;
+    int bad = 0;
+    for (int e = tid; e < nC; e += 256) {
+      const int64_t at = oC + tcc.g[e & 63] + tcc.g[64 + (e >> 6)];
+      float sx = 0.f, sy = 0.f;
+      for (int s = 0; s < ns; ++s) {
+        const float2 v = d.P[(int64_t)s * d.p_stride + at];
+        sx += v.x;
+        sy += v.y;
+      }
+      store_out<SC>(d, at, make_float2(sx, sy), sc, lmax, bad);
+    }
+    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
   }
 }
 
@@ -448,7 +614,8 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
 #define RQC_SIMT_CASE(a, b, c)                                                         \
   if (sa == a && sb == b && sc == c) {                                                 \
     hipLaunchKernelGGL((k_simt<a, b, c>), grid, dim3(kSimtBlock), lds, s, d);         \
-    return hipGetLastError();                                                          \
+    e = hipGetLastError();                                                             \
+    goto reduce;                                                                       \
   }
 #define RQC_MFMA_CASE(a, b, c)                                                         \
   if (sa == a && sb == b && sc == c) {                                                 \
@@ -456,13 +623,25 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
     return hipGetLastError();                                                          \
   }
 
-hipError_t launch_step(const StepDesc& d, int kernel, int sa, int sb, int sc, int lp_kind,
+template <int KB>
+static hipError_t launch_rows(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
+  if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, ST_F16>), grid, dim3(256), 0, s, d);
+  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, ST_BF16>), grid, dim3(256), 0, s, d);
+  else hipLaunchKernelGGL((k_rows<KB, ST_C64>), grid, dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const StepDesc& d0, int kernel, int sa, int sb, int sc, int lp_kind,
                        hipStream_t s) {
   (void)lp_kind;
+  StepDesc d = d0;
+  d.sb_store = sb;
+  d.sc_store = sc;
   const uint64_t tiles = (uint64_t)d.n_row_tiles * (uint64_t)d.n_col_tiles;
   const unsigned gy = (unsigned)(d.copies < 65535 ? d.copies : 65535);
   dim3 grid((unsigned)tiles, gy);
-  if (kernel == 1) {
+  hipError_t e = hipSuccess;
+  if (kernel == KERN_MFMA) {
     RQC_MFMA_CASE(ST_C64, ST_C64, ST_C64)
     RQC_MFMA_CASE(ST_C64, ST_C64, ST_F16)
     RQC_MFMA_CASE(ST_C64, ST_C64, ST_BF16)
@@ -480,25 +659,45 @@ hipError_t launch_step(const StepDesc& d, int kernel, int sa, int sb, int sc, in
     RQC_MFMA_CASE(ST_BF16, ST_BF16, ST_C64)
     return hipErrorInvalidValue;
   }
-  const size_t lds = sizeof(float2) * ((size_t)(1 << d.rt) * ((1 << d.kt) + 1) +
-                                       (size_t)(1 << d.kt) * ((1 << d.nt) + 1)) +
-                     64;
-  RQC_SIMT_CASE(ST_C64, ST_C64, ST_C64)
-  RQC_SIMT_CASE(ST_C64, ST_C64, ST_F16)
-  RQC_SIMT_CASE(ST_C64, ST_C64, ST_BF16)
-  RQC_SIMT_CASE(ST_F16, ST_C64, ST_F16)
-  RQC_SIMT_CASE(ST_F16, ST_C64, ST_C64)
-  RQC_SIMT_CASE(ST_BF16, ST_C64, ST_BF16)
-  RQC_SIMT_CASE(ST_BF16, ST_C64, ST_C64)
-  RQC_SIMT_CASE(ST_C64, ST_F16, ST_F16)
-  RQC_SIMT_CASE(ST_C64, ST_F16, ST_C64)
-  RQC_SIMT_CASE(ST_C64, ST_BF16, ST_BF16)
-  RQC_SIMT_CASE(ST_C64, ST_BF16, ST_C64)
-  RQC_SIMT_CASE(ST_F16, ST_F16, ST_F16)
-  RQC_SIMT_CASE(ST_F16, ST_F16, ST_C64)
-  RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_BF16)
-  RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_C64)
-  return hipErrorInvalidValue;
+  if (kernel == KERN_ROWS) {
+    switch (d.kt) {
+      case 0: return launch_rows<0>(d, sa, grid, s);
+      case 1: return launch_rows<1>(d, sa, grid, s);
+      case 2: return launch_rows<2>(d, sa, grid, s);
+      case 3: return launch_rows<3>(d, sa, grid, s);
+      case 4: return launch_rows<4>(d, sa, grid, s);
+      case 5: return launch_rows<5>(d, sa, grid, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  {
+    grid.x = (unsigned)(tiles << d.ksplit);
+    const size_t lds = sizeof(float2) * ((size_t)(1 << d.rt) * ((1 << d.kt) + 1) +
+                                         (size_t)(1 << d.kt) * ((1 << d.nt) + 1));
+    RQC_SIMT_CASE(ST_C64, ST_C64, ST_C64)
+    RQC_SIMT_CASE(ST_C64, ST_C64, ST_F16)
+    RQC_SIMT_CASE(ST_C64, ST_C64, ST_BF16)
+    RQC_SIMT_CASE(ST_F16, ST_C64, ST_F16)
+    RQC_SIMT_CASE(ST_F16, ST_C64, ST_C64)
+    RQC_SIMT_CASE(ST_BF16, ST_C64, ST_BF16)
+    RQC_SIMT_CASE(ST_BF16, ST_C64, ST_C64)
+    RQC_SIMT_CASE(ST_C64, ST_F16, ST_F16)
+    RQC_SIMT_CASE(ST_C64, ST_F16, ST_C64)
+    RQC_SIMT_CASE(ST_C64, ST_BF16, ST_BF16)
+    RQC_SIMT_CASE(ST_C64, ST_BF16, ST_C64)
+    RQC_SIMT_CASE(ST_F16, ST_F16, ST_F16)
+    RQC_SIMT_CASE(ST_F16, ST_F16, ST_C64)
+    RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_BF16)
+    RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_C64)
+    return hipErrorInvalidValue;
+  }
+reduce:
+  if (e != hipSuccess || d.ksplit == 0) return e;
+  grid.x = (unsigned)tiles;
+  if (sc == ST_F16) hipLaunchKernelGGL(k_splitk_reduce<ST_F16>, grid, dim3(256), 0, s, d);
+  else if (sc == ST_BF16) hipLaunchKernelGGL(k_splitk_reduce<ST_BF16>, grid, dim3(256), 0, s, d);
+  else hipLaunchKernelGGL(k_splitk_reduce<ST_C64>, grid, dim3(256), 0, s, d);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -561,7 +561,7 @@ std::string plan_json(const PlanData& p) {
   for (size_t i = 0; i < p.steps.size(); ++i) {
     const Step& st = p.steps[i];
     o << (i ? "," : "") << "{\"node\":" << st.node << ",\"a\":" << st.a << ",\"b\":" << st.b
-      << ",\"m\":" << st.m << ",\"n\":" << st.n << ",\"k\":" << st.k << ",\"kernel\":" << st.kernel
+      << ",\"m\":" << st.m << ",\"n\":" << st.n << ",\"k\":" << st.k
       << ",\"dep_s\":" << (int)st.dep_s << ",\"dep_b\":" << (int)st.dep_b << ",\"lp\":" << (int)st.lp
       << ",\"la\":";
     json_list(o, st.la);

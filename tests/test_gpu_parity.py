@@ -211,3 +211,24 @@ def test_bitstring_batch_and_slice_subsets_and_small_workspace():
     ref = oracle.slice_values_tn(c, openq, bits[0], wires, ids)
     assert oracle.per_slice_error(R.to_complex(per)[:, 0], ref) < 1e-4
     assert oracle.normalized_error(R.to_complex(sub)[0], ref.sum(0), 25) < 1e-4
+
+
+def test_row_streaming_kernel_plan_layout():
+    """Row-streaming kernel on a plan-style layout: summed labels lowest in
+    both operands in the same order, small B, several row tiles."""
+    _say("rows kernel")
+    for (m, n, k, seed) in ((14, 3, 3, 21), (12, 6, 5, 22), (9, 0, 2, 23), (13, 2, 0, 24)):
+        M = list(range(m))
+        N = list(range(100, 100 + n))
+        K = list(range(200, 200 + k))
+        rng = np.random.default_rng(seed)
+        la = [M[i] for i in rng.permutation(m)] + K
+        lb = [N[i] for i in rng.permutation(n)] + K
+        lc = [x for x in (M + N)]
+        lc = [lc[i] for i in rng.permutation(len(lc))]
+        a = rqcgen.random_complex(1 << (m + k), seed)
+        b = rqcgen.random_complex(1 << (n + k), seed + 1)
+        ref = oracle.einsum_step(a, b, la, lb, lc)
+        c = R.pair_contract(_dev_c64(a), _dev_c64(b), la, lb, lc, kernel=2)
+        torch.cuda.synchronize()
+        assert _rel_rms(c.cpu().numpy(), ref) < 2e-5, (m, n, k)
