@@ -29,6 +29,14 @@ PEAK_HBM = 8000.0        # GB/s
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", default="amplitudes", choices=["amplitudes", "steps", "kernel"],
+                    help="amplitudes: the sliced circuit contraction (default); steps: "
+                         "synthetic rank-24..32 pairwise contractions, fused vs permute+GEMM; "
+                         "kernel: one plan-shaped contraction repeated")
+    ap.add_argument("--mnk", default="15,10,13", help="kernel mode: m,n,k bits")
+    ap.add_argument("--batch", type=int, default=8, help="kernel mode: copies per launch")
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--cases", type=int, default=12, help="steps mode: number of synthetic cases")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
@@ -89,6 +97,92 @@ def log(*msg):
     print("[bench]", *msg, file=sys.stderr, flush=True)
 
 
+def _events_time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def kernel_mode(a):
+    """One plan-shaped contraction (summed labels lowest in A and B, random
+    output order) repeated; reports TFLOP/s of the chosen kernel."""
+    import numpy as np
+    import torch
+    import paper_2110_14502_amd as R
+    m, n, k = [int(x) for x in a.mnk.split(",")]
+    rng = np.random.default_rng(7)
+    M, N, K = list(range(m)), list(range(100, 100 + n)), list(range(200, 200 + k))
+    la = [M[i] for i in rng.permutation(m)] + K
+    lb = [N[i] for i in rng.permutation(n)] + K
+    lc = M + N
+    lc = [lc[i] for i in rng.permutation(len(lc))]
+    A = torch.randn(a.batch << (m + k), dtype=torch.complex64, device="cuda")
+    B = torch.randn(a.batch << (n + k), dtype=torch.complex64, device="cuda")
+    C = torch.empty(a.batch << (m + n), dtype=torch.complex64, device="cuda")
+    res = {"mode": "kernel", "m": m, "n": n, "k": k, "batch": a.batch}
+    for kern in (-1, 0):
+        ms = _events_time(lambda: R.pair_contract(A, B, la, lb, lc, C_out=C, kernel=kern,
+                                                  batch=a.batch, stride_a=1 << (m + k),
+                                                  stride_b=1 << (n + k), stride_c=1 << (m + n)),
+                          a.reps)
+        fl = 8.0 * a.batch * 2.0 ** (m + n + k)
+        by = 8.0 * a.batch * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n))
+        res["auto" if kern < 0 else "generic"] = {"ms": ms, "tflops": fl / ms / 1e9,
+                                                 "gbs": by / ms / 1e6}
+        log(f"kernel {kern}: {ms:.3f} ms, {fl / ms / 1e9:.1f} TFLOP/s")
+    print(json.dumps(res), flush=True)
+
+
+def steps_mode(a):
+    """Synthetic pairwise contractions of complex64 tensors of rank 24..32
+    with random index orders: the fused kernel vs permute + GEMM + permute."""
+    import numpy as np
+    import torch
+    import rqcgen
+    import paper_2110_14502_amd as R
+    cases = rqcgen.synthetic_step_cases(3, n_cases=a.cases)
+    out = []
+    for st in cases:
+        ra, rb, rc = len(st.labels_a), len(st.labels_b), len(st.labels_c)
+        g = torch.Generator(device="cuda").manual_seed(st.seed)
+        A = torch.randn(1 << ra, dtype=torch.complex64, device="cuda", generator=g)
+        B = torch.randn(1 << rb, dtype=torch.complex64, device="cuda", generator=g)
+        C = torch.empty(1 << rc, dtype=torch.complex64, device="cuda")
+        K = [x for x in st.labels_a if x in st.labels_b]
+        Mf = [x for x in st.labels_a if x not in K]
+        Nf = [x for x in st.labels_b if x not in K]
+        m, n, k = len(Mf), len(Nf), len(K)
+        fl = 8.0 * 2.0 ** (m + n + k)
+        t_f = _events_time(lambda: R.pair_contract(A, B, st.labels_a, st.labels_b, st.labels_c,
+                                                   C_out=C), a.reps)
+        A2, B2, C2 = torch.empty_like(A), torch.empty_like(B), torch.empty_like(C)
+
+        def unfused():
+            R.permute(A, st.labels_a, Mf + K, out=A2)
+            R.permute(B, st.labels_b, K + Nf, out=B2)
+            R.cgemm(A2, B2, 1 << m, 1 << n, 1 << k, out=C2)
+            R.permute(C2, Mf + Nf, st.labels_c, out=C)
+        t_u = _events_time(unfused, a.reps)
+        row = {"ranks": [ra, rb, rc], "mnk": [m, n, k], "fused_ms": t_f, "unfused_ms": t_u,
+               "fused_tflops": fl / t_f / 1e9, "unfused_tflops": fl / t_u / 1e9,
+               "speedup": t_u / t_f}
+        log(json.dumps(row))
+        out.append(row)
+        del A, B, C, A2, B2, C2
+        torch.cuda.empty_cache()
+    gm = float(np.exp(np.mean([np.log(r["speedup"]) for r in out])))
+    print(json.dumps({"mode": "steps", "cases": out, "geomean_speedup": gm,
+                      "median_fused_tflops": float(np.median([r["fused_tflops"] for r in out]))}),
+          flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -96,6 +190,10 @@ def main():
               "(the slices would shard across GPUs with one final reduction, not built here)",
               file=sys.stderr)
         sys.exit(2)
+    if a.mode == "kernel":
+        return kernel_mode(a)
+    if a.mode == "steps":
+        return steps_mode(a)
     import numpy as np
     import torch
     import rqcgen

@@ -79,7 +79,9 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   } else if (kernel == KERN_ROWS) {
     kt = k;
     nt = n;
-    rt = std::min(m, 11 - n);
+    // Rows per workgroup: 256 threads x rows kept in flight per thread.
+    const int rp_bits = k <= 3 ? 3 : (k == 4 ? 2 : 1);
+    rt = std::min(m, std::min(11 - n, 8 + rp_bits));
     // LDS capacity of the row kernel: B (N*K) and the padded C tile.
     const int64_t ldc = n == 0 ? 1 : (int64_t(1) << n) + 1;
     if ((int64_t(1) << (n + k)) > 2048 || (int64_t(1) << rt) * ldc > 3072 || (rt + n) > 11)

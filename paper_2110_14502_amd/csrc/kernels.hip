@@ -232,17 +232,21 @@ constexpr int kRowsMaxC = 2048;  // R*N
 // C tile with a padded row stride ldc = N + 1 (N >= 2) or 1 (N == 1):
 // R * ldc <= R*N + R <= 2048 + 1024.
 constexpr int kRowsCs = kRowsMaxC + kRowsMaxC / 2;
+// Rows each thread keeps in flight (all loads issued before any use).
+__host__ __device__ constexpr int rows_per_thread(int kb) { return kb <= 3 ? 8 : (kb == 4 ? 4 : 2); }
 
 template <int KB, int SA>
 __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   constexpr int K = 1 << KB;
-  __shared__ float2 Bs[kRowsMaxB];
-  __shared__ float2 Cs[kRowsCs];
+  constexpr int RP = rows_per_thread(KB);
+  extern __shared__ float2 rows_lds[];
   __shared__ TileTab tc;
   __shared__ float red[16];
   const int tid = threadIdx.x;
   const int N = 1 << d.nt, R = 1 << d.rt;
   const int ldc = N == 1 ? 1 : N + 1;
+  float2* Bs = rows_lds;          // [N][K]
+  float2* Cs = rows_lds + N * K;  // [R][ldc]
   build_tab(d.tC, ldc, 1, 0, tc);
   const uint64_t ro = blockIdx.x;
   const int nC = R * N;
@@ -250,6 +254,17 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     int64_t oA, oB, oC;
     outer_offsets(d, ro, 0, js, jb, oA, oB, oC);
+    // Issue this thread's row loads first: they are the HBM stream.
+    float2 a[RP][K];
+#pragma unroll
+    for (int rp = 0; rp < RP; ++rp) {
+      const int r = tid + 256 * rp;
+      if (r < R) {
+        const int64_t base = oA + (int64_t)r * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) a[rp][k] = load_c<SA>(d.A, base + k);
+      }
+    }
     __syncthreads();
     // B is [N][K] and contiguous (it is the whole operand).
     for (int i = tid; i < N * K; i += 256) {
@@ -260,23 +275,23 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
       Bs[i] = v;
     }
     __syncthreads();
-    for (int r = tid; r < R; r += 256) {
-      float2 a[K];
-      const int64_t base = oA + (int64_t)r * K;
 #pragma unroll
-      for (int k = 0; k < K; ++k) a[k] = load_c<SA>(d.A, base + k);
-      for (int n = 0; n < N; ++n) {
-        const float2* b = Bs + n * K;
-        float sx = 0.f, sy = 0.f;
+    for (int rp = 0; rp < RP; ++rp) {
+      const int r = tid + 256 * rp;
+      if (r < R) {
+        for (int n = 0; n < N; ++n) {
+          const float2* b = Bs + n * K;
+          float sx = 0.f, sy = 0.f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float2 bv = b[k];
-          sx = fmaf(a[k].x, bv.x, sx);
-          sx = fmaf(-a[k].y, bv.y, sx);
-          sy = fmaf(a[k].x, bv.y, sy);
-          sy = fmaf(a[k].y, bv.x, sy);
+          for (int k = 0; k < K; ++k) {
+            const float2 bv = b[k];
+            sx = fmaf(a[rp][k].x, bv.x, sx);
+            sx = fmaf(-a[rp][k].y, bv.y, sx);
+            sy = fmaf(a[rp][k].x, bv.y, sy);
+            sy = fmaf(a[rp][k].y, bv.x, sy);
+          }
+          Cs[r * ldc + n] = make_float2(sx, sy);
         }
-        Cs[r * ldc + n] = make_float2(sx, sy);
       }
     }
     __syncthreads();
@@ -439,7 +454,11 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(StepDesc d) {
 // ---------------------------------------------------------------------------
 // MFMA contraction (FP32 matrix cores, v_mfma_f32_32x32x2_f32): 128 rows x
 // 64 complex columns per workgroup, 16 complex k per LDS chunk, double
-// buffered; 4 waves in a 2x2 grid, each 64 rows x 64 real columns.
+// buffered; 4 waves in a 2x2 grid, each 64 rows x 64 real columns.  The
+// operand offsets come from LDS tables built once per workgroup; the output
+// tile is staged through LDS in two halves of 64 rows (inside the operand
+// buffers) and stored in C's address order.  49.7 KB of LDS: three
+// workgroups per CU.
 // ---------------------------------------------------------------------------
 constexpr int kTM = 128, kTN = 64, kTK = 16;
 constexpr int kAPlane = kTM + 1;          // floats per (k, re/im) plane
@@ -447,16 +466,46 @@ constexpr int kAStride = 2 * kAPlane;     // floats per k
 constexpr int kABuf = kTK * kAStride;     // floats per buffer
 constexpr int kBStride = kTN + 1;         // float2 per k
 constexpr int kBBuf = kTK * kBStride;     // float2 per buffer
-constexpr int kCStride = 2 * kTN + 4;     // floats per C row
-constexpr int kMfmaLdsFloats =
-    (2 * kABuf + 4 * kBBuf) > (kTM * kCStride) ? (2 * kABuf + 4 * kBBuf) : (kTM * kCStride);
+constexpr int kMainFloats = 2 * kABuf + 4 * kBBuf;
+constexpr int kCStride = 2 * kTN + 4;     // floats per staged C row
+constexpr int kCHalf = 64 * kCStride;     // floats of one staged half
+constexpr int kTabFloats = (int)(sizeof(TileTab) / sizeof(float));
+static_assert(kCHalf + kTabFloats <= kMainFloats, "C staging must fit the operand buffers");
+static_assert(2 * kTabFloats <= kMainFloats, "operand tables must fit the operand buffers");
+
+// Table over the tile bits of `t` except bit `skip` (lo: first six, hi: rest).
+__device__ __forceinline__ void build_tab_skip(const TileMap& t, int skip, int row_stride,
+                                               int col_stride, TileTab& tab) {
+  int pos[kMaxTile];
+  int nb = 0;
+  for (int b = 0; b < t.nbits; ++b)
+    if (b != skip) pos[nb++] = b;
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+    const int hi = i >= 64;
+    const int v = hi ? i - 64 : i;
+    const int b0 = hi ? 6 : 0;
+    const int b1 = hi ? nb : (nb < 6 ? nb : 6);
+    int64_t g = 0;
+    int32_t c = 0;
+    for (int j = b0; j < b1; ++j) {
+      if ((v >> (j - b0)) & 1) {
+        const int b = pos[j];
+        g += int64_t(1) << t.gpos[b];
+        const int w = 1 << t.cbit[b];
+        c += t.role[b] == 0 ? w * row_stride : w * col_stride;
+      }
+    }
+    tab.g[i] = g;
+    tab.c[i] = c;
+  }
+}
 
 template <int SA, int SB, int SC>
-__global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
-  __shared__ float lds[kMfmaLdsFloats + 16];
-  float* Abuf = lds;                                       // [2][kTK][2][kAPlane]
+__global__ __launch_bounds__(256, 3) void k_mfma32(StepDesc d) {
+  __shared__ float lds[kMainFloats + 16];
+  float* Abuf = lds;                                          // [2][kTK][2][kAPlane]
   float2* Bbuf = reinterpret_cast<float2*>(lds + 2 * kABuf);  // [2][kTK][kBStride]
-  float* red = lds + kMfmaLdsFloats;
+  float* red = lds + kMainFloats;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -473,22 +522,29 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
   int lA[8];
   int64_t gB[4];
   int lB[4];
+  {
+    TileTab* ta = reinterpret_cast<TileTab*>(lds);
+    TileTab* tb = ta + 1;
+    build_tab(d.tA, 1, 0, kAStride, *ta);
+    build_tab(d.tB, 0, 1, kBStride, *tb);
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    int64_t g = 0;
-    int r = 0, c = 0, k = 0;
-    decode(d.tA, tid + 256 * j, 0, d.tA.nbits, g, r, c, k);
-    gA[j] = g;
-    lA[j] = k * kAStride + r;
-  }
+    for (int j = 0; j < 8; ++j) {
+      gA[j] = ta->g[lane] + ta->g[64 + wave + 4 * j];
+      lA[j] = ta->c[lane] + ta->c[64 + wave + 4 * j];
+    }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int64_t g = 0;
-    int r = 0, c = 0, k = 0;
-    decode(d.tB, tid + 256 * j, 0, d.tB.nbits, g, r, c, k);
-    gB[j] = g;
-    lB[j] = k * kBStride + c;
+    for (int j = 0; j < 4; ++j) {
+      gB[j] = tb->g[lane] + tb->g[64 + wave + 4 * j];
+      lB[j] = tb->c[lane] + tb->c[64 + wave + 4 * j];
+    }
   }
+  // The C tile bit that carries row bit 6 (which half of the tile).
+  int hb = 0;
+  for (int b = 0; b < d.tC.nbits; ++b)
+    if (d.tC.role[b] == 0 && d.tC.cbit[b] == 6) hb = b;
+  const int64_t g_half = int64_t(1) << d.tC.gpos[hb];
+
   // Lane roles inside the real-expanded operands.
   const int lrow = lane & 31;          // row inside a 32-row block
   const int cpart = lane >> 5;         // A_r column parity: 0 re, 1 im
@@ -542,18 +598,29 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
       }
       const float* As = Abuf + cur * kABuf + cpart * kAPlane + wm * 64 + lrow;
       const float2* Bs = Bbuf + cur * kBBuf + wn * 32 + ncol;
-#pragma unroll 4
+      // Operands of step k+1 are read from LDS while the MFMAs of step k run.
+      float a0 = As[0], a1 = As[32];
+      float2 b0 = Bs[0], b1 = Bs[16];
+#pragma unroll
       for (int k = 0; k < kTK; ++k) {
-        const float a0 = As[k * kAStride];
-        const float a1 = As[k * kAStride + 32];
-        const float2 b0 = Bs[k * kBStride];
-        const float2 b1 = Bs[k * kBStride + 16];
+        float a0n = 0.f, a1n = 0.f;
+        float2 b0n = make_float2(0.f, 0.f), b1n = make_float2(0.f, 0.f);
+        if (k + 1 < kTK) {
+          a0n = As[(k + 1) * kAStride];
+          a1n = As[(k + 1) * kAStride + 32];
+          b0n = Bs[(k + 1) * kBStride];
+          b1n = Bs[(k + 1) * kBStride + 16];
+        }
         const float v0 = bsign * (bswap ? b0.y : b0.x);
         const float v1 = bsign * (bswap ? b1.y : b1.x);
         acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v1, acc[1][1], 0, 0, 0);
+        a0 = a0n;
+        a1 = a1n;
+        b0 = b0n;
+        b1 = b1n;
       }
       if (more) {
         float* An = Abuf + (cur ^ 1) * kABuf;
@@ -569,39 +636,38 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
       __syncthreads();
     }
 
-    // Stage the 128 x 128 real tile through LDS, then store in C order.
+    // Epilogue: two halves of 64 rows staged in the operand buffers.
     float* Cs = lds;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = wm * 64 + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          const int col = wn * 64 + j * 32 + (lane & 31);
-          Cs[row * kCStride + col] = acc[i][j][r];
-        }
-    __syncthreads();
+    TileTab* tcs = reinterpret_cast<TileTab*>(lds + kCHalf);
+    build_tab_skip(d.tC, hb, kCStride, 2, *tcs);
     const Scale sc = compute_scale(d, js, jb);
     float lmax = 0.f;
     int bad = 0;
-    for (int j = 0; j < (kTM * kTN) / 256; ++j) {
-      int64_t g = 0;
-      int r = 0, c = 0, k = 0;
-      decode(d.tC, tid + 256 * j, 0, d.tC.nbits, g, r, c, k);
-      float2 v = make_float2(Cs[r * kCStride + 2 * c], Cs[r * kCStride + 2 * c + 1]);
-      if (sc.shift) {
-        v.x = ldexpf(v.x, -sc.shift);
-        v.y = ldexpf(v.y, -sc.shift);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (wm == h) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+              const int col = wn * 64 + j * 32 + (lane & 31);
+              Cs[row * kCStride + col] = acc[i][j][r];
+            }
       }
-      store_c<SC>(d.C, oC + g, v);
-      if (d.track) {
-        float2 w = v;
-        if (SC != ST_C64) w = load_c<SC>(d.C, oC + g);
-        const float m = fmaxf(fabsf(w.x), fabsf(w.y));
-        if (!(m <= 3.4e38f)) bad = 1;
-        else lmax = fmaxf(lmax, m);
+      __syncthreads();
+      const int64_t gl = tcs->g[lane] + (h ? g_half : 0);
+      const int32_t cl = tcs->c[lane];
+#pragma unroll 4
+      for (int j = 0; j < 16; ++j) {
+        const int hi = 64 + wave + 4 * j;
+        const int c = cl + tcs->c[hi];
+        const int64_t at = oC + gl + tcs->g[hi];
+        store_out<SC>(d, at, make_float2(Cs[c], Cs[c + 1]), sc, lmax, bad);
       }
+      __syncthreads();
     }
     finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
     __syncthreads();
@@ -625,9 +691,14 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d) {
 
 template <int KB>
 static hipError_t launch_rows(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
-  if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, ST_F16>), grid, dim3(256), 0, s, d);
-  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, ST_BF16>), grid, dim3(256), 0, s, d);
-  else hipLaunchKernelGGL((k_rows<KB, ST_C64>), grid, dim3(256), 0, s, d);
+  const int N = 1 << d.nt, R = 1 << d.rt;
+  const int ldc = N == 1 ? 1 : N + 1;
+  if (R > 256 * rows_per_thread(KB) || N * (1 << KB) > kRowsMaxB || R * ldc > kRowsCs)
+    return hipErrorInvalidValue;
+  const size_t lds = sizeof(float2) * ((size_t)N * (1 << KB) + (size_t)R * ldc);
+  if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, ST_F16>), grid, dim3(256), lds, s, d);
+  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, ST_BF16>), grid, dim3(256), lds, s, d);
+  else hipLaunchKernelGGL((k_rows<KB, ST_C64>), grid, dim3(256), lds, s, d);
   return hipGetLastError();
 }
 

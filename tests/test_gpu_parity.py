@@ -145,7 +145,7 @@ def test_sliced_per_slice_and_sum_fp32():
     assert per.shape == ref.shape
     err = oracle.per_slice_error(per, ref)
     assert err < 1e-4
-    full = oracle.amplitudes_sv(c, list(range(21, 25)), bits)
+    full = oracle.amplitudes_tn(c, list(range(21, 25)), bits)
     assert np.max(np.abs(ref.sum(0) - full)) < 1e-13  # oracle self-consistency
     assert oracle.normalized_error(amps, full, 25) < 1e-4
 
@@ -170,7 +170,7 @@ def test_overflow_filter_reruns_in_fp32():
     P.set_scale_bias(40)
     amps = R.to_complex(P.contract(bits, prec=R.F16))[0]
     assert P.last_report["fp32_reruns"] == 8
-    full = oracle.amplitudes_sv(c, openq, bits)
+    full = oracle.amplitudes_tn(c, openq, bits)
     assert oracle.normalized_error(amps, full, 25) < 1e-4
     P.set_scale_bias(0)
 
@@ -189,7 +189,7 @@ def test_graph_replay_is_bitwise_identical():
     bits2 = rqcgen.random_bits(21, 10)
     a3 = R.to_complex(P.contract(bits2))[0]
     assert P.last_report["graph_reused"] == 1
-    ref = oracle.amplitudes_sv(c, openq, bits2)
+    ref = oracle.amplitudes_tn(c, openq, bits2)
     assert oracle.normalized_error(a3, ref, 25) < 1e-4
 
 
@@ -199,7 +199,7 @@ def test_bitstring_batch_and_slice_subsets_and_small_workspace():
     bits = np.stack([rqcgen.random_bits(21, s) for s in (1, 2, 3)])
     batch = R.to_complex(P.contract(bits))
     for i in range(3):
-        ref = oracle.amplitudes_sv(c, openq, bits[i])
+        ref = oracle.amplitudes_tn(c, openq, bits[i])
         assert oracle.normalized_error(batch[i], ref, 25) < 1e-4
     # a subset of slices, with a workspace that forces ragged groups
     ids = [0, 3, 5, 6, 9, 12, 15]
