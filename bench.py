@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--mnk", default="15,10,13", help="kernel mode: m,n,k bits")
     ap.add_argument("--batch", type=int, default=8, help="kernel mode: copies per launch")
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--kprec", default="f32", choices=["f32", "f16", "bf16"],
+                    help="kernel mode: arithmetic")
     ap.add_argument("--cases", type=int, default=12, help="steps mode: number of synthetic cases")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
@@ -126,11 +128,13 @@ def kernel_mode(a):
     A = torch.randn(a.batch << (m + k), dtype=torch.complex64, device="cuda")
     B = torch.randn(a.batch << (n + k), dtype=torch.complex64, device="cuda")
     C = torch.empty(a.batch << (m + n), dtype=torch.complex64, device="cuda")
-    res = {"mode": "kernel", "m": m, "n": n, "k": k, "batch": a.batch}
+    res = {"mode": "kernel", "m": m, "n": n, "k": k, "batch": a.batch, "prec": a.kprec}
+    kp = R.PRECISIONS[a.kprec]
     for kern in (-1, 0):
         ms = _events_time(lambda: R.pair_contract(A, B, la, lb, lc, C_out=C, kernel=kern,
                                                   batch=a.batch, stride_a=1 << (m + k),
-                                                  stride_b=1 << (n + k), stride_c=1 << (m + n)),
+                                                  stride_b=1 << (n + k), stride_c=1 << (m + n),
+                                                  prec=kp),
                           a.reps)
         fl = 8.0 * a.batch * 2.0 ** (m + n + k)
         by = 8.0 * a.batch * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n))

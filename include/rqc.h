@@ -228,14 +228,17 @@ rqc_status rqc_contract_report(rqc_plan* p, rqc_stream stream,
  * stride_c (0 = shared).  Ranks up to 40.  kernel: -1 auto, 0 generic SIMT,
  * 1 MFMA (needs m >= 7, n >= 6, k >= 4), 2 row streaming (needs the summed
  * labels to be the lowest bits of A and of B in the same order, k <= 5,
- * n <= 6); an unmet condition falls back to the generic kernel. */
+ * n <= 6); an unmet condition falls back to the generic kernel.  prec
+ * RQC_F16 / RQC_BF16 runs dense shapes (m >= 7, n >= 6, k >= 5) on the
+ * 16-bit matrix cores (operands rounded to 16 bits, FP32 accumulation,
+ * complex64 in and out); other shapes and RQC_F32 use FP32 arithmetic. */
 rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a,
                              const int32_t* labels_b, int32_t rank_b,
                              const int32_t* labels_c, int32_t rank_c,
                              const void* A, const void* B, void* C,
                              int32_t batch_count, int64_t stride_a,
                              int64_t stride_b, int64_t stride_c,
-                             int32_t kernel, rqc_stream stream);
+                             int32_t kernel, int32_t prec, rqc_stream stream);
 
 /* Bit permutation of a complex64 tensor: out (labels_out) = in (labels_in).
  * The separate-permutation baseline of Section 5.4. */

@@ -125,7 +125,7 @@ _PROTOS = {
     "rqc_contract_report": (_S, [_P, _P, C.POINTER(rqc_run_report)]),
     "rqc_pair_contract": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                C.POINTER(C.c_int32), C.c_int32, _P, _P, _P, C.c_int32,
-                               C.c_int64, C.c_int64, C.c_int64, C.c_int32, _P]),
+                               C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P]),
     "rqc_permute": (_S, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, _P, _P, _P]),
     "rqc_cgemm": (_S, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P]),
     "rqc_server_create": (_S, [C.POINTER(rqc_server_opts), C.POINTER(_P)]),
@@ -364,7 +364,7 @@ def to_complex(t):
 
 # ---------------------------------------------------------------- single steps
 def pair_contract(A, B, labels_a, labels_b, labels_c, C_out=None, kernel=-1, batch=1,
-                  stride_a=0, stride_b=0, stride_c=0, stream=None):
+                  stride_a=0, stride_b=0, stride_c=0, prec=F32, stream=None):
     """C = A * B summed over shared labels (complex64 torch tensors on device)."""
     import torch
     if C_out is None:
@@ -373,7 +373,7 @@ def pair_contract(A, B, labels_a, labels_b, labels_c, C_out=None, kernel=-1, bat
     _check(_lib.rqc_pair_contract(_i32(labels_a), len(labels_a), _i32(labels_b), len(labels_b),
                                   _i32(labels_c), len(labels_c), _ptr(A), _ptr(B), _ptr(C_out),
                                   int(batch), int(stride_a), int(stride_b), int(stride_c),
-                                  int(kernel), _stream_handle(stream)))
+                                  int(kernel), int(prec), _stream_handle(stream)))
     return C_out
 
 

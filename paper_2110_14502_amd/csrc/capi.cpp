@@ -292,7 +292,8 @@ rqc_status rqc_plan_get_timing(const rqc_plan* p, rqc_timing* out) {
 rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int32_t* labels_b,
                              int32_t rank_b, const int32_t* labels_c, int32_t rank_c, const void* A,
                              const void* B, void* C, int32_t batch_count, int64_t stride_a,
-                             int64_t stride_b, int64_t stride_c, int32_t kernel, rqc_stream stream) {
+                             int64_t stride_b, int64_t stride_c, int32_t kernel, int32_t prec,
+                             rqc_stream stream) {
   RQC_TRY
   if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
   if (rank_a < 0 || rank_b < 0 || rank_c < 0 || rank_a > 40 || rank_b > 40 || rank_c > 40)
@@ -301,6 +302,7 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
     throw rqc::Error{RQC_EINVAL, "NULL labels"};
   if (batch_count < 1 || batch_count > 65535) throw rqc::Error{RQC_EINVAL, "batch_count out of range"};
   if (kernel < -1 || kernel > 2) throw rqc::Error{RQC_EINVAL, "kernel must be -1, 0, 1 or 2"};
+  if (prec != RQC_F32 && prec != RQC_F16 && prec != RQC_BF16) throw rqc::Error{RQC_EINVAL, "bad precision"};
   std::vector<int> la(labels_a, labels_a + rank_a), lb(labels_b, labels_b + rank_b),
       lc(labels_c, labels_c + rank_c);
   for (auto* l : {&la, &lb}) {
@@ -309,6 +311,7 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
     if (std::adjacent_find(s.begin(), s.end()) != s.end()) throw rqc::Error{RQC_EINVAL, "repeated label"};
   }
   int kern = kernel;
+  if (prec != RQC_F32 && (kernel == -1 || kernel == rqc::KERN_MFMA)) kern = rqc::KERN_MFMA16;
   rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, kern);
   d.A = A;
   d.B = B;
@@ -318,7 +321,8 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
   d.sC_s = stride_c;
   d.gs_c = batch_count;
   d.copies = batch_count;
-  rqc::hip_check(rqc::launch_step(d, kern, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, 0,
+  const int lp_kind = prec == RQC_F16 ? rqc::ST_F16 : (prec == RQC_BF16 ? rqc::ST_BF16 : 0);
+  rqc::hip_check(rqc::launch_step(d, kern, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, lp_kind,
                                   static_cast<hipStream_t>(stream)),
                  "pair contract");
   return RQC_OK;

@@ -68,7 +68,9 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
     rows_ok = pos_in(lb, xa) == p;
   }
   const bool mfma_ok = m >= 7 && n >= 6 && k >= 4;
+  const bool mfma16_ok = m >= 7 && n >= 6 && k >= 5;
   if (kernel < 0) kernel = mfma_ok ? KERN_MFMA : (rows_ok ? KERN_ROWS : KERN_SIMT);
+  if (kernel == KERN_MFMA16 && !mfma16_ok) kernel = mfma_ok ? KERN_MFMA : KERN_SIMT;
   if (kernel == KERN_MFMA && !mfma_ok) kernel = KERN_SIMT;
   if (kernel == KERN_ROWS && !rows_ok) kernel = KERN_SIMT;
   int rt, nt, kt;
@@ -76,6 +78,10 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
     rt = 7;
     nt = 6;
     kt = 4;
+  } else if (kernel == KERN_MFMA16) {
+    rt = 7;
+    nt = 6;
+    kt = 5;
   } else if (kernel == KERN_ROWS) {
     kt = k;
     nt = n;
@@ -208,10 +214,16 @@ size_t resident_bytes(rqc_plan* p) {
   p->inv_bytes = off;
   p->tmpl.clear();
   p->kern.clear();
+  p->tmpl_lp.clear();
+  p->kern_lp.clear();
   for (const Step& st : pd.steps) {
     int k = -1;
     p->tmpl.push_back(make_pair_desc(st.la, st.lb, st.lc, k));
     p->kern.push_back(k);
+    // Reduced precision: dense steps with k >= 5 go to the FP16/BF16 MFMA.
+    int k2 = k == KERN_MFMA ? KERN_MFMA16 : k;
+    p->tmpl_lp.push_back(make_pair_desc(st.la, st.lb, st.lc, k2));
+    p->kern_lp.push_back(k2);
   }
   return (size_t)off;
 }
@@ -479,7 +491,8 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
       for (size_t i = 0; i < pd.steps.size(); ++i) {
         const Step& st = pd.steps[i];
         if (st.invariant) continue;
-        StepDesc d = p->tmpl[i];
+        const bool lpm = L.prec != RQC_F32;
+        StepDesc d = lpm ? p->tmpl_lp[i] : p->tmpl[i];
         const Placement &A = L.place[st.a], &B = L.place[st.b], &C = L.place[st.node];
         d.A = ptr(A);
         d.B = ptr(B);
@@ -501,14 +514,14 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
           d.dep_s_c = C.dep_s;
           d.flag_n = gsc;
         }
-        const int kern = p->kern[i];
+        const int kern = lpm ? p->kern_lp[i] : p->kern[i];
         if (L.ksplit[i]) {
           d.ksplit = L.ksplit[i];
           d.P = reinterpret_cast<float2*>(arena + L.p_off[i]);
           d.p_stride = (int64_t(1) << pd.node_labels[st.node].size()) * (C.dep_s ? L.gs : 1) *
                        (C.dep_b ? L.gb : 1);
         }
-        const bool timed = kern == p->timing_kernel;
+        const bool timed = kern == p->timing_kernel || (kern == KERN_MFMA16 && p->timing_kernel == KERN_MFMA);
         if (timed) {
           if (p->tev.size() < 2 * (probe + 1)) {
             hipEvent_t a, b;
@@ -519,7 +532,8 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
           }
           hip_check(hipEventRecord(p->tev[2 * probe], s), "event record");
         }
-        hip_check(launch_step(d, kern, A.store, B.store, C.store, 0, s), "step");
+        const int lp_kind = L.prec == RQC_F16 ? ST_F16 : (L.prec == RQC_BF16 ? ST_BF16 : 0);
+        hip_check(launch_step(d, kern, A.store, B.store, C.store, lp_kind, s), "step");
         if (timed) {
           hip_check(hipEventRecord(p->tev[2 * probe + 1], s), "event record");
           ++probe;

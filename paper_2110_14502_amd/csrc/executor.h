@@ -84,8 +84,8 @@ struct rqc_plan {
   int64_t inv_bytes = 0;
   int scale_bias = 0;
   // Per-step descriptor templates (layout only) and chosen kernels.
-  std::vector<rqc::StepDesc> tmpl;
-  std::vector<int> kern;
+  std::vector<rqc::StepDesc> tmpl, tmpl_lp;  // FP32 and reduced precision
+  std::vector<int> kern, kern_lp;
   // Timing probe: events around launches of one kernel kind.
   int timing_kernel = -1;
   std::vector<hipEvent_t> tev;          // pairs (start, stop)

@@ -81,7 +81,9 @@ struct LeafJob {
 };
 
 // Kernel kinds of a step.
-enum Kernel : int { KERN_SIMT = 0, KERN_MFMA = 1, KERN_ROWS = 2 };
+// KERN_MFMA16: FP16/BF16 matrix cores, 32 complex k per chunk (reduced
+// precision only).
+enum Kernel : int { KERN_SIMT = 0, KERN_MFMA = 1, KERN_ROWS = 2, KERN_MFMA16 = 3 };
 
 // Launchers (kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_step(const StepDesc& d, int kernel, int sa, int sb, int sc, int lp_kind,

@@ -232,3 +232,25 @@ def test_row_streaming_kernel_plan_layout():
         c = R.pair_contract(_dev_c64(a), _dev_c64(b), la, lb, lc, kernel=2)
         torch.cuda.synchronize()
         assert _rel_rms(c.cpu().numpy(), ref) < 2e-5, (m, n, k)
+
+
+@pytest.mark.parametrize("prec,tol", [("f16", 6e-3), ("bf16", 4e-2)])
+def test_lp_mfma_kernel_vs_einsum(prec, tol):
+    """FP16 / BF16 matrix-core contraction: operands rounded to 16 bits
+    (unit roundoff 2^-11 / 2^-8), FP32 accumulation.  Error relative to the
+    RMS output <= a few unit roundoffs (random-sign sums keep the relative
+    error at the operand rounding level)."""
+    _say("lp mfma", prec)
+    for (ra, rb, s, seed) in ((15, 13, 6, 31), (16, 14, 7, 32)):
+        st = rqcgen.synthetic_step(ra, rb, s, seed)
+        a = rqcgen.random_complex(1 << ra, seed)
+        b = rqcgen.random_complex(1 << rb, seed + 1)
+        ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
+        c = R.pair_contract(_dev_c64(a), _dev_c64(b), st.labels_a, st.labels_b, st.labels_c,
+                            prec=R.PRECISIONS[prec])
+        torch.cuda.synchronize()
+        got = c.cpu().numpy().astype(np.complex128)
+        err = _rel_rms(got, ref)
+        assert err < tol, err
+        # and it is not the FP32 path: the error is at the 16-bit level
+        assert err > 1e-6
