@@ -118,10 +118,11 @@ typedef struct rqc_plan_opts {
   uint64_t seed;
   int32_t n_forced;       /* wires that must be sliced, first in slice order */
   const int32_t* forced_wires; /* n_forced (qubit, segment) pairs */
-  int32_t lp_min_log2;    /* reduced-precision modes store intermediates of at
-                             least 2^lp_min_log2 elements per slice in 16 bits;
+  int32_t lp_min_log2;    /* RQC_F16 stores intermediates of at least
+                             2^lp_min_log2 elements per slice in 16 bits;
                              0 = default (14) */
-  int32_t reserved;
+  int32_t bf16_min_log2;  /* the same for RQC_BF16, whose 8-bit significand
+                             rounds more per stored stage; 0 = default (24) */
 } rqc_plan_opts;
 
 void rqc_plan_opts_default(rqc_plan_opts* o);

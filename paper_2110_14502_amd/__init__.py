@@ -46,7 +46,7 @@ class rqc_plan_opts(C.Structure):
                 ("path_trials", C.c_int32), ("reconf_rounds", C.c_int32),
                 ("seed", C.c_uint64), ("n_forced", C.c_int32),
                 ("forced_wires", C.POINTER(C.c_int32)), ("lp_min_log2", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("bf16_min_log2", C.c_int32)]
 
 
 class rqc_plan_info(C.Structure):
@@ -229,7 +229,7 @@ class Plan:
     """Contraction path + slicing plan, optionally bound to device memory."""
 
     def __init__(self, network: Network, max_log2_elems=0, n_sliced=-1, path_trials=256,
-                 reconf_rounds=-1, seed=0, forced_wires=(), lp_min_log2=0):
+                 reconf_rounds=-1, seed=0, forced_wires=(), lp_min_log2=0, bf16_min_log2=0):
         o = rqc_plan_opts()
         _lib.rqc_plan_opts_default(C.byref(o))
         o.max_log2_elems = int(max_log2_elems)
@@ -242,6 +242,7 @@ class Plan:
         o.n_forced = len(forced_wires)
         o.forced_wires = C.cast(self._forced, C.POINTER(C.c_int32))
         o.lp_min_log2 = int(lp_min_log2)
+        o.bf16_min_log2 = int(bf16_min_log2)
         h = C.c_void_p()
         _check(_lib.rqc_plan_create(network.h, C.byref(o), C.byref(h)))
         self.h = h
@@ -326,8 +327,12 @@ class Plan:
             ps = torch.zeros(2 * n_out * cnt, dtype=torch.float64, device=dev)
         if workspace is None:
             lo, pref = self.workspace_bytes(n_ids, n_batch, prec)
-            if self._ws is None or self._ws.numel() < pref:
-                self._ws = torch.empty(pref, dtype=torch.uint8, device=dev)
+            have = self._ws.numel() if self._ws is not None else 0
+            if have < min(pref, max(lo, have)) or have < lo or (have < pref and self._ws is None):
+                self._ws = None
+                free, _ = torch.cuda.mem_get_info(dev)
+                size = int(min(pref, max(lo, 0.8 * free)))
+                self._ws = torch.empty(size, dtype=torch.uint8, device=dev)
             workspace = self._ws
         idp = ids.ctypes.data_as(C.POINTER(C.c_uint64)) if ids is not None else None
         _check(_lib.rqc_contract(self.h, idp, n_ids, bits.ctypes.data_as(C.POINTER(C.c_uint8)),

@@ -111,6 +111,7 @@ void rqc_plan_opts_default(rqc_plan_opts* o) {
   o->reconf_rounds = -1;
   o->seed = 0;
   o->lp_min_log2 = 14;
+  o->bf16_min_log2 = 24;
 }
 
 rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_plan** out) {
@@ -134,6 +135,7 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_
     po.seed = o.seed;
     for (int i = 0; i < o.n_forced; ++i) po.forced.push_back({o.forced_wires[2 * i], o.forced_wires[2 * i + 1]});
     po.lp_min_log2 = o.lp_min_log2 > 0 ? o.lp_min_log2 : 14;
+    po.bf16_min_log2 = o.bf16_min_log2 > 0 ? o.bf16_min_log2 : 24;
     rqc::make_plan(p->pd);
     rqc::resident_bytes(p);
   } catch (...) {

@@ -87,6 +87,7 @@ struct PlanOpts {
   uint64_t seed = 0;
   std::vector<std::pair<int, int>> forced;
   int lp_min_log2 = 14;
+  int bf16_min_log2 = 24;
 };
 
 struct Tree {
@@ -113,7 +114,8 @@ struct Step {
   int kernel = 0;      // 0 SIMT, 1 MFMA
   bool dep_s = false, dep_b = false;  // output depends on slice / bits
   bool invariant = false;
-  bool lp = false;     // output stored in 16 bits in reduced precision
+  bool lp = false;     // output stored in 16 bits in FP16 mode
+  bool lp_bf16 = false;  // output stored in 16 bits in BF16 mode
 };
 
 struct PlanData {

@@ -69,7 +69,9 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   }
   const bool mfma_ok = m >= 7 && n >= 6 && k >= 4;
   const bool mfma16_ok = m >= 7 && n >= 6 && k >= 5;
-  if (kernel < 0) kernel = mfma_ok ? KERN_MFMA : (rows_ok ? KERN_ROWS : KERN_SIMT);
+  // Short sums (k <= 4) are memory-bound: row streaming beats one MFMA chunk.
+  if (kernel < 0)
+    kernel = (mfma_ok && !(rows_ok && k <= 4)) ? KERN_MFMA : (rows_ok ? KERN_ROWS : KERN_SIMT);
   if (kernel == KERN_MFMA16 && !mfma16_ok) kernel = mfma_ok ? KERN_MFMA : KERN_SIMT;
   if (kernel == KERN_MFMA && !mfma_ok) kernel = KERN_SIMT;
   if (kernel == KERN_ROWS && !rows_ok) kernel = KERN_SIMT;
@@ -87,11 +89,20 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
     nt = n;
     // Rows per workgroup: 256 threads x rows kept in flight per thread.
     const int rp_bits = k <= 3 ? 3 : (k == 4 ? 2 : 1);
-    rt = std::min(m, std::min(11 - n, 8 + rp_bits));
-    // LDS capacity of the row kernel: B (N*K) and the padded C tile.
-    const int64_t ldc = n == 0 ? 1 : (int64_t(1) << n) + 1;
-    if ((int64_t(1) << (n + k)) > 2048 || (int64_t(1) << rt) * ldc > 3072 || (rt + n) > 11)
+    rt = std::min(m, 8 + rp_bits);
+    d.ncb = std::min(n, 11 - rt);  // output columns staged per round
+    // LDS capacity of the row kernel: B (N*K) and the padded C chunk.
+    const int64_t ldc = d.ncb == 0 ? 1 : (int64_t(1) << d.ncb) + 1;
+    if ((int64_t(1) << (n + k)) > 2048 || (int64_t(1) << rt) * ldc > 3072 || rt + d.ncb > 11)
       throw Error{RQC_EINVAL, "internal: row kernel tile exceeds LDS capacity"};
+  } else if (m + n <= 8) {
+    // Tiny output, long sum: deep K tiles (split-K spreads them over blocks).
+    rt = m;
+    nt = n;
+    kt = std::min(k, 12 - std::max(m, n));
+    while (kt > 0 && (((int64_t(1) << rt) * ((int64_t(1) << kt) + 1) +
+                       (int64_t(1) << kt) * ((int64_t(1) << nt) + 1)) * 8) > 60 * 1024)
+      --kt;
   } else {
     kt = std::min(k, 4);
     nt = std::min(n, 4);
@@ -106,9 +117,10 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   };
   std::vector<int> Ms, Ns, Ks;
   if (kernel == KERN_ROWS) {
-    // Rows: the lowest M bits of A (just above K), columns in B's order.
+    // Rows: the lowest M bits of A (just above K); columns in C's order so
+    // that a chunk of output columns is (nearly) contiguous in C.
     Ms = by(M, pa);
-    Ns = by(N, pb);
+    Ns = by(N, pc);
     Ks = by(K, pa);
   } else {
     Ms = by(M, [&](int x) { return std::min(pa(x), pc(x)); });
@@ -147,8 +159,22 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   if (kernel != KERN_ROWS) {
     tile(d.tA, ba, pa);
     tile(d.tB, bb, pb);
+    tile(d.tC, bc, pc);
+  } else {
+    // tB: column bit j (in C order) -> its B position; tC: rows and the
+    // chunk's low column bits; nh_C: C positions of the chunk-selecting bits.
+    d.tB.nbits = n;
+    for (int j = 0; j < n; ++j) {
+      d.tB.gpos[j] = (int8_t)pb(Nt[j]);
+      d.tB.role[j] = 1;
+      d.tB.cbit[j] = (int8_t)j;
+    }
+    std::vector<std::pair<int, int>> bcr;
+    for (int x : Rt) bcr.push_back({x, 0});
+    for (int j = 0; j < d.ncb; ++j) bcr.push_back({Nt[j], 1});
+    tile(d.tC, bcr, pc);
+    for (int j = d.ncb; j < n; ++j) d.nh_C[j - d.ncb] = (int8_t)pc(Nt[j]);
   }
-  tile(d.tC, bc, pc);
   d.rt = rt;
   d.nt = nt;
   d.kt = kt;
@@ -319,7 +345,9 @@ static GroupLayout compute_layout(rqc_plan* p, int prec, int gs, int gb) {
       continue;
     }
     const int cs = P.dep_s ? gs : 1, cb = P.dep_b ? gb : 1;
-    P.store = (track && v >= nl && pd.steps[pd.step_of_node[v]].lp) ? lp_store : ST_C64;
+    const Step& ps = pd.steps[v >= nl ? pd.step_of_node[v] : 0];
+    const bool lp16 = v >= nl && (prec == RQC_BF16 ? ps.lp_bf16 : ps.lp);
+    P.store = (track && lp16) ? lp_store : ST_C64;
     P.s_stride = P.dep_s ? E : 0;
     P.b_stride = P.dep_b ? E * cs : 0;
     bytes[v] = align256(E * cs * cb * elsize(P.store));
@@ -367,8 +395,10 @@ static GroupLayout compute_layout(rqc_plan* p, int prec, int gs, int gb) {
       const Placement& C = L.place[st.node];
       const int64_t copies = (int64_t)(C.dep_s ? gs : 1) * (C.dep_b ? gb : 1);
       const int64_t work = (int64_t)t.n_row_tiles * t.n_col_tiles * copies;
+      // Enough workgroups to fill the GPU, and no more than 2^12 summed
+      // chunks left per workgroup.
       int ks = 0;
-      while (ks < t.n_ko && (work << ks) < 1024) ++ks;
+      while (ks < t.n_ko && ((work << ks) < 4096 || t.n_ko - ks > 12)) ++ks;
       const int64_t cbytes = (int64_t(8) << pd.node_labels[st.node].size()) *
                              (C.dep_s ? gs : 1) * (C.dep_b ? gb : 1);
       while (ks > 0 && (cbytes << ks) > (int64_t(1) << 30)) --ks;

@@ -60,6 +60,10 @@ struct StepDesc {
   float2* P;
   int64_t p_stride;
   int32_t sb_store, sc_store;  // storage codes of B and C (runtime copies)
+  // Row kernel: output columns staged 2^ncb at a time; the remaining column
+  // bits (their C positions in nh_C) select the chunk.
+  int32_t ncb;
+  int8_t nh_C[16];
   int8_t ro_A[kMaxOuter], ro_C[kMaxOuter];
   int8_t no_B[kMaxOuter], no_C[kMaxOuter];
   int8_t ko_A[kMaxOuter], ko_B[kMaxOuter];

@@ -9,8 +9,9 @@
 //   2. per trial, greedy slicing: repeatedly slice the wire that keeps the
 //      total (all-slice) cost lowest, preferring wires that shrink the
 //      largest intermediate while it exceeds the bound;
-//   3. subtree re-optimisation of the best tree: small subtrees are
-//      re-solved exactly by dynamic programming over subsets;
+//   3. subtree re-optimisation of the 32 best trees: small subtrees are
+//      re-solved exactly by dynamic programming over subsets, and the best
+//      re-optimised tree wins;
 //   4. execution order, slice/bit dependence, and per-step layouts chosen
 //      top-down so that each operand's summed labels are its lowest address
 //      bits (contiguous K runs) and its free labels keep the order of the
@@ -25,6 +26,7 @@
 #include <random>
 #include <set>
 #include <sstream>
+#include <thread>
 #include <unordered_map>
 
 #include "core.h"
@@ -444,6 +446,7 @@ static void build_steps(PlanData& p) {
     st.dep_b = p.dep_b[v];
     st.invariant = !st.dep_s && !st.dep_b;
     st.lp = !st.invariant && (int)s[v].size() >= p.opts.lp_min_log2;
+    st.lp_bf16 = !st.invariant && (int)s[v].size() >= p.opts.bf16_min_log2;
     const double fl = 8.0 * std::ldexp(1.0, st.m + st.n + st.k);
     const double by = 8.0 * (std::ldexp(1.0, (int)s[a].size()) + std::ldexp(1.0, (int)s[b].size()) +
                              std::ldexp(1.0, (int)s[v].size()));
@@ -483,41 +486,88 @@ void make_plan(PlanData& p) {
     throw Error{RQC_EINVAL, "n_sliced smaller than the forced wires"};
   if (p.opts.n_sliced > 62) throw Error{RQC_EUNSUPPORTED, "more than 62 sliced wires"};
 
-  std::mt19937_64 rng(p.opts.seed * 0x9E3779B97F4A7C15ull + 12345);
-  std::uniform_real_distribution<double> ua(0.0, 1.6);
+  // Independent trials: trial t draws from its own generator seeded by
+  // (seed, t), so the result does not depend on how trials are spread over
+  // threads.
   const double temps[] = {0.0, 0.02, 0.1, 0.3, 0.6, 1.0};
   const int trials = std::max(1, p.opts.trials);
-
-  Tree best_tree;
-  SliceResult best_sl;
-  double best_score = 1e308;
-  for (int tr = 0; tr < trials; ++tr) {
+  struct TrialResult {
+    double score = 1e308;
+    Tree tree;
+    SliceResult sl;
+  };
+  std::vector<TrialResult> results(trials);
+  auto run_trial = [&](int tr) {
+    std::mt19937_64 rng(p.opts.seed * 0x9E3779B97F4A7C15ull + 0x51ED27ull * (uint64_t)tr + 12345);
+    std::uniform_real_distribution<double> ua(0.0, 1.6);
     const double alpha = tr == 0 ? 1.0 : ua(rng);
     const double temp = tr == 0 ? 0.0 : temps[rng() % 6];
     Tree t = greedy_tree(leaf_sets, nlab, alpha, temp, rng);
     SliceResult sr = slice_tree(t, leaf_sets, nlab, sliceable, forced, p.opts.max_log2, p.opts.n_sliced);
     const double total = std::log2(sr.per_slice.flops) + (double)sr.sliced.size();
-    // Penalise plans that still exceed the width bound (could not slice).
     const double over = p.opts.max_log2 > 0 ? std::max(0, sr.per_slice.width - p.opts.max_log2) : 0;
-    const double score = total + 4.0 * over;
-    if (score < best_score) {
-      best_score = score;
-      best_tree = std::move(t);
-      best_sl = std::move(sr);
+    results[tr].score = total + 4.0 * over;
+    results[tr].tree = std::move(t);
+    results[tr].sl = std::move(sr);
+  };
+  const int n_threads = std::min(8, trials);
+  {
+    std::vector<std::thread> pool;
+    for (int w = 0; w < n_threads; ++w)
+      pool.emplace_back([&, w] {
+        for (int tr = w; tr < trials; tr += n_threads) run_trial(tr);
+      });
+    for (auto& th : pool) th.join();
+  }
+  // Re-optimise the best few trees on their sliced networks; keep the best.
+  std::vector<int> order(trials);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return results[x].score < results[y].score; });
+  const int n_refine = std::min(trials, 32);
+  struct Refined {
+    double score = 1e308;
+    Tree tree;
+    std::vector<LSet> sets;
+    std::vector<int> sliced;
+  };
+  std::vector<Refined> refined(n_refine);
+  auto refine = [&](int r) {
+    TrialResult& tr = results[order[r]];
+    std::vector<char> drop(nlab, 0);
+    for (int x : tr.sl.sliced) drop[x] = 1;
+    std::vector<LSet> sliced_leaf(nl);
+    for (int i = 0; i < nl; ++i) sliced_leaf[i] = remove_labels(leaf_sets[i], drop);
+    std::vector<LSet> s = node_sets(tr.tree, sliced_leaf);
+    const int w0 = tree_cost(tr.tree, s).width;
+    const int wb = p.opts.max_log2 > 0 ? std::max(p.opts.max_log2, w0) : w0;
+    if (p.opts.reconf_rounds > 0) {
+      std::mt19937_64 rng(p.opts.seed * 0x2545F4914F6CDD1Dull + (uint64_t)r + 777);
+      reconfigure(tr.tree, s, p.opts.reconf_rounds, 8, wb, rng);
+      s = node_sets(tr.tree, sliced_leaf);
     }
+    const CostModel c = tree_cost(tr.tree, s);
+    refined[r].score = std::log2(c.flops) + (double)tr.sl.sliced.size() +
+                       (p.opts.max_log2 > 0 ? 4.0 * std::max(0, c.width - p.opts.max_log2) : 0.0);
+    refined[r].tree = tr.tree;
+    refined[r].sets = std::move(s);
+    refined[r].sliced = tr.sl.sliced;
+  };
+  {
+    std::vector<std::thread> pool;
+    for (int w = 0; w < std::min(8, n_refine); ++w)
+      pool.emplace_back([&, w] {
+        for (int r = w; r < n_refine; r += 8) refine(r);
+      });
+    for (auto& th : pool) th.join();
   }
-  // Re-optimise the sliced tree.
-  std::vector<char> drop(nlab, 0);
-  for (int x : best_sl.sliced) drop[x] = 1;
-  std::vector<LSet> sliced_leaf(nl);
-  for (int i = 0; i < nl; ++i) sliced_leaf[i] = remove_labels(leaf_sets[i], drop);
-  std::vector<LSet> s = node_sets(best_tree, sliced_leaf);
-  const int wb = p.opts.max_log2 > 0 ? std::max(p.opts.max_log2, tree_cost(best_tree, s).width)
-                                     : tree_cost(best_tree, s).width;
-  if (p.opts.reconf_rounds > 0) {
-    reconfigure(best_tree, s, p.opts.reconf_rounds, 8, wb, rng);
-    s = node_sets(best_tree, sliced_leaf);
-  }
+  int best = 0;
+  for (int r = 1; r < n_refine; ++r)
+    if (refined[r].score < refined[best].score) best = r;
+  Tree best_tree = std::move(refined[best].tree);
+  std::vector<LSet> s = std::move(refined[best].sets);
+  SliceResult best_sl;
+  best_sl.sliced = refined[best].sliced;
   p.tree = std::move(best_tree);
   p.sliced = best_sl.sliced;
   p.node_labels = s;

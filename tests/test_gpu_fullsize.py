@@ -1,0 +1,125 @@
+"""Full-size checks of the benchmark workload: the 6x6 (1+14+1) circuit with
+64 open-qubit amplitudes and 8 sliced wires (256 slices).
+
+The oracle cannot contract one of its 256 slices in seconds (about 2^37
+complex multiply-adds each), so the full size is covered by:
+* element-by-element parity on sub-slices of the same circuit: the slicing
+  refined to 24 fixed wires makes each sub-slice cheap for the oracle;
+* the plan's densest step at its real shape and layouts, checked on sampled
+  output coordinates computed one by one by the oracle;
+* properties that hold at any size: two plans with different trees and
+  different sliced wires give the same amplitudes; a closed bitstring gives
+  the matching entry of the open batch; FP16/BF16 agree with FP32 within
+  the reduced-precision tolerance; Porter-Thomas mean of 2^n |a|^2.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import rqcgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2110_14502_amd")
+
+ROWS, COLS, DEPTH, SEED, N_OPEN, N_SLICED, TRIALS, PLAN_SEED = 6, 6, 14, 2, 6, 8, 4096, 2
+N = ROWS * COLS
+OPEN = list(range(N - N_OPEN, N))
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def workload():
+    circ = rqcgen.grid_rqc(ROWS, COLS, DEPTH, SEED)
+    bits = rqcgen.random_bits(N - N_OPEN, SEED)
+    net = R.Network(R.Circuit.from_rqcgen(circ), OPEN)
+    plan = R.Plan(net, n_sliced=N_SLICED, path_trials=TRIALS, seed=PLAN_SEED).bind()
+    amps = R.to_complex(plan.contract(bits))[0]
+    return circ, bits, net, plan, amps
+
+
+def test_fullsize_subslices_vs_oracle(workload):
+    circ, bits, net, plan, _ = workload
+    _say("fullsize subslices")
+    base = plan.sliced_wires()
+    fine = R.Plan(net, n_sliced=24, forced_wires=base, path_trials=64, seed=PLAN_SEED).bind()
+    wires = fine.sliced_wires()
+    assert wires[:N_SLICED] == base
+    ids = [int(x) for x in np.random.default_rng(1).choice(1 << 24, size=3, replace=False)]
+    _, per = fine.contract(bits, slice_ids=ids, per_slice=True)
+    got = R.to_complex(per)[:, 0]
+    ref = oracle.slice_values_tn(circ, OPEN, bits, wires, ids)
+    assert oracle.per_slice_error(got, ref) < 1e-4
+
+
+def test_fullsize_dense_step_sampled(workload):
+    """The plan's largest step at its real layouts, batch of 2 copies,
+    random operands; 48 sampled outputs vs direct complex128 sums."""
+    _, _, _, plan, _ = workload
+    _say("fullsize dense step")
+    e = plan.export()
+    st = max(e["steps"], key=lambda s: s["m"] + s["n"] + s["k"])
+    la, lb, lc = st["la"], st["lb"], st["lc"]
+    nb = 2
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn(nb << len(la), dtype=torch.complex64, device="cuda", generator=g)
+    B = torch.randn(nb << len(lb), dtype=torch.complex64, device="cuda", generator=g)
+    C = R.pair_contract(A, B, la, lb, lc, batch=nb, stride_a=1 << len(la),
+                        stride_b=1 << len(lb), stride_c=1 << len(lc))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    for copy in range(nb):
+        coords = rng.integers(0, 1 << len(lc), size=24)
+        a0, b0, c0 = copy << len(la), copy << len(lb), copy << len(lc)
+
+        def get(T, off):
+            return lambda idx: T[torch.from_numpy(np.asarray(idx) + off).cuda()].cpu().numpy()
+        ref = oracle.sampled_step(get(A, a0), get(B, b0), la, lb, lc, coords)
+        got = C[torch.from_numpy(coords + c0).cuda()].cpu().numpy()
+        scale = np.sqrt(2.0 ** st["k"])  # RMS of a sum of 2^k unit-variance products
+        assert np.max(np.abs(got - ref)) / scale < 2e-5
+
+
+def test_fullsize_two_plans_agree(workload):
+    circ, bits, net, plan, amps = workload
+    _say("fullsize two plans")
+    other = R.Plan(net, n_sliced=N_SLICED, path_trials=512, seed=11).bind()
+    assert other.sliced_wires() != plan.sliced_wires()
+    amps2 = R.to_complex(other.contract(bits))[0]
+    assert oracle.normalized_error(amps2, amps, N) < 1e-4
+
+
+def test_fullsize_closed_entry_matches_open_batch(workload):
+    circ, bits, net, plan, amps = workload
+    _say("fullsize closed entry")
+    j = 37
+    full_bits = list(bits) + [(j >> i) & 1 for i in range(N_OPEN)]
+    netc = R.Network(R.Circuit.from_rqcgen(circ), [])
+    pc = R.Plan(netc, n_sliced=N_SLICED, path_trials=512, seed=3).bind()
+    a = R.to_complex(pc.contract(np.array(full_bits, dtype=np.uint8)))[0][0]
+    assert abs(a - amps[j]) * 2 ** (N / 2) < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_fullsize_reduced_precision_vs_fp32(workload, prec):
+    circ, bits, net, plan, amps = workload
+    _say("fullsize", prec)
+    lp = R.to_complex(plan.contract(bits, prec=R.PRECISIONS[prec]))[0]
+    assert plan.last_report["fp32_reruns"] == 0
+    assert oracle.normalized_error(lp, amps, N) < 2e-2
+    assert oracle.linear_fidelity(lp, amps) > 0.99
+
+
+def test_fullsize_porter_thomas_mean(workload):
+    _, _, _, _, amps = workload
+    p = np.abs(amps) ** 2 * 2 ** N
+    # 64 draws of an Exp(1) variable: the mean is within 0.5..1.6 with
+    # probability > 0.999.
+    assert 0.5 < p.mean() < 1.6
