@@ -30,7 +30,8 @@ PEAK_HBM = 8000.0        # GB/s
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", default="amplitudes", choices=["amplitudes", "steps", "kernel"],
+    ap.add_argument("--mode", default="amplitudes",
+                    choices=["amplitudes", "steps", "kernel", "serve"],
                     help="amplitudes: the sliced circuit contraction (default); steps: "
                          "synthetic rank-24..32 pairwise contractions, fused vs permute+GEMM; "
                          "kernel: one plan-shaped contraction repeated")
@@ -40,6 +41,9 @@ def parse():
     ap.add_argument("--kprec", default="f32", choices=["f32", "f16", "bf16"],
                     help="kernel mode: arithmetic")
     ap.add_argument("--cases", type=int, default=12, help="steps mode: number of synthetic cases")
+    ap.add_argument("--requests", type=int, default=600, help="serve mode: Poisson requests")
+    ap.add_argument("--load", type=float, default=0.8, help="serve mode: rate / saturation rate")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve mode: device pool")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
@@ -188,6 +192,108 @@ def steps_mode(a):
           flush=True)
 
 
+def serve_mode(a):
+    """Continuous batching of amplitude requests over seeded circuits from 5x5
+    to 8x8 qubits at depths 10-20 (families whose plan exceeds 2^42 flops are
+    rejected), 0-10 open qubits, FP16 or FP32; Poisson arrivals at a fraction
+    of the measured saturation rate."""
+    import numpy as np
+    import torch
+    import rqcgen
+    import paper_2110_14502_amd as R
+    rng = np.random.default_rng(5)
+    fams, tried = [], 0
+    t = time.perf_counter()
+    for (r, c) in ((5, 5), (6, 6), (7, 7), (8, 8)):
+        for d in range(10, 21, 2):
+            tried += 1
+            n = r * c
+            circ = rqcgen.grid_rqc(r, c, d, 1)
+            try:
+                P = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), list(range(n - 10, n))),
+                           max_log2_elems=26, path_trials=64, seed=1)
+                ok = P.info()["log2_total_flops"] <= 42
+            except R.RqcError:
+                ok = False
+            if ok:
+                fams.append((r, c, d))
+    log(f"serve: {len(fams)}/{tried} circuit families accepted ({time.perf_counter() - t:.1f}s)")
+    pool = {}
+    for f in fams:
+        for sd in range(4):
+            pool[(f, sd)] = rqcgen.grid_rqc(f[0], f[1], f[2], 1000 + sd)
+
+    def draw(i):
+        f = fams[int(rng.integers(len(fams)))]
+        sd = int(rng.integers(4))
+        circ = pool[(f, sd)]
+        n = circ.n_qubits
+        n_open = int(rng.integers(0, 11))
+        openq = list(range(n - n_open, n))
+        bits = rqcgen.random_bits(n - n_open, 10000 + i)
+        prec = R.F16 if rng.random() < 0.5 else R.F32
+        return circ, openq, bits, prec
+
+    srv = R.Server(int(a.budget_gb * (1 << 30)), max_inflight=8, n_streams=4, max_batch=32)
+
+    def submit(q):
+        circ, openq, bits, prec = q
+        return srv.submit(circ.n_qubits, circ.gates, openq, bits, prec=prec, max_log2_elems=26)
+
+    def collect(tickets):
+        got = {}
+        while len(got) < len(tickets):
+            for r in srv.poll(1024):
+                got[r["ticket"]] = r
+            time.sleep(0.0005)
+        return [got[t] for t in tickets]
+
+    # Warm-up: one request per circuit builds and binds every plan.
+    warm = [submit((c, list(range(c.n_qubits - 2, c.n_qubits)), rqcgen.random_bits(c.n_qubits - 2, 1),
+                    R.F32)) for c in pool.values()]
+    collect(warm)
+    log(f"serve: warmed {len(warm)} plans")
+    # Saturation: a burst of requests at once.
+    burst = [draw(i) for i in range(min(200, a.requests))]
+    t0 = time.perf_counter()
+    res = collect([submit(q) for q in burst])
+    t_sat = time.perf_counter() - t0
+    sat_rate = len(burst) / t_sat
+    log(f"serve: saturation {sat_rate:.1f} requests/s")
+    # Poisson stream at `load` x saturation.
+    lam = a.load * sat_rate
+    arr = rqcgen.poisson_arrivals(lam, a.requests, 6)
+    stream = [draw(10000 + i) for i in range(a.requests)]
+    tickets = []
+    t0 = time.perf_counter()
+    for q, ta in zip(stream, arr):
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        tickets.append(submit(q))
+    res = collect(tickets)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    ok = [r for r in res if r["status"] == 0]
+    failed = {}
+    for q, r in zip(stream, res):
+        if r["status"] != 0:
+            key = f"{q[0].n_qubits}q open{len(q[1])} prec{q[3]} status{r['status']}"
+            failed[key] = failed.get(key, 0) + 1
+    lat = np.array([r["t_done"] - r["t_submit"] for r in ok])
+    n_amp = sum(1 << len(q[1]) for q, r in zip(stream, res) if r["status"] == 0)
+    out = {"mode": "serve", "requests": a.requests, "completed": len(ok),
+           "families_accepted": f"{len(fams)}/{tried}", "saturation_req_s": sat_rate,
+           "offered_req_s": lam, "amplitudes_per_s": n_amp / wall,
+           "requests_per_s": len(ok) / wall,
+           "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),
+                          "p99": 1000 * float(np.percentile(lat, 99))},
+           "max_inflight_seen": st["max_inflight_seen"], "plans_built": st["plans_built"],
+           "plans_reused": st["plans_reused"], "peak_bytes": st["peak_bytes"], "failed": failed}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -199,6 +305,8 @@ def main():
         return kernel_mode(a)
     if a.mode == "steps":
         return steps_mode(a)
+    if a.mode == "serve":
+        return serve_mode(a)
     import numpy as np
     import torch
     import rqcgen
