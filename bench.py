@@ -14,6 +14,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -25,13 +26,16 @@ METRIC = "amplitudes/s + contraction TFLOP/s vs plain FP32 path at stated error;
 PEAK_MFMA_FP32 = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_MFMA_16 = 2500.0    # TFLOP/s, MI355X dense FP16 / BF16 matrix
 PEAK_HBM = 8000.0        # GB/s
+# Counter summary (FETCH_SIZE / WRITE_SIZE) of the FP32 MFMA launches of the
+# default amplitude workload.
+TRAFFIC_PROFILE = "k_mfma32_config2_6x6x14_fp32_traffic.md"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", default="amplitudes",
-                    choices=["amplitudes", "steps", "kernel", "serve"],
+                    choices=["amplitudes", "steps", "kernel", "serve", "copy"],
                     help="amplitudes: the sliced circuit contraction (default); steps: "
                          "synthetic rank-24..32 pairwise contractions, fused vs permute+GEMM; "
                          "kernel: one plan-shaped contraction repeated")
@@ -98,6 +102,43 @@ def cpu_baseline(circ, openq, bits, n_fixed, budget_s, plan_seed, base_wires):
             "sample": f"{done} of the 2^{n_fixed} sub-slices (wires fixed: the 8-wire slicing refined "
                       f"to {n_fixed}) of the same 64-amplitude sum, complex128 numpy, "
                       f"{dt:.1f} s, extrapolated to the full sum ({full:.3g} s)"}
+
+
+def _norm_err(a, ref, n_qubits):
+    """max |a - ref| in units of the RMS amplitude 2^(-n/2)."""
+    import numpy as np
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(ref)))) * 2.0 ** (n_qubits / 2)
+
+
+def _fidelity(a, ref):
+    """Linear fidelity |<ref|a>|^2 / (<ref|ref><a|a>)."""
+    import numpy as np
+    a, ref = np.asarray(a).ravel(), np.asarray(ref).ravel()
+    num = abs(np.vdot(ref, a)) ** 2
+    return float(num / (np.vdot(ref, ref).real * np.vdot(a, a).real))
+
+
+def _profile_traffic(name, flops_per_launch):
+    """HBM bytes per launch of the dominant kernel from a committed counter
+    summary, or None when the summary does not match: the kernel sources
+    changed since the counters were taken, or its launches were different."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        text = open(os.path.join(root, "profiles", name)).read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
+    src = os.path.join(root, "paper_2110_14502_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    try:
+        if vals.get("kernels_hip_sha256") != sha:
+            return None
+        if abs(float(vals["flops_per_launch"]) / flops_per_launch - 1) > 1e-6:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
 
 
 def log(*msg):
@@ -294,6 +335,17 @@ def serve_mode(a):
     print(json.dumps(out), flush=True)
 
 
+def copy_mode(a):
+    """A plain device copy of 1 GiB (calibration of the traffic counters)."""
+    import torch
+    n = 1 << 30
+    x = torch.ones(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    ms = _events_time(lambda: y.copy_(x), 3)
+    print(json.dumps({"mode": "copy", "bytes_read": n, "bytes_written": n, "ms": ms,
+                      "gbs": 2 * n / ms / 1e6}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -307,6 +359,8 @@ def main():
         return steps_mode(a)
     if a.mode == "serve":
         return serve_mode(a)
+    if a.mode == "copy":
+        return copy_mode(a)
     import numpy as np
     import torch
     import rqcgen
@@ -403,7 +457,9 @@ def main():
             "peak": PEAK_MFMA_FP32 if a.prec == "f32" else PEAK_MFMA_16,
             "unit": "TFLOP/s",
             "frac": achieved / (PEAK_MFMA_FP32 if a.prec == "f32" else PEAK_MFMA_16),
-            "traffic": None,
+            "traffic": (_profile_traffic(TRAFFIC_PROFILE, tim["flops"] / max(1, tim["launches"]))
+                        if a.prec == "f32" else None),
+            "algorithmic_bytes_per_launch": tim["bytes"] / max(1, tim["launches"]),
             "launches": tim["launches"],
             "avg_launch_ms": tim["total_ms"] / max(1, tim["launches"]),
             "flops_per_launch": tim["flops"] / max(1, tim["launches"]),
@@ -428,15 +484,14 @@ def main():
             rep16 = step(R.F16, "f16")
         torch.cuda.synchronize()
         ms16 = 1000.0 * (time.perf_counter() - t0) / a.lp_steps / frac
-        import oracle.metrics as om  # error measure only; no oracle arithmetic
         lp_amps = R.to_complex(out.view(-1, 2))
         f32_amps = R.to_complex(ref_amps.view(-1, 2))
         res["reduced_precision"] = {
             "dtype": "f16 (16-bit storage of large intermediates, FP16 MFMA, FP32 accumulate)",
             "ms_per_step": ms16, "value": n_amp / (ms16 / 1000.0), "speedup_vs_f32": ms / ms16,
             "fp32_reruns": rep16["fp32_reruns"],
-            "normalized_error_vs_f32": om.normalized_error(lp_amps, f32_amps, n),
-            "fidelity_vs_f32": om.linear_fidelity(lp_amps, f32_amps)}
+            "normalized_error_vs_f32": _norm_err(lp_amps, f32_amps, n),
+            "fidelity_vs_f32": _fidelity(lp_amps, f32_amps)}
     if a.cpu_seconds > 0:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(circ, openq, bits, a.sliced + 16, a.cpu_seconds,

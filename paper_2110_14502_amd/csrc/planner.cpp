@@ -568,8 +568,8 @@ void make_plan(PlanData& p) {
   std::vector<LSet> s = std::move(refined[best].sets);
   SliceResult best_sl;
   best_sl.sliced = refined[best].sliced;
-  if (best_sl.sliced.size() > 48)
-    throw Error{RQC_EUNSUPPORTED, "the width bound needs more than 48 sliced wires (2^48 slices)"};
+  if (best_sl.sliced.size() > 62)
+    throw Error{RQC_EUNSUPPORTED, "the width bound needs more than 62 sliced wires (2^62 slices)"};
   p.tree = std::move(best_tree);
   p.sliced = best_sl.sliced;
   p.node_labels = s;
