@@ -14,7 +14,8 @@ Everything is plain numpy in complex128:
   class of simulators), used as the ground truth for small circuits;
 * ``tn``          -- one tensor per gate (Section 3.2, tensor approach),
   optional slicing of wires (Section 5.1), pairwise contraction with
-  ``numpy.tensordot`` in a plain greedy order;
+  ``numpy.tensordot`` in a plain greedy order, or in an order given as
+  data (``contract_ordered``: the order changes cost, never the value);
 * ``step``        -- a single pairwise contraction (Section 5.4) by
   ``numpy.einsum``, and by direct summation at sampled output coordinates;
 * ``metrics``     -- normalised error and linear fidelity.
@@ -28,7 +29,7 @@ tiny inputs.
 from .gates import gate_matrix, H_M, SQRT_X_M, SQRT_Y_M, SQRT_W_M, fsim
 from .statevector import statevector, amplitudes_sv, bit_index
 from .tn import (build_network, contract_network, amplitudes_tn,
-                 slice_values_tn, wire_labels)
+                 slice_values_tn, wire_labels, contract_ordered, slice_values_ordered)
 from .step import einsum_step, sampled_step
 from .metrics import normalized_error, linear_fidelity, per_slice_error
 
@@ -36,6 +37,7 @@ __all__ = [
     "gate_matrix", "H_M", "SQRT_X_M", "SQRT_Y_M", "SQRT_W_M", "fsim",
     "statevector", "amplitudes_sv", "bit_index",
     "build_network", "contract_network", "amplitudes_tn", "slice_values_tn",
+    "contract_ordered", "slice_values_ordered",
     "wire_labels", "einsum_step", "sampled_step",
     "normalized_error", "linear_fidelity", "per_slice_error",
 ]

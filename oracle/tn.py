@@ -194,6 +194,80 @@ def contract_network(tensors, out_labels):
     return np.transpose(res, order).reshape(-1) if order else np.asarray(res).reshape(1)
 
 
+def contract_ordered(tensors, out_labels, groups, pairs):
+    """Contract along an order given as data (the order changes rounding and
+    cost, never the value).
+
+    ``groups`` partitions the tensor indices; each group is first contracted
+    in its listed order and becomes node ``g``.  ``pairs`` then lists
+    contractions (a, b) of live nodes; the i-th pair creates node
+    ``len(groups) + i``.  A label shared by the two operands is summed when
+    no other live tensor carries it and it is not an output label.  Returns
+    the array over ``out_labels`` flattened as in ``contract_network``.
+    """
+    seen = sorted(i for g in groups for i in g)
+    if seen != list(range(len(tensors))):
+        raise ValueError("groups must partition the tensors")
+    live = {}
+    owners = {}
+    keep = set(out_labels)
+
+    def add(nid, arr, labs):
+        live[nid] = (arr, labs)
+        for lab in labs:
+            owners.setdefault(lab, set()).add(nid)
+
+    def drop(nid):
+        arr, labs = live.pop(nid)
+        for lab in labs:
+            owners[lab].discard(nid)
+        return arr, labs
+
+    def merge(x, y, nid):
+        ta, la = drop(x)
+        tb, lb = drop(y)
+        summed = [lab for lab in la if lab in lb and lab not in keep and not owners.get(lab)]
+        shared = [lab for lab in la if lab in lb]
+        if len(shared) != len(summed):
+            raise NotImplementedError("an index shared by three tensors")
+        tc = np.tensordot(ta, tb, axes=([la.index(x) for x in summed], [lb.index(x) for x in summed]))
+        add(nid, tc, [x for x in la if x not in summed] + [x for x in lb if x not in summed])
+
+    # Tensors are registered under temporary ids first so that the summation
+    # rule sees every tensor of the network.
+    for i, (a, l) in enumerate(tensors):
+        add(("t", i), np.asarray(a), list(l))
+    for g, members in enumerate(groups):
+        cur = ("t", members[0])
+        for j, i in enumerate(members[1:]):
+            nxt = ("g", g, j)
+            merge(cur, ("t", i), nxt)
+            cur = nxt
+        arr, labs = drop(cur)
+        add(g, arr, labs)
+    for i, (a, b) in enumerate(pairs):
+        merge(a, b, len(groups) + i)
+    ids = sorted(live, key=str)
+    res, rl = live[ids[0]]
+    for i in ids[1:]:
+        t, l = live[i]
+        res = np.tensordot(res, t, axes=0)
+        rl = rl + l
+    if sorted(rl) != sorted(out_labels):
+        raise RuntimeError("contraction left unexpected labels")
+    order = [rl.index(lab) for lab in reversed(out_labels)]
+    return np.transpose(res, order).reshape(-1) if order else np.asarray(res).reshape(1)
+
+
+def slice_values_ordered(circuit, open_qubits, closed_bits, sliced, slice_ids, groups, pairs):
+    """``slice_values_tn`` with the contraction order given as data."""
+    res = []
+    for sid in slice_ids:
+        tensors, out = build_network(circuit, open_qubits, closed_bits, sliced, int(sid))
+        res.append(contract_ordered(tensors, out, groups, pairs))
+    return np.array(res)
+
+
 def amplitudes_tn(circuit, open_qubits, closed_bits):
     """Amplitude batch by unsliced contraction (batch order as in the state
     vector oracle: open_qubits[0] is the least significant bit)."""

@@ -252,3 +252,62 @@ def test_metrics():
     assert oracle.linear_fidelity(np.array([1, 0]), np.array([0, 1])) == 0.0
     assert abs(oracle.per_slice_error(ref * 1.01, ref) -
                0.01 * np.max(np.abs(ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))) < 1e-15
+
+
+def _random_order(tensors, rng):
+    """A random grouping of the tensors and a random tree over the groups:
+    each pair is drawn among the three connected pairs with the fewest
+    result labels, so intermediates stay small."""
+    idx = list(rng.permutation(len(tensors)))
+    groups = []
+    while idx:
+        k = int(rng.integers(1, 4))
+        groups.append([int(i) for i in idx[:k]])
+        idx = idx[k:]
+    labels = {g: set(l for i in m for l in tensors[i][1]) for g, m in enumerate(groups)}
+    live = dict(labels)
+    pairs = []
+    nid = len(groups)
+    while len(live) > 1:
+        keys = list(live)
+        cand = sorted((len(live[a] ^ live[b]), a, b) for a in keys for b in keys
+                      if a < b and live[a] & live[b])
+        if cand:
+            _, a, b = cand[int(rng.integers(min(3, len(cand))))]
+        else:
+            a, b = keys[0], keys[1]
+        pairs.append((a, b))
+        live[nid] = live.pop(a) | live.pop(b)
+        nid += 1
+    return groups, pairs
+
+
+def test_contract_ordered_vs_statevector_random_trees():
+    """Any order given as data reaches the same amplitudes: random groupings
+    and random trees vs the state vector, with and without slicing."""
+    rng = np.random.default_rng(3)
+    c = rqcgen.grid_rqc(2, 3, 5, 8)
+    openq = [4, 5]
+    closed = rqcgen.random_bits(4, 2)
+    ref = oracle.amplitudes_sv(c, openq, closed)
+    for _ in range(4):
+        tensors, out = otn.build_network(c, openq, closed)
+        groups, pairs = _random_order(tensors, rng)
+        got = oracle.contract_ordered(tensors, out, groups, pairs)
+        assert np.max(np.abs(got - ref)) < 1e-14
+    wires = sorted(otn.wire_labels(c))
+    sliced = [wires[i] for i in rng.choice(len(wires), size=3, replace=False)]
+    tensors, _ = otn.build_network(c, openq, closed, sliced, 0)
+    groups, pairs = _random_order(tensors, rng)
+    vals = oracle.slice_values_ordered(c, openq, closed, sliced, range(8), groups, pairs)
+    assert np.max(np.abs(vals.sum(axis=0) - ref)) < 1e-14
+    for sid in (0, 6):
+        proj = {w: (sid >> j) & 1 for j, w in enumerate(sliced)}
+        assert np.max(np.abs(oracle.amplitudes_sv(c, openq, closed, proj) - vals[sid])) < 1e-14
+
+
+def test_contract_ordered_rejects_bad_groups():
+    c = rqcgen.grid_rqc(2, 2, 2, 1)
+    tensors, out = otn.build_network(c, [0], [0, 1, 1])
+    with pytest.raises(ValueError):
+        oracle.contract_ordered(tensors, out, [[0, 1]], [])
