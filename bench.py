@@ -35,10 +35,11 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", default="amplitudes",
-                    choices=["amplitudes", "steps", "kernel", "serve", "copy"],
+                    choices=["amplitudes", "steps", "kernel", "serve", "copy", "share"],
                     help="amplitudes: the sliced circuit contraction (default); steps: "
                          "synthetic rank-24..32 pairwise contractions, fused vs permute+GEMM; "
-                         "kernel: one plan-shaped contraction repeated")
+                         "kernel: one plan-shaped contraction repeated; share: one GPU's "
+                         "1024-slice share of a 10x10 (1+20+1) circuit in FP32, FP16, BF16")
     ap.add_argument("--mnk", default="15,10,13", help="kernel mode: m,n,k bits")
     ap.add_argument("--batch", type=int, default=8, help="kernel mode: copies per launch")
     ap.add_argument("--reps", type=int, default=5)
@@ -48,6 +49,13 @@ def parse():
     ap.add_argument("--requests", type=int, default=600, help="serve mode: Poisson requests")
     ap.add_argument("--load", type=float, default=0.8, help="serve mode: rate / saturation rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve mode: device pool")
+    ap.add_argument("--share-bound", type=int, default=28,
+                    help="share mode: per-slice bound, log2 elements")
+    ap.add_argument("--share-local", type=int, default=10,
+                    help="share mode: enumerated sliced wires (2^L slices)")
+    ap.add_argument("--share-trials", type=int, default=256)
+    ap.add_argument("--share-f32-parts", type=int, default=2,
+                    help="share mode: FP32 baseline calls (each prints a progress line)")
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
@@ -118,21 +126,28 @@ def _fidelity(a, ref):
     return float(num / (np.vdot(ref, ref).real * np.vdot(a, a).real))
 
 
+def kernel_source_hash(root):
+    """SHA-256 over the sources of the FP32 MFMA kernel and its headers."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_mfma32.hip", "kernels_dev.h", "kernels.h"):
+        h.update(open(os.path.join(root, "paper_2110_14502_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def _profile_traffic(name, flops_per_launch):
     """HBM bytes per launch of the dominant kernel from a committed counter
     summary, or None when the summary does not match: the kernel sources
     changed since the counters were taken, or its launches were different."""
-    import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
         text = open(os.path.join(root, "profiles", name)).read()
     except OSError:
         return None
     vals = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
-    src = os.path.join(root, "paper_2110_14502_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = kernel_source_hash(root)
     try:
-        if vals.get("kernels_hip_sha256") != sha:
+        if vals.get("kernel_source_sha256") != sha:
             return None
         if abs(float(vals["flops_per_launch"]) / flops_per_launch - 1) > 1e-6:
             return None
@@ -335,6 +350,102 @@ def serve_mode(a):
     print(json.dumps(out), flush=True)
 
 
+def share_mode(a):
+    """One GPU's share of a 10x10 (1+20+1) circuit: 2^L slices of a plan
+    whose other sliced wires are fixed, every intermediate within the bound.
+    FP16 and BF16 each run the whole share as one call (one graph launch of
+    every slice); the FP32 baseline runs the same slices in a few calls."""
+    import numpy as np
+    import torch
+    import rqcgen
+    import paper_2110_14502_amd as R
+
+    torch.cuda.set_device(0)
+    rows = cols = 10
+    depth, seed = 20, 4
+    n = rows * cols
+    circ = rqcgen.grid_rqc(rows, cols, depth, seed)
+    bits = rqcgen.random_bits(n, seed)
+    t = time.perf_counter()
+    plan = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), []), max_log2_elems=a.share_bound,
+                  path_trials=a.share_trials, seed=seed, n_local_sliced=a.share_local)
+    t_plan = time.perf_counter() - t
+    info = plan.info()
+    n_sl = info["n_slices"]
+    log(f"share plan: {t_plan:.1f}s, log2 flops/slice {math.log2(info['flops_per_slice']):.2f}, "
+        f"width {info['max_log2_elems']}, {n_sl} slices, {len(plan.fixed_wires())} fixed, "
+        f"{len(plan.pruned_wires())} pruned wires")
+    t = time.perf_counter()
+    plan.bind("cuda:0")
+    torch.cuda.synchronize()
+    t_bind = time.perf_counter() - t
+    free, _ = torch.cuda.mem_get_info()
+    lo, pref = plan.workspace_bytes(n_sl, 1, R.F32)
+    ws = torch.empty(int(min(pref, max(lo, a.ws_fraction * free))), dtype=torch.uint8, device="cuda:0")
+    share_flops = info["flops_per_slice"] * n_sl
+    checked = sorted(int(x) for x in np.random.default_rng(seed).choice(n_sl, 32, replace=False))
+    res = {"mode": "share", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"{rows}x{cols} grid RQC depth 1+{depth}+1, fSim(pi/2,pi/6) ABCDCDAB, "
+                                  f"circuit seed {seed}, one bitstring; share of {n_sl} slices "
+                                  f"({a.share_local} enumerated sliced wires, "
+                                  f"{len(plan.fixed_wires())} fixed), per-slice bound 2^{a.share_bound}",
+                      "plan_log2_flops_per_slice": math.log2(info["flops_per_slice"]),
+                      "plan_max_log2_elems": info["max_log2_elems"],
+                      "plan_seconds": round(t_plan, 2), "bind_seconds": round(t_bind, 2),
+                      "invariant_log2_flops": math.log2(info["flops_invariant"] + 1.0)},
+           "unit": "slices/s"}
+    vals = {}
+    for prec in ("f32", "f16", "bf16"):
+        pc = R.PRECISIONS[prec]
+        parts = a.share_f32_parts if prec == "f32" else 1
+        # Timed: the product path, each call one graph launch of its slices.
+        plan.set_timing(-1)
+        per_all = []
+        total_ms = 0.0
+        reruns = 0
+        for part in range(parts):
+            ids = list(range(part * n_sl // parts, (part + 1) * n_sl // parts))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, per = plan.contract(bits, slice_ids=ids, per_slice=True, prec=pc, workspace=ws)
+            torch.cuda.synchronize()
+            ms = 1000 * (time.perf_counter() - t0)
+            total_ms += ms
+            reruns += plan.last_report["fp32_reruns"]
+            per_all.append(R.to_complex(per)[:, 0, 0])
+            log(f"share {prec} part {part + 1}/{parts}: {ms / 1000:.1f}s "
+                f"(groups of {plan.last_report['slices_per_group']})")
+        vals[prec] = np.concatenate(per_all)
+        # MFMA rate: the same launches run directly with events around the
+        # matrix-core steps, on the first eighth of the slices.
+        plan.set_timing(1)
+        plan.contract(bits, slice_ids=list(range(max(1, n_sl // 8))), prec=pc, workspace=ws)
+        tim = plan.timing()
+        log(f"share {prec} MFMA probe: {tim['launches']} launches")
+        achieved = tim["flops"] / (tim["total_ms"] / 1000.0) / 1e12 if tim["total_ms"] > 0 else 0.0
+        peak = PEAK_MFMA_FP32 if prec == "f32" else PEAK_MFMA_16
+        res[prec] = {"seconds": total_ms / 1000, "slices_per_s": n_sl / (total_ms / 1000),
+                     "tflops": share_flops / (total_ms / 1000) / 1e12, "calls": parts,
+                     "fp32_reruns": reruns,
+                     "mfma": {"achieved_tflops": achieved, "peak": peak, "frac": achieved / peak,
+                              "launches": tim["launches"],
+                              "share_of_flops": tim["flops"] / (info["flops_per_slice"] * max(1, n_sl // 8))}}
+    plan.set_timing(-1)
+    for prec in ("f16", "bf16"):
+        ref, got = vals["f32"][checked], vals[prec][checked]
+        rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+        res[prec]["speedup_vs_f32"] = res["f32"]["seconds"] / res[prec]["seconds"]
+        res[prec]["per_slice_error_vs_f32"] = float(np.max(np.abs(got - ref)) / rms) if rms > 0 else None
+        res[prec]["fidelity_vs_f32"] = _fidelity(got, ref)
+    best = max(("f16", "bf16"), key=lambda p: res[p]["slices_per_s"])
+    res["metric"] = "share slices/s (reduced precision) and contraction TFLOP/s"
+    res["value"] = res[best]["slices_per_s"]
+    res["dtype"] = best
+    res["share_sum_f32"] = [float(vals["f32"].sum().real), float(vals["f32"].sum().imag)]
+    res["checked_slices"] = len(checked)
+    print(json.dumps(res), flush=True)
+
+
 def copy_mode(a):
     """A plain device copy of 1 GiB (calibration of the traffic counters)."""
     import torch
@@ -361,6 +472,8 @@ def main():
         return serve_mode(a)
     if a.mode == "copy":
         return copy_mode(a)
+    if a.mode == "share":
+        return share_mode(a)
     import numpy as np
     import torch
     import rqcgen

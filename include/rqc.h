@@ -123,6 +123,18 @@ typedef struct rqc_plan_opts {
                              0 = default (14) */
   int32_t bf16_min_log2;  /* the same for RQC_BF16, whose 8-bit significand
                              rounds more per stored stage; 0 = default (24) */
+  /* Slice share (Section 5.1: slices are independent sub-tasks, so a device
+   * can own a contiguous range of them).  0: every sliced wire is enumerated
+   * by the slice ids of rqc_contract (at most 62 wires).  L > 0: only the
+   * first L sliced wires (slice bits 0..L-1, L <= 62) are enumerated; sliced
+   * wire L+i is fixed to share_bits[i] (0 for i >= n_share_bits), so the
+   * plan computes the 2^L slices whose high slice bits are share_bits.  Every
+   * subtree that carries only fixed wires is contracted once at bind.  With
+   * a share the full slicing may have more than 62 wires.  share_bits is
+   * read during rqc_plan_create only. */
+  int32_t n_local_sliced;
+  int32_t n_share_bits;
+  const uint8_t* share_bits;
 } rqc_plan_opts;
 
 void rqc_plan_opts_default(rqc_plan_opts* o);

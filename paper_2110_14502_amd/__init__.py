@@ -46,7 +46,8 @@ class rqc_plan_opts(C.Structure):
                 ("path_trials", C.c_int32), ("reconf_rounds", C.c_int32),
                 ("seed", C.c_uint64), ("n_forced", C.c_int32),
                 ("forced_wires", C.POINTER(C.c_int32)), ("lp_min_log2", C.c_int32),
-                ("bf16_min_log2", C.c_int32)]
+                ("bf16_min_log2", C.c_int32), ("n_local_sliced", C.c_int32),
+                ("n_share_bits", C.c_int32), ("share_bits", C.POINTER(C.c_uint8))]
 
 
 class rqc_plan_info(C.Structure):
@@ -229,7 +230,8 @@ class Plan:
     """Contraction path + slicing plan, optionally bound to device memory."""
 
     def __init__(self, network: Network, max_log2_elems=0, n_sliced=-1, path_trials=256,
-                 reconf_rounds=-1, seed=0, forced_wires=(), lp_min_log2=0, bf16_min_log2=0):
+                 reconf_rounds=-1, seed=0, forced_wires=(), lp_min_log2=0, bf16_min_log2=0,
+                 n_local_sliced=0, share_bits=()):
         o = rqc_plan_opts()
         _lib.rqc_plan_opts_default(C.byref(o))
         o.max_log2_elems = int(max_log2_elems)
@@ -243,6 +245,10 @@ class Plan:
         o.forced_wires = C.cast(self._forced, C.POINTER(C.c_int32))
         o.lp_min_log2 = int(lp_min_log2)
         o.bf16_min_log2 = int(bf16_min_log2)
+        o.n_local_sliced = int(n_local_sliced)
+        self._share = (C.c_uint8 * max(1, len(share_bits)))(*[int(b) for b in share_bits])
+        o.n_share_bits = len(share_bits)
+        o.share_bits = C.cast(self._share, C.POINTER(C.c_uint8))
         h = C.c_void_p()
         _check(_lib.rqc_plan_create(network.h, C.byref(o), C.byref(h)))
         self.h = h
@@ -278,7 +284,18 @@ class Plan:
         return json.loads(buf.value.decode())
 
     def sliced_wires(self):
+        """Enumerated sliced wires (q, segment), slice-bit order."""
         return [tuple(w) for w in self.export()["sliced_wires"]]
+
+    def pruned_wires(self):
+        """Wires that carry a single value (a zero slab in a leaf), projected
+        out before planning: (q, segment, value)."""
+        return [tuple(w) for w in self.export()["pruned_wires"]]
+
+    def fixed_wires(self):
+        """Sliced wires fixed by the slice share: (q, segment, value), in
+        slice-bit order after the enumerated ones."""
+        return [tuple(w) for w in self.export()["fixed_wires"]]
 
     def resident_bytes(self) -> int:
         b = C.c_size_t()

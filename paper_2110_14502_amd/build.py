@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librqc.so")
 
-SOURCES = ["kernels.hip", "network.cpp", "planner.cpp", "executor.cpp", "capi.cpp", "server.cpp"]
+SOURCES = ["k_mfma32.hip", "k_mfma16.hip", "k_rows.hip", "k_simt.hip", "kernels.hip", "network.cpp", "planner.cpp", "executor.cpp", "capi.cpp", "server.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-I" + INCLUDE, "-I" + CSRC]
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -124,6 +124,8 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_
   if (o.max_log2_elems < 0 || o.max_log2_elems > 40) throw rqc::Error{RQC_EINVAL, "max_log2_elems out of range"};
   if (o.n_sliced < -1) throw rqc::Error{RQC_EINVAL, "n_sliced < -1"};
   if (o.n_forced < 0 || (o.n_forced && !o.forced_wires)) throw rqc::Error{RQC_EINVAL, "forced wires"};
+  if (o.n_local_sliced < 0 || o.n_local_sliced > 62) throw rqc::Error{RQC_EINVAL, "n_local_sliced out of range"};
+  if (o.n_share_bits < 0 || (o.n_share_bits && !o.share_bits)) throw rqc::Error{RQC_EINVAL, "share bits"};
   auto* p = new rqc_plan;
   try {
     p->pd.net = n->n;
@@ -136,6 +138,10 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_
     for (int i = 0; i < o.n_forced; ++i) po.forced.push_back({o.forced_wires[2 * i], o.forced_wires[2 * i + 1]});
     po.lp_min_log2 = o.lp_min_log2 > 0 ? o.lp_min_log2 : 14;
     po.bf16_min_log2 = o.bf16_min_log2 > 0 ? o.bf16_min_log2 : 24;
+    po.n_local = o.n_local_sliced;
+    po.share_bits.assign(o.share_bits, o.share_bits + o.n_share_bits);
+    for (auto& b : po.share_bits)
+      if (b > 1) throw rqc::Error{RQC_EINVAL, "share bits must be 0 or 1"};
     rqc::make_plan(p->pd);
     rqc::resident_bytes(p);
   } catch (...) {

@@ -88,6 +88,8 @@ struct PlanOpts {
   std::vector<std::pair<int, int>> forced;
   int lp_min_log2 = 14;
   int bf16_min_log2 = 24;
+  int n_local = 0;            // 0: all sliced wires enumerated by slice ids
+  std::vector<uint8_t> share_bits;  // values of the fixed sliced wires
 };
 
 struct Tree {
@@ -122,7 +124,8 @@ struct PlanData {
   Network net;
   PlanOpts opts;
   Tree tree;
-  std::vector<int> sliced;              // sliced wire labels, slice-bit order
+  std::vector<int> sliced;              // enumerated sliced wire labels, slice-bit order
+  std::vector<std::pair<int, int>> fixed;  // sliced wires fixed by the share: (label, value)
   std::vector<std::vector<int>> node_labels;  // contracted labels per node
   std::vector<int> node_layout_dummy;
   std::vector<std::vector<int>> layout; // per node: chosen layout
@@ -134,6 +137,7 @@ struct PlanData {
   double flops_per_slice = 0;
   double bytes_per_slice = 0;
   int max_log2 = 0;
+  std::vector<std::pair<int, int>> pruned;  // single-valued wires projected out: (label, value)
 };
 
 // Builds everything in PlanData from the network and options.

@@ -237,6 +237,8 @@ size_t resident_bytes(rqc_plan* p) {
   }
   p->inv_max_off = off;
   off = align256(off + 4 * (int64_t)nn);
+  p->inv_exp_off = off;
+  off = align256(off + 4 * (int64_t)nn);
   p->inv_bytes = off;
   p->tmpl.clear();
   p->kern.clear();
@@ -288,6 +290,9 @@ void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
   }
   hip_check(hipMemcpyAsync(base + p->inv_max_off, maxes.data(), 4 * nn, hipMemcpyHostToDevice, s),
             "upload maxima");
+  const std::vector<int32_t> zeros(nn, 0);
+  hip_check(hipMemcpyAsync(base + p->inv_exp_off, zeros.data(), 4 * nn, hipMemcpyHostToDevice, s),
+            "upload exponents");
   // Slice-invariant subtrees: contracted once, kept resident.
   for (const Step& st : pd.steps) {
     if (!st.invariant) continue;
@@ -298,9 +303,13 @@ void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
     d.B = base + p->inv_off[st.b];
     d.C = base + p->inv_off[st.node];
     float* mx = reinterpret_cast<float*>(base + p->inv_max_off);
+    int32_t* ex = reinterpret_cast<int32_t*>(base + p->inv_exp_off);
     d.maxA = mx + st.a;
     d.maxB = mx + st.b;
     d.maxC = mx + st.node;
+    d.expA = ex + st.a;
+    d.expB = ex + st.b;
+    d.expC = ex + st.node;
     d.track = 1;
     d.lp_out = 0;
     d.copies = 1;
@@ -327,7 +336,10 @@ static GroupLayout compute_layout(rqc_plan* p, int prec, int gs, int gb) {
   L.gs = gs;
   L.gb = gb;
   L.place.assign(nn, Placement());
-  const bool track = prec != RQC_F32;
+  // Exponents and maxima are kept in every precision (complex64 outputs are
+  // normalised too); 16-bit storage only in reduced precision.
+  const bool track = true;
+  const bool lp_mode = prec != RQC_F32;
   const int lp_store = prec == RQC_F16 ? ST_F16 : ST_BF16;
   std::vector<int64_t> bytes(nn, 0);
   for (int v = 0; v < nn; ++v) {
@@ -342,12 +354,13 @@ static GroupLayout compute_layout(rqc_plan* p, int prec, int gs, int gb) {
       P.off = p->inv_off[v];
       P.store = ST_C64;
       if (v >= nl) P.m_off = p->inv_max_off + 4 * v;
+      P.e_off = p->inv_exp_off + 4 * v;
       continue;
     }
     const int cs = P.dep_s ? gs : 1, cb = P.dep_b ? gb : 1;
     const Step& ps = pd.steps[v >= nl ? pd.step_of_node[v] : 0];
     const bool lp16 = v >= nl && (prec == RQC_BF16 ? ps.lp_bf16 : ps.lp);
-    P.store = (track && lp16) ? lp_store : ST_C64;
+    P.store = (lp_mode && lp16) ? lp_store : ST_C64;
     P.s_stride = P.dep_s ? E : 0;
     P.b_stride = P.dep_b ? E * cs : 0;
     bytes[v] = align256(E * cs * cb * elsize(P.store));
@@ -486,7 +499,8 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
                         uint64_t n_batch, char* ws, double* out, double* per_slice,
                         int64_t ps_row0, hipStream_t s) {
   PlanData& pd = p->pd;
-  const bool track = L.prec != RQC_F32;
+  const bool track = true;                  // exponents in every precision
+  const bool lp_mode = L.prec != RQC_F32;   // slice flags drive FP32 re-runs
   char* arena = ws + W.arena_off;
   char* scale = ws + W.scale_off;
   int32_t* flags = reinterpret_cast<int32_t*>(ws + W.flags_off);
@@ -497,7 +511,8 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
   const int n_elems = 1 << pd.net.open.size();
   auto ptr = [&](const Placement& P) -> char* { return P.resident ? p->res + P.off : arena + P.off; };
   auto eptr = [&](const Placement& P) -> int32_t* {
-    return P.e_off >= 0 ? reinterpret_cast<int32_t*>(scale + P.e_off) : nullptr;
+    if (P.e_off < 0) return nullptr;
+    return reinterpret_cast<int32_t*>(P.resident ? p->res + P.e_off : scale + P.e_off);
   };
   auto mptr = [&](const Placement& P) -> float* {
     if (P.m_off < 0) return nullptr;
@@ -579,7 +594,7 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
       const int root = pd.tree.root;
       const Placement& R = L.place[root];
       hip_check(launch_slice_sum(ptr(R), R.store, eptr(R), R.s_stride, R.b_stride, R.es, R.eb,
-                                 R.dep_s, R.dep_b, n_elems, gsc, gbc, track ? flags + g0 : nullptr,
+                                 R.dep_s, R.dep_b, n_elems, gsc, gbc, lp_mode ? flags + g0 : nullptr,
                                  out, per_slice, ps_row0 + (int64_t)g0, (int64_t)n_batch,
                                  (int64_t)b0, g0 == 0 ? 1 : 0, s),
                 "slice sum");
@@ -724,10 +739,6 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
   rep->bits_per_group = r.gb;
   rep->graph_reused = r.graph_reused;
   rep->flops = r.flops;
-  if (r.prec == RQC_F32) {
-    r.active = false;
-    return;
-  }
   const GroupLayout& L0 = group_layout(p, r.prec, r.gs, r.gb);
   const WsLayout W0 = ws_layout(p, L0, r.n_ids, r.n_batch);
   std::vector<int32_t> flags(r.n_ids);
@@ -737,6 +748,9 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
     if (flags[i]) redo.push_back(i);
   r.active = false;
   if (redo.empty()) return;
+  // With normalised complex64 storage a non-finite FP32 value can only come
+  // from non-finite inputs.
+  if (r.prec == RQC_F32) throw Error{RQC_ENUMERIC, "non-finite values in the FP32 contraction"};
   // Filter of Section 5.5, re-read: a slice whose reduced-precision result is
   // not finite is contracted again in FP32 instead of being discarded.
   int gb = (int)std::min<uint64_t>(r.n_batch, 4096);

@@ -81,6 +81,7 @@ struct rqc_plan {
   std::vector<float> leaf_max;          // per leaf
   std::vector<int64_t> inv_off;         // per node: bytes in resident, -1
   int64_t inv_max_off = 0;              // bytes: float per node
+  int64_t inv_exp_off = 0;              // bytes: int32 exponent per node
   int64_t inv_bytes = 0;
   int scale_bias = 0;
   // Per-step descriptor templates (layout only) and chosen kernels.

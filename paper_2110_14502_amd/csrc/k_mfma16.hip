@@ -1,0 +1,276 @@
+// FP16 / BF16 matrix-core contraction kernel (reduced precision).
+#include "kernels_dev.h"
+
+namespace rqc {
+
+// ---------------------------------------------------------------------------
+// Reduced-precision MFMA contraction (FP16 / BF16 matrix cores,
+// v_mfma_f32_32x32x16_{f16,bf16}, FP32 accumulation).  Same tiling as the
+// FP32 kernel (128 rows x 64 complex columns, 4 waves 2x2) with 32 complex
+// k per LDS chunk.  Operands live in LDS as packed complex words (re in the
+// low half, im in the high half), k contiguous: a lane's 8 consecutive real
+// k of A_r are one 16-byte read; for B_r the lane reads 4 complex values of
+// its column and forms (re, -im) by a sign flip (column parity 0) or
+// (im, re) by swapping the halves (parity 1).  An operand stored in
+// complex64 is converted with a per-copy power-of-two pre-scale that maps
+// its max-abs to 2^14; the output exponent undoes it.
+// ---------------------------------------------------------------------------
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLTK = 32;                 // complex k per chunk
+constexpr int kLRow = kLTK + 4;          // words per LDS row (16-byte aligned)
+constexpr int kLABuf = kTM * kLRow;      // words per A buffer
+constexpr int kLBBuf = kTN * kLRow;      // words per B buffer
+constexpr int kLMainWords = 2 * kLABuf + 2 * kLBBuf;
+static_assert(kCHalf + kTabFloats <= kLMainWords, "C staging must fit the operand buffers");
+
+template <int LP>
+__device__ __forceinline__ uint32_t pack_lp(float2 v);
+template <>
+__device__ __forceinline__ uint32_t pack_lp<ST_F16>(float2 v) {
+  h2 o;
+  o.x = (_Float16)v.x;
+  o.y = (_Float16)v.y;
+  return __builtin_bit_cast(uint32_t, o);
+}
+template <>
+__device__ __forceinline__ uint32_t pack_lp<ST_BF16>(float2 v) {
+  b2 o;
+  o.x = (__bf16)v.x;
+  o.y = (__bf16)v.y;
+  return __builtin_bit_cast(uint32_t, o);
+}
+
+// Load one operand element as a packed low-precision complex word.
+template <int LP, int S>
+__device__ __forceinline__ uint32_t load_lp(const void* p, int64_t i, int pre) {
+  if (S == LP) return reinterpret_cast<const uint32_t*>(p)[i];
+  float2 v = load_c<S>(p, i);
+  if (pre) {
+    v.x = ldexpf(v.x, pre);
+    v.y = ldexpf(v.y, pre);
+  }
+  return pack_lp<LP>(v);
+}
+
+template <int LP>
+__device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c);
+template <>
+__device__ __forceinline__ floatx16 mfma16<ST_F16>(u32x4 a, u32x4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(halfx8, a),
+                                                __builtin_bit_cast(halfx8, b), c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ floatx16 mfma16<ST_BF16>(u32x4 a, u32x4 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// B_r words of a lane from four packed complex values of its column.
+__device__ __forceinline__ u32x4 expand_b(u32x4 w, bool swap_halves) {
+  u32x4 o;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    o[i] = swap_halves ? ((w[i] >> 16) | (w[i] << 16)) : (w[i] ^ 0x80000000u);
+  return o;
+}
+
+template <int LP, int SA, int SB, int SC>
+__global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
+  __shared__ __attribute__((aligned(16))) uint32_t lw[kLMainWords + 16];
+  uint32_t* Abuf = lw;                  // [2][kTM][kLRow]
+  uint32_t* Bbuf = lw + 2 * kLABuf;     // [2][kTN][kLRow]
+  float* lds = reinterpret_cast<float*>(lw);
+  float* red = lds + kLMainWords;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  uint64_t bid = blockIdx.x;
+  const uint64_t nblk = gridDim.x;
+  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+  const uint64_t no = bid % (uint64_t)d.n_col_tiles;
+  const uint64_t ro = bid / (uint64_t)d.n_col_tiles;
+
+  // A chunk tile: 128 rows x 32 k (4096 elements, 16 per thread); B chunk
+  // tile: 32 k x 64 columns (2048, 8 per thread).
+  int64_t gA[16];
+  int lA[16];
+  int64_t gB[8];
+  int lB[8];
+  {
+    TileTab* ta = reinterpret_cast<TileTab*>(lds);
+    TileTab* tb = ta + 1;
+    build_tab(d.tA, kLRow, 0, 1, *ta);
+    build_tab(d.tB, 0, kLRow, 1, *tb);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      gA[j] = ta->g[lane] + ta->g[64 + wave + 4 * j];
+      lA[j] = ta->c[lane] + ta->c[64 + wave + 4 * j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      gB[j] = tb->g[lane] + tb->g[64 + wave + 4 * j];
+      lB[j] = tb->c[lane] + tb->c[64 + wave + 4 * j];
+    }
+  }
+  int hb = 0;
+  for (int b = 0; b < d.tC.nbits; ++b)
+    if (d.tC.role[b] == 0 && d.tC.cbit[b] == 6) hb = b;
+  const int64_t g_half = int64_t(1) << d.tC.gpos[hb];
+
+  const int lrow = lane & 31;
+  const int kq = (lane >> 5) * 4;      // first complex k of the lane's 8 real k
+  const int ncol = (lane & 31) >> 1;
+  const bool bswap = (lane & 1) != 0;  // C_r column parity 1: (im, re)
+
+  const int n_kc = 1 << d.n_ko;
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    // Pre-scales of complex64 operands and the output scale.
+    const float mA = d.maxA ? d.maxA[js * d.eA_s + jb * d.eA_b] : d.maxA_const;
+    const float mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
+    const int EA = mA > 0.f ? ceil_log2(mA) : 0, EB = mB > 0.f ? ceil_log2(mB) : 0;
+    const int pA = (SA == LP || mA <= 0.f) ? 0 : 14 - EA;
+    const int pB = (SB == LP || mB <= 0.f) ? 0 : 14 - EB;
+    // The accumulator holds the product times 2^(pA+pB); the output shift
+    // maps the bound to the storage target (as in compute_scale).
+    Scale sc{pA + pB, 0};
+    {
+      const int eA = (d.track && d.expA) ? d.expA[js * d.eA_s + jb * d.eA_b] : 0;
+      const int eB = (d.track && d.expB) ? d.expB[js * d.eB_s + jb * d.eB_b] : 0;
+      sc.expC = eA + eB;
+      if (d.track && mA > 0.f && mB > 0.f && mA <= 3.0e38f && mB <= 3.0e38f) {
+        const int t = d.k_total + 1 + (EA + pA) + (EB + pB) - target_log2(d);
+        sc.shift = t;
+        sc.expC = eA - pA + eB - pB + t;
+      }
+    }
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    uint32_t ra[16], rb[8];
+    {
+      int64_t kA, kB;
+      k_offsets(d, 0, kA, kB);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) Abuf[lA[j]] = ra[j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Bbuf[lB[j]] = rb[j];
+    __syncthreads();
+
+    for (int kc = 0; kc < n_kc; ++kc) {
+      const int cur = kc & 1;
+      const bool more = kc + 1 < n_kc;
+      if (more) {
+        int64_t kA, kB;
+        k_offsets(d, kc + 1, kA, kB);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
+      }
+      const uint32_t* As = Abuf + cur * kLABuf + (wm * 64 + lrow) * kLRow + kq;
+      const uint32_t* Bs = Bbuf + cur * kLBBuf + (wn * 32 + ncol) * kLRow + kq;
+#pragma unroll
+      for (int kk = 0; kk < kLTK / 8; ++kk) {
+        const u32x4 a0 = *reinterpret_cast<const u32x4*>(As + kk * 8);
+        const u32x4 a1 = *reinterpret_cast<const u32x4*>(As + 32 * kLRow + kk * 8);
+        const u32x4 b0 = expand_b(*reinterpret_cast<const u32x4*>(Bs + kk * 8), bswap);
+        const u32x4 b1 = expand_b(*reinterpret_cast<const u32x4*>(Bs + 16 * kLRow + kk * 8), bswap);
+        acc[0][0] = mfma16<LP>(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16<LP>(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16<LP>(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16<LP>(a1, b1, acc[1][1]);
+      }
+      if (more) {
+        uint32_t* An = Abuf + (cur ^ 1) * kLABuf;
+        uint32_t* Bn = Bbuf + (cur ^ 1) * kLBBuf;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) An[lA[j]] = ra[j];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) Bn[lB[j]] = rb[j];
+      }
+      __syncthreads();
+    }
+
+    float* Cs = lds;
+    TileTab* tcs = reinterpret_cast<TileTab*>(lds + kCHalf);
+    build_tab_skip(d.tC, hb, kCStride, 2, *tcs);
+    float lmax = 0.f;
+    int bad = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (wm == h) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+              const int col = wn * 64 + j * 32 + (lane & 31);
+              Cs[row * kCStride + col] = acc[i][j][r];
+            }
+      }
+      __syncthreads();
+      const int64_t gl = tcs->g[lane] + (h ? g_half : 0);
+      const int32_t cl = tcs->c[lane];
+#pragma unroll 4
+      for (int j = 0; j < 16; ++j) {
+        const int hi = 64 + wave + 4 * j;
+        const int c = cl + tcs->c[hi];
+        const int64_t at = oC + gl + tcs->g[hi];
+        store_out<SC>(d, at, make_float2(Cs[c], Cs[c + 1]), sc, lmax, bad);
+      }
+      __syncthreads();
+    }
+    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
+    __syncthreads();
+  }
+}
+
+template <int LP>
+static hipError_t launch_mfma16(const StepDesc& d, int sa, int sb, int sc, dim3 grid,
+                                hipStream_t s) {
+  constexpr int C = ST_C64;
+#define RQC_LP_CASE(a, b, c)                                                        \
+  if (sa == a && sb == b && sc == c) {                                              \
+    hipLaunchKernelGGL((k_mfma16<LP, a, b, c>), grid, dim3(256), 0, s, d);         \
+    return hipGetLastError();                                                       \
+  }
+  RQC_LP_CASE(LP, LP, LP)
+  RQC_LP_CASE(LP, LP, C)
+  RQC_LP_CASE(LP, C, LP)
+  RQC_LP_CASE(LP, C, C)
+  RQC_LP_CASE(C, LP, LP)
+  RQC_LP_CASE(C, LP, C)
+  RQC_LP_CASE(C, C, LP)
+  RQC_LP_CASE(C, C, C)
+#undef RQC_LP_CASE
+  return hipErrorInvalidValue;
+}
+hipError_t launch_mfma16_kernel(const StepDesc& d, int sa, int sb, int sc, int lp_kind, dim3 grid,
+                                hipStream_t s) {
+  if (d.rt != 7 || d.nt != 6 || d.kt != 5) return hipErrorInvalidValue;
+  if (lp_kind == ST_F16) return launch_mfma16<ST_F16>(d, sa, sb, sc, grid, s);
+  if (lp_kind == ST_BF16) return launch_mfma16<ST_BF16>(d, sa, sb, sc, grid, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rqc

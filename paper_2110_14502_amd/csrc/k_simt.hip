@@ -1,0 +1,187 @@
+// Generic table-driven SIMT contraction kernel and its split-K reduction.
+#include "kernels_dev.h"
+
+namespace rqc {
+
+// ---------------------------------------------------------------------------
+// Generic SIMT contraction (any layouts, any sizes): tiles of R rows x N
+// columns, K in chunks; loads follow each operand's address order through
+// the offset tables; optional split-K into partial buffers.
+// ---------------------------------------------------------------------------
+constexpr int kSimtBlock = 256;
+constexpr int kSimtMaxC = 8;  // C tile <= 2048 elements
+
+template <int SA, int SB, int SC>
+__global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
+  extern __shared__ float2 smem2[];
+  __shared__ TileTab ta, tb, tcc;
+  __shared__ float red[16];
+  const int R = 1 << d.rt, N = 1 << d.nt, K = 1 << d.kt;
+  const int ldA = K + 1, ldB = N + 1;
+  float2* As = smem2;
+  float2* Bs = As + R * ldA;
+  const int tid = threadIdx.x, lane = tid & 63;
+  build_tab(d.tA, ldA, 0, 1, ta);
+  build_tab(d.tB, 0, 1, ldB, tb);
+  build_tab(d.tC, 4096, 1, 0, tcc);  // coordinate = row * 4096 + col
+  const uint64_t tiles = (uint64_t)d.n_row_tiles * (uint64_t)d.n_col_tiles;
+  const uint64_t split = blockIdx.x / tiles;
+  const uint64_t tile = blockIdx.x % tiles;
+  const uint64_t ro = tile % (uint64_t)d.n_row_tiles;
+  const uint64_t no = tile / (uint64_t)d.n_row_tiles;
+  const int nC = R * N;
+  const int nA = R * K, nB = K * N;
+  const int n_kc_all = 1 << d.n_ko;
+  const int n_kc = n_kc_all >> d.ksplit;
+  const int kc0 = (int)split * n_kc;
+  __syncthreads();
+  // Owned C elements, C address order: global offset and (row, col).
+  int64_t cg[kSimtMaxC];
+  int crow[kSimtMaxC], ccol[kSimtMaxC];
+  const int64_t glo = tcc.g[lane];
+  const int32_t clo = tcc.c[lane];
+#pragma unroll
+  for (int i = 0; i < kSimtMaxC; ++i) {
+    const int e = tid + i * kSimtBlock;
+    const int hi = 64 + (e >> 6);
+    const int ee = e < nC ? hi : 64;
+    cg[i] = glo + tcc.g[ee];
+    const int c = clo + tcc.c[ee];
+    crow[i] = c >> 12;
+    ccol[i] = c & 4095;
+  }
+  const int64_t gAlo = ta.g[lane], gBlo = tb.g[lane];
+  const int32_t cAlo = ta.c[lane], cBlo = tb.c[lane];
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    float2 acc[kSimtMaxC];
+#pragma unroll
+    for (int i = 0; i < kSimtMaxC; ++i) acc[i] = make_float2(0.f, 0.f);
+    for (int kc = kc0; kc < kc0 + n_kc; ++kc) {
+      int64_t kA, kB;
+      k_offsets(d, kc, kA, kB);
+      for (int e = tid; e < nA; e += kSimtBlock) {
+        const int hi = 64 + (e >> 6);
+        As[cAlo + ta.c[hi]] = load_c<SA>(d.A, oA + kA + gAlo + ta.g[hi]);
+      }
+      for (int e = tid; e < nB; e += kSimtBlock) {
+        const int hi = 64 + (e >> 6);
+        Bs[cBlo + tb.c[hi]] = load_c<SB>(d.B, oB + kB + gBlo + tb.g[hi]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kSimtMaxC; ++i) {
+        if (tid + i * kSimtBlock < nC) {
+          const float2* ar = As + crow[i] * ldA;
+          const float2* bc = Bs + ccol[i];
+          float sx = acc[i].x, sy = acc[i].y;
+          for (int k = 0; k < K; ++k) {
+            const float2 a = ar[k], b = bc[k * ldB];
+            sx = fmaf(a.x, b.x, sx);
+            sx = fmaf(-a.y, b.y, sx);
+            sy = fmaf(a.x, b.y, sy);
+            sy = fmaf(a.y, b.x, sy);
+          }
+          acc[i] = make_float2(sx, sy);
+        }
+      }
+      __syncthreads();
+    }
+    if (d.ksplit) {
+      // Partial sums: plain complex64, reduced by k_splitk_reduce.
+      float2* P = d.P + (int64_t)split * d.p_stride;
+#pragma unroll
+      for (int i = 0; i < kSimtMaxC; ++i)
+        if (tid + i * kSimtBlock < nC) P[oC + cg[i]] = acc[i];
+      continue;
+    }
+    const Scale sc = compute_scale(d, js, jb);
+    float lmax = 0.f;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < kSimtMaxC; ++i)
+      if (tid + i * kSimtBlock < nC) store_out<SC>(d, oC + cg[i], acc[i], sc, lmax, bad);
+    finish_scale<kSimtBlock>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
+  }
+}
+
+// Split-K reduction: C = sum over splits of the partial buffers, in split
+// order, then the usual scale / store / tracking epilogue.  One workgroup
+// per (row tile, column tile) of C and copy, elements in C address order.
+template <int SC>
+__global__ __launch_bounds__(256) void k_splitk_reduce(StepDesc d) {
+  __shared__ TileTab tcc;
+  __shared__ float red[16];
+  const int tid = threadIdx.x;
+  build_tab(d.tC, 0, 0, 0, tcc);
+  const uint64_t ro = blockIdx.x % (uint64_t)d.n_row_tiles;
+  const uint64_t no = blockIdx.x / (uint64_t)d.n_row_tiles;
+  const int nC = 1 << (d.rt + d.nt);
+  const int ns = 1 << d.ksplit;
+  __syncthreads();
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    const Scale sc = compute_scale(d, js, jb);
+    float lmax = 0.f;
+    int bad = 0;
+    for (int e = tid; e < nC; e += 256) {
+      const int64_t at = oC + tcc.g[e & 63] + tcc.g[64 + (e >> 6)];
+      float sx = 0.f, sy = 0.f;
+      for (int s = 0; s < ns; ++s) {
+        const float2 v = d.P[(int64_t)s * d.p_stride + at];
+        sx += v.x;
+        sy += v.y;
+      }
+      store_out<SC>(d, at, make_float2(sx, sy), sc, lmax, bad);
+    }
+    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
+  }
+}
+
+#define RQC_SIMT_CASE(a, b, c)                                                         \
+  if (sa == a && sb == b && sc == c) {                                                 \
+    hipLaunchKernelGGL((k_simt<a, b, c>), grid, dim3(kSimtBlock), lds, s, d);         \
+    e = hipGetLastError();                                                             \
+    goto reduce;                                                                       \
+  }
+
+hipError_t launch_simt_kernel(const StepDesc& d, int sa, int sb, int sc, uint64_t tiles,
+                              hipStream_t s) {
+  const unsigned gy = (unsigned)(d.copies < 65535 ? d.copies : 65535);
+  dim3 grid((unsigned)(tiles << d.ksplit), gy);
+  hipError_t e = hipSuccess;
+  {
+    const size_t lds = sizeof(float2) * ((size_t)(1 << d.rt) * ((1 << d.kt) + 1) +
+                                         (size_t)(1 << d.kt) * ((1 << d.nt) + 1));
+    RQC_SIMT_CASE(ST_C64, ST_C64, ST_C64)
+    RQC_SIMT_CASE(ST_C64, ST_C64, ST_F16)
+    RQC_SIMT_CASE(ST_C64, ST_C64, ST_BF16)
+    RQC_SIMT_CASE(ST_F16, ST_C64, ST_F16)
+    RQC_SIMT_CASE(ST_F16, ST_C64, ST_C64)
+    RQC_SIMT_CASE(ST_BF16, ST_C64, ST_BF16)
+    RQC_SIMT_CASE(ST_BF16, ST_C64, ST_C64)
+    RQC_SIMT_CASE(ST_C64, ST_F16, ST_F16)
+    RQC_SIMT_CASE(ST_C64, ST_F16, ST_C64)
+    RQC_SIMT_CASE(ST_C64, ST_BF16, ST_BF16)
+    RQC_SIMT_CASE(ST_C64, ST_BF16, ST_C64)
+    RQC_SIMT_CASE(ST_F16, ST_F16, ST_F16)
+    RQC_SIMT_CASE(ST_F16, ST_F16, ST_C64)
+    RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_BF16)
+    RQC_SIMT_CASE(ST_BF16, ST_BF16, ST_C64)
+    return hipErrorInvalidValue;
+  }
+reduce:
+  if (e != hipSuccess || d.ksplit == 0) return e;
+  grid.x = (unsigned)tiles;
+  if (sc == ST_F16) hipLaunchKernelGGL(k_splitk_reduce<ST_F16>, grid, dim3(256), 0, s, d);
+  else if (sc == ST_BF16) hipLaunchKernelGGL(k_splitk_reduce<ST_BF16>, grid, dim3(256), 0, s, d);
+  else hipLaunchKernelGGL(k_splitk_reduce<ST_C64>, grid, dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+#undef RQC_SIMT_CASE
+
+}  // namespace rqc

@@ -1,0 +1,283 @@
+// Device-side helpers shared by the contraction kernels: storage types,
+// per-copy power-of-two scaling, offset tables and tile constants.
+//
+// Complex arithmetic on the real matrix cores: an interleaved complex
+// A[m][k] is read as the real matrix A_r[m][2k+c] (c = 0 re, 1 im); the
+// complex B[k][n] is expanded per lane into the real 2x2 block
+//   B_r[2k+0][2n+0] = Br   B_r[2k+0][2n+1] = Bi
+//   B_r[2k+1][2n+0] = -Bi  B_r[2k+1][2n+1] = Br
+// so that A_r * B_r is exactly the interleaved complex C[m][2n+d].  The real
+// flops executed equal 8 per complex multiply-add, the algorithmic count.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace rqc {
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// Storage helpers
+// ---------------------------------------------------------------------------
+template <int S>
+__device__ __forceinline__ float2 load_c(const void* p, int64_t i);
+template <>
+__device__ __forceinline__ float2 load_c<ST_C64>(const void* p, int64_t i) {
+  return reinterpret_cast<const float2*>(p)[i];
+}
+template <>
+__device__ __forceinline__ float2 load_c<ST_F16>(const void* p, int64_t i) {
+  h2 v = reinterpret_cast<const h2*>(p)[i];
+  return make_float2((float)v.x, (float)v.y);
+}
+template <>
+__device__ __forceinline__ float2 load_c<ST_BF16>(const void* p, int64_t i) {
+  b2 v = reinterpret_cast<const b2*>(p)[i];
+  return make_float2((float)v.x, (float)v.y);
+}
+
+template <int S>
+__device__ __forceinline__ void store_c(void* p, int64_t i, float2 v);
+template <>
+__device__ __forceinline__ void store_c<ST_C64>(void* p, int64_t i, float2 v) {
+  reinterpret_cast<float2*>(p)[i] = v;
+}
+template <>
+__device__ __forceinline__ void store_c<ST_F16>(void* p, int64_t i, float2 v) {
+  h2 o;
+  o.x = (_Float16)v.x;
+  o.y = (_Float16)v.y;
+  reinterpret_cast<h2*>(p)[i] = o;
+}
+template <>
+__device__ __forceinline__ void store_c<ST_BF16>(void* p, int64_t i, float2 v) {
+  b2 o;
+  o.x = (__bf16)v.x;
+  o.y = (__bf16)v.y;
+  reinterpret_cast<b2*>(p)[i] = o;
+}
+
+// Smallest E with x <= 2^E, for x > 0.
+__device__ __forceinline__ int ceil_log2(float x) {
+  int e;
+  float m = frexpf(x, &e);
+  return m == 0.5f ? e - 1 : e;
+}
+
+__device__ __forceinline__ void decode(const TileMap& t, uint32_t e, int lo, int hi, int64_t& g,
+                                       int& r, int& cc, int& k) {
+  for (int b = lo; b < hi; ++b) {
+    if ((e >> (b - lo)) & 1) {
+      g += int64_t(1) << t.gpos[b];
+      const int v = 1 << t.cbit[b];
+      if (t.role[b] == 0) r += v;
+      else if (t.role[b] == 1) cc += v;
+      else k += v;
+    }
+  }
+}
+
+// Per-copy scale bookkeeping shared by the kernels' epilogues.  Every
+// stored tensor copy carries a power-of-two exponent: value = stored * 2^exp.
+// The output shift t is chosen from the rigorous bound
+//   |C_re|, |C_im| <= 2^k * (sqrt2 mA)(sqrt2 mB) <= 2^(k+1+E(mA)+E(mB))
+// so that the bound lands on 2^15 for 16-bit storage (inside the binary16
+// range) and on 2^0 for complex64.  The complex64 normalisation keeps
+// heavily sliced networks, whose slice values are far below 2^-126, inside
+// the FP32 range; a power-of-two shift changes no rounding.
+constexpr int kC64Target = 0;
+struct Scale {
+  int shift;  // C_stored = acc * 2^-shift
+  int expC;
+};
+__device__ __forceinline__ int target_log2(const StepDesc& d) {
+  return d.lp_out ? 15 + d.bias : kC64Target;
+}
+__device__ __forceinline__ Scale compute_scale(const StepDesc& d, int js, int jb) {
+  Scale s{0, 0};
+  if (!d.track) return s;
+  const int eA = d.expA ? d.expA[js * d.eA_s + jb * d.eA_b] : 0;
+  const int eB = d.expB ? d.expB[js * d.eB_s + jb * d.eB_b] : 0;
+  int t = 0;
+  const float mA = d.maxA ? d.maxA[js * d.eA_s + jb * d.eA_b] : d.maxA_const;
+  const float mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
+  if (mA > 0.f && mB > 0.f && mA <= 3.0e38f && mB <= 3.0e38f)
+    t = d.k_total + 1 + ceil_log2(mA) + ceil_log2(mB) - target_log2(d);
+  s.shift = t;
+  s.expC = eA + eB + t;
+  return s;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void finish_scale(const StepDesc& d, int js, int jb, float local_max,
+                                             int bad, float* red, bool write_exp, const Scale& sc) {
+  if (!d.track) return;
+  float m = wave_max(local_max);
+  int anybad = __any(bad);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = m;
+    reinterpret_cast<int*>(red)[BLOCK / 64 + w] = anybad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float bm = 0.f;
+    int bb = 0;
+    for (int i = 0; i < BLOCK / 64; ++i) {
+      bm = fmaxf(bm, red[i]);
+      bb |= reinterpret_cast<int*>(red)[BLOCK / 64 + i];
+    }
+    const int ci = js * d.eC_s + jb * d.eC_b;
+    if (d.maxC) atomicMax(reinterpret_cast<unsigned int*>(d.maxC) + ci, __float_as_uint(bm));
+    if (write_exp && d.expC) d.expC[ci] = sc.expC;
+    if (bb && d.flag) {
+      if (d.dep_s_c) d.flag[js] = 1;
+      else
+        for (int i = 0; i < d.flag_n; ++i) d.flag[i] = 1;  // shared by every slice
+    }
+  }
+}
+
+__device__ __forceinline__ void outer_offsets(const StepDesc& d, uint64_t ro, uint64_t no, int js,
+                                              int jb, int64_t& oA, int64_t& oB, int64_t& oC) {
+  oA = js * d.sA_s + jb * d.sA_b;
+  oB = js * d.sB_s + jb * d.sB_b;
+  oC = js * d.sC_s + jb * d.sC_b;
+  for (int i = 0; i < d.n_ro; ++i)
+    if ((ro >> i) & 1) {
+      oA += int64_t(1) << d.ro_A[i];
+      oC += int64_t(1) << d.ro_C[i];
+    }
+  for (int i = 0; i < d.n_no; ++i)
+    if ((no >> i) & 1) {
+      oB += int64_t(1) << d.no_B[i];
+      oC += int64_t(1) << d.no_C[i];
+    }
+}
+
+__device__ __forceinline__ void k_offsets(const StepDesc& d, uint32_t kc, int64_t& kA, int64_t& kB) {
+  kA = 0;
+  kB = 0;
+  for (int i = 0; i < d.n_ko; ++i)
+    if ((kc >> i) & 1) {
+      kA += int64_t(1) << d.ko_A[i];
+      kB += int64_t(1) << d.ko_B[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Offset tables of a tile: element e (bits in increasing address order) sits
+// at global offset g_lo[e & 63] + g_hi[e >> 6] and at LDS coordinate
+// c_lo[e & 63] + c_hi[e >> 6], where the coordinate of a tile bit is its
+// weight inside the LDS array (row bits scaled by the row stride).  Built
+// once per workgroup into LDS, so the per-element cost is two lookups.
+// ---------------------------------------------------------------------------
+struct TileTab {
+  int64_t g[128];  // [0, 64) low six bits, [64, 128) the high bits
+  int32_t c[128];
+};
+
+__device__ __forceinline__ void build_tab(const TileMap& t, int row_stride, int col_stride,
+                                          int k_stride, TileTab& tab) {
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+    const int hi = i >= 64;
+    const int v = hi ? i - 64 : i;
+    const int b0 = hi ? 6 : 0;
+    const int b1 = hi ? t.nbits : (t.nbits < 6 ? t.nbits : 6);
+    int64_t g = 0;
+    int32_t c = 0;
+    for (int b = b0; b < b1; ++b) {
+      if ((v >> (b - b0)) & 1) {
+        g += int64_t(1) << t.gpos[b];
+        const int w = 1 << t.cbit[b];
+        c += t.role[b] == 0 ? w * row_stride : (t.role[b] == 1 ? w * col_stride : w * k_stride);
+      }
+    }
+    tab.g[i] = g;
+    tab.c[i] = c;
+  }
+}
+
+// Epilogue shared by the SIMT kernels: scale, convert, store, track.
+template <int SC>
+__device__ __forceinline__ void store_out(const StepDesc& d, int64_t at, float2 v, const Scale& sc,
+                                          float& lmax, int& bad) {
+  if (sc.shift) {
+    v.x = ldexpf(v.x, -sc.shift);
+    v.y = ldexpf(v.y, -sc.shift);
+  }
+  store_c<SC>(d.C, at, v);
+  if (d.track) {
+    float2 w = v;
+    if (SC != ST_C64) w = load_c<SC>(d.C, at);
+    const float m = fmaxf(fabsf(w.x), fabsf(w.y));
+    if (!(m <= 3.4e38f)) bad = 1;
+    else lmax = fmaxf(lmax, m);
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Tile constants of the MFMA kernels and the C staging table builder.
+// ---------------------------------------------------------------------------
+constexpr int kTM = 128, kTN = 64, kTK = 16;
+constexpr int kAPlane = kTM + 1;          // floats per (k, re/im) plane
+constexpr int kAStride = 2 * kAPlane;     // floats per k
+constexpr int kABuf = kTK * kAStride;     // floats per buffer
+constexpr int kBStride = kTN + 1;         // float2 per k
+constexpr int kBBuf = kTK * kBStride;     // float2 per buffer
+constexpr int kMainFloats = 2 * kABuf + 4 * kBBuf;
+constexpr int kCStride = 2 * kTN + 4;     // floats per staged C row
+constexpr int kCHalf = 64 * kCStride;     // floats of one staged half
+constexpr int kTabFloats = (int)(sizeof(TileTab) / sizeof(float));
+static_assert(kCHalf + kTabFloats <= kMainFloats, "C staging must fit the operand buffers");
+static_assert(2 * kTabFloats <= kMainFloats, "operand tables must fit the operand buffers");
+
+// Table over the tile bits of `t` except bit `skip` (lo: first six, hi: rest).
+__device__ __forceinline__ void build_tab_skip(const TileMap& t, int skip, int row_stride,
+                                               int col_stride, TileTab& tab) {
+  int pos[kMaxTile];
+  int nb = 0;
+  for (int b = 0; b < t.nbits; ++b)
+    if (b != skip) pos[nb++] = b;
+  for (int i = threadIdx.x; i < 128; i += blockDim.x) {
+    const int hi = i >= 64;
+    const int v = hi ? i - 64 : i;
+    const int b0 = hi ? 6 : 0;
+    const int b1 = hi ? nb : (nb < 6 ? nb : 6);
+    int64_t g = 0;
+    int32_t c = 0;
+    for (int j = b0; j < b1; ++j) {
+      if ((v >> (j - b0)) & 1) {
+        const int b = pos[j];
+        g += int64_t(1) << t.gpos[b];
+        const int w = 1 << t.cbit[b];
+        c += t.role[b] == 0 ? w * row_stride : w * col_stride;
+      }
+    }
+    tab.g[i] = g;
+    tab.c[i] = c;
+  }
+}
+
+
+// Per-kernel launchers (one translation unit each).
+hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t s);
+hipError_t launch_simt_kernel(const StepDesc& d, int sa, int sb, int sc, uint64_t tiles,
+                              hipStream_t s);
+hipError_t launch_mfma32_kernel(const StepDesc& d, int sa, int sb, int sc, dim3 grid,
+                                hipStream_t s);
+hipError_t launch_mfma16_kernel(const StepDesc& d, int sa, int sb, int sc, int lp_kind, dim3 grid,
+                                hipStream_t s);
+
+}  // namespace rqc

@@ -461,6 +461,64 @@ static void build_steps(PlanData& p) {
   }
 }
 
+// Fixes `label` of a leaf to `value`: keeps the half of the data with that
+// address bit and drops the label.
+static void project_leaf(Leaf& leaf, int label, int value) {
+  const auto it = std::find(leaf.labels.begin(), leaf.labels.end(), label);
+  if (it == leaf.labels.end()) return;
+  const int rank = (int)leaf.labels.size();
+  const int bit = rank - 1 - (int)(it - leaf.labels.begin());  // address bit, LSB = 0
+  std::vector<cd> out(leaf.data.size() / 2);
+  for (size_t e = 0; e < out.size(); ++e) {
+    const size_t lo = e & ((size_t(1) << bit) - 1);
+    const size_t hi = (e >> bit) << (bit + 1);
+    out[e] = leaf.data[hi | (size_t(value) << bit) | lo];
+  }
+  leaf.labels.erase(it);
+  leaf.data = std::move(out);
+}
+
+// Wires that carry a single value: a leaf whose slab at one value of a wire
+// is zero (relative to the leaf's largest entry) forces the other value, as
+// when the input |0> and the first single-qubit gates of a qubit leave it in
+// a basis state that the next two-qubit gate, a phased swap for
+// fSim(pi/2, phi), passes on.  Fixing such a wire to the forced value drops
+// only zero terms, so it is projected out of every leaf (repeatedly, since a
+// projection can expose more).  Wires in `keep` stay.  Returns the pruned
+// wires with their values.
+static std::vector<std::pair<int, int>> prune_constant_wires(Network& net,
+                                                             const std::vector<char>& keep) {
+  std::vector<std::pair<int, int>> pruned;
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    for (Leaf& leaf : net.leaves) {
+      double mx = 0;
+      for (const cd& v : leaf.data) mx = std::max(mx, std::abs(v));
+      if (mx == 0) continue;
+      const int rank = (int)leaf.labels.size();
+      for (int pos = 0; pos < rank; ++pos) {
+        const int x = leaf.labels[pos];
+        if (net.labels[x].kind != WIRE || keep[x]) continue;
+        const int bit = rank - 1 - pos;
+        double slab[2] = {0, 0};
+        for (size_t e = 0; e < leaf.data.size(); ++e)
+          slab[(e >> bit) & 1] = std::max(slab[(e >> bit) & 1], std::abs(leaf.data[e]));
+        int forced = -1;
+        if (slab[0] <= 1e-13 * mx && slab[1] > 1e-13 * mx) forced = 1;
+        if (slab[1] <= 1e-13 * mx && slab[0] > 1e-13 * mx) forced = 0;
+        if (forced < 0) continue;
+        for (Leaf& other : net.leaves) project_leaf(other, x, forced);
+        net.wire_label.erase({net.labels[x].q, net.labels[x].seg});
+        pruned.push_back({x, forced});
+        changed = true;
+        break;  // this leaf's labels changed
+      }
+    }
+  }
+  return pruned;
+}
+
 void make_plan(PlanData& p) {
   Network& net = p.net;
   const int nlab = (int)net.labels.size();
@@ -484,94 +542,174 @@ void make_plan(PlanData& p) {
   }
   if (p.opts.n_sliced >= 0 && p.opts.n_sliced < (int)forced.size())
     throw Error{RQC_EINVAL, "n_sliced smaller than the forced wires"};
-  if (p.opts.n_sliced > 62) throw Error{RQC_EUNSUPPORTED, "more than 62 sliced wires"};
+  {
+    std::vector<char> keep(nlab, 0);
+    for (int x : forced) keep[x] = 1;
+    p.pruned = prune_constant_wires(net, keep);
+    for (int i = 0; i < nl; ++i) {
+      leaf_sets[i].clear();
+      for (int x : net.leaves[i].labels)
+        if (net.labels[x].kind != CLOSED) leaf_sets[i].push_back(x);
+      std::sort(leaf_sets[i].begin(), leaf_sets[i].end());
+    }
+    std::fill(sliceable.begin(), sliceable.end(), 0);
+    for (auto& kv : net.wire_label) sliceable[kv.second] = 1;
+  }
+  if (p.opts.n_sliced > 62 && p.opts.n_local == 0)
+    throw Error{RQC_EUNSUPPORTED, "more than 62 sliced wires need a slice share (n_local_sliced)"};
+  if (p.opts.n_sliced > 4096) throw Error{RQC_EUNSUPPORTED, "more than 4096 sliced wires"};
 
-  // Independent trials: trial t draws from its own generator seeded by
-  // (seed, t), so the result does not depend on how trials are spread over
-  // threads.
   const double temps[] = {0.0, 0.02, 0.1, 0.3, 0.6, 1.0};
   const int trials = std::max(1, p.opts.trials);
-  struct TrialResult {
-    double score = 1e308;
-    Tree tree;
-    SliceResult sl;
-  };
-  std::vector<TrialResult> results(trials);
-  auto run_trial = [&](int tr) {
-    std::mt19937_64 rng(p.opts.seed * 0x9E3779B97F4A7C15ull + 0x51ED27ull * (uint64_t)tr + 12345);
-    std::uniform_real_distribution<double> ua(0.0, 1.6);
-    const double alpha = tr == 0 ? 1.0 : ua(rng);
-    const double temp = tr == 0 ? 0.0 : temps[rng() % 6];
-    Tree t = greedy_tree(leaf_sets, nlab, alpha, temp, rng);
-    SliceResult sr = slice_tree(t, leaf_sets, nlab, sliceable, forced, p.opts.max_log2, p.opts.n_sliced);
-    const double total = std::log2(sr.per_slice.flops) + (double)sr.sliced.size();
-    const double over = p.opts.max_log2 > 0 ? std::max(0, sr.per_slice.width - p.opts.max_log2) : 0;
-    results[tr].score = total + 4.0 * over;
-    results[tr].tree = std::move(t);
-    results[tr].sl = std::move(sr);
-  };
-  const int n_threads = std::min(8, trials);
-  {
-    std::vector<std::thread> pool;
-    for (int w = 0; w < n_threads; ++w)
-      pool.emplace_back([&, w] {
-        for (int tr = w; tr < trials; tr += n_threads) run_trial(tr);
-      });
-    for (auto& th : pool) th.join();
-  }
-  // Re-optimise the best few trees on their sliced networks; keep the best.
-  std::vector<int> order(trials);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return results[x].score < results[y].score; });
-  const int n_refine = std::min(trials, 32);
-  struct Refined {
-    double score = 1e308;
+  struct Candidate {
+    double score = 1e308;  // log2(per-slice multiply-adds) + sliced wires + width penalty
     Tree tree;
     std::vector<LSet> sets;
     std::vector<int> sliced;
   };
-  std::vector<Refined> refined(n_refine);
-  auto refine = [&](int r) {
-    TrialResult& tr = results[order[r]];
-    std::vector<char> drop(nlab, 0);
-    for (int x : tr.sl.sliced) drop[x] = 1;
-    std::vector<LSet> sliced_leaf(nl);
-    for (int i = 0; i < nl; ++i) sliced_leaf[i] = remove_labels(leaf_sets[i], drop);
-    std::vector<LSet> s = node_sets(tr.tree, sliced_leaf);
-    const int w0 = tree_cost(tr.tree, s).width;
-    const int wb = p.opts.max_log2 > 0 ? std::max(p.opts.max_log2, w0) : w0;
-    if (p.opts.reconf_rounds > 0) {
-      std::mt19937_64 rng(p.opts.seed * 0x2545F4914F6CDD1Dull + (uint64_t)r + 777);
-      reconfigure(tr.tree, s, p.opts.reconf_rounds, 8, wb, rng);
-      s = node_sets(tr.tree, sliced_leaf);
-    }
-    const CostModel c = tree_cost(tr.tree, s);
-    refined[r].score = std::log2(c.flops) + (double)tr.sl.sliced.size() +
-                       (p.opts.max_log2 > 0 ? 4.0 * std::max(0, c.width - p.opts.max_log2) : 0.0);
-    refined[r].tree = tr.tree;
-    refined[r].sets = std::move(s);
-    refined[r].sliced = tr.sl.sliced;
+  auto width_penalty = [&](int width) {
+    return p.opts.max_log2 > 0 ? 4.0 * std::max(0, width - p.opts.max_log2) : 0.0;
   };
-  {
-    std::vector<std::thread> pool;
-    for (int w = 0; w < std::min(8, n_refine); ++w)
-      pool.emplace_back([&, w] {
-        for (int r = w; r < n_refine; r += 8) refine(r);
-      });
-    for (auto& th : pool) th.join();
+  auto sliced_leaves = [&](const std::vector<int>& sl) {
+    std::vector<char> drop(nlab, 0);
+    for (int x : sl) drop[x] = 1;
+    std::vector<LSet> out(nl);
+    for (int i = 0; i < nl; ++i) out[i] = remove_labels(leaf_sets[i], drop);
+    return out;
+  };
+  // One search: n_trials randomized greedy trees, each sliced (the given
+  // wires first, then greedily up to n_target or the width bound); the best
+  // 32 are re-optimised on their sliced networks.  With `on_sliced` the
+  // greedy trees are built on the network with the given wires removed.
+  // Trial t draws from its own generator seeded by (seed, salt, t), so the
+  // result does not depend on how trials are spread over threads.
+  auto search = [&](const std::vector<int>& given, int n_target, uint64_t salt, int n_trials,
+                    bool on_sliced) {
+    std::vector<Candidate> res(n_trials);
+    const std::vector<LSet> base = on_sliced ? sliced_leaves(given) : leaf_sets;
+    auto run_trial = [&](int tr) {
+      std::mt19937_64 rng(p.opts.seed * 0x9E3779B97F4A7C15ull + 0x51ED27ull * (uint64_t)tr + 12345 +
+                          salt * 0xD1B54A32D192ED03ull);
+      std::uniform_real_distribution<double> ua(0.0, 1.6);
+      const double alpha = tr == 0 ? 1.0 : ua(rng);
+      const double temp = tr == 0 ? 0.0 : temps[rng() % 6];
+      Tree t = greedy_tree(base, nlab, alpha, temp, rng);
+      SliceResult sr = slice_tree(t, leaf_sets, nlab, sliceable, given, p.opts.max_log2, n_target);
+      res[tr].score = std::log2(sr.per_slice.flops) + (double)sr.sliced.size() +
+                      width_penalty(sr.per_slice.width);
+      res[tr].tree = std::move(t);
+      res[tr].sliced = std::move(sr.sliced);
+    };
+    {
+      std::vector<std::thread> pool;
+      for (int w = 0; w < std::min(8, n_trials); ++w)
+        pool.emplace_back([&, w] {
+          for (int tr = w; tr < n_trials; tr += 8) run_trial(tr);
+        });
+      for (auto& th : pool) th.join();
+    }
+    std::vector<int> order(n_trials);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return res[x].score < res[y].score; });
+    const int n_refine = std::min(n_trials, 32);
+    auto refine = [&](int r) {
+      Candidate& c = res[order[r]];
+      const std::vector<LSet> sl = sliced_leaves(c.sliced);
+      std::vector<LSet> ss = node_sets(c.tree, sl);
+      const int w0 = tree_cost(c.tree, ss).width;
+      const int wb = p.opts.max_log2 > 0 ? std::max(p.opts.max_log2, w0) : w0;
+      if (p.opts.reconf_rounds > 0) {
+        std::mt19937_64 rng(p.opts.seed * 0x2545F4914F6CDD1Dull + (uint64_t)r + 777 + salt * 0x9E37ull);
+        reconfigure(c.tree, ss, p.opts.reconf_rounds, 8, wb, rng);
+        ss = node_sets(c.tree, sl);
+      }
+      const CostModel cm = tree_cost(c.tree, ss);
+      c.score = std::log2(cm.flops) + (double)c.sliced.size() + width_penalty(cm.width);
+      c.sets = std::move(ss);
+    };
+    {
+      std::vector<std::thread> pool;
+      for (int w = 0; w < std::min(8, n_refine); ++w)
+        pool.emplace_back([&, w] {
+          for (int r = w; r < n_refine; r += 8) refine(r);
+        });
+      for (auto& th : pool) th.join();
+    }
+    int best = order[0];
+    for (int r = 1; r < n_refine; ++r)
+      if (res[order[r]].score < res[best].score) best = order[r];
+    return std::move(res[best]);
+  };
+
+  Candidate best = search(forced, p.opts.n_sliced, 0, trials, false);
+  // Improvement rounds, choosing path and slicing together: the first
+  // search slices trees built for the whole network, so trees built
+  // again with the chosen wires fixed -- greedily on the whole network and
+  // on the sliced one -- are often far cheaper per slice.  With automatic
+  // slicing, wires whose removal keeps every intermediate within the bound
+  // are then un-sliced (the total cost never grows: a slice at most doubles).
+  const int n_user = (int)forced.size();
+  for (int round = 1; round <= 3 && !best.sliced.empty(); ++round) {
+    const int t2 = std::min(trials, 512);
+    bool improved = false;
+    for (bool on_sliced : {false, true}) {
+      Candidate c = search(best.sliced, (int)best.sliced.size(), 2 * round + on_sliced, t2, on_sliced);
+      if (c.score < best.score - 1e-9) {
+        best = std::move(c);
+        improved = true;
+      }
+    }
+    bool unsliced = false;
+    while (p.opts.n_sliced < 0 && p.opts.max_log2 > 0 && (int)best.sliced.size() > n_user) {
+      int pick = -1;
+      double pick_flops = 0;
+      for (int j = n_user; j < (int)best.sliced.size(); ++j) {
+        std::vector<int> sl = best.sliced;
+        sl.erase(sl.begin() + j);
+        const CostModel cm = tree_cost(best.tree, node_sets(best.tree, sliced_leaves(sl)));
+        if (cm.width > p.opts.max_log2) continue;
+        if (pick < 0 || cm.flops < pick_flops) {
+          pick = j;
+          pick_flops = cm.flops;
+        }
+      }
+      if (pick < 0) break;
+      best.sliced.erase(best.sliced.begin() + pick);
+      unsliced = true;
+    }
+    if (unsliced) {
+      best.sets = node_sets(best.tree, sliced_leaves(best.sliced));
+      const CostModel cm = tree_cost(best.tree, best.sets);
+      best.score = std::log2(cm.flops) + (double)best.sliced.size() + width_penalty(cm.width);
+    }
+    if (!improved && !unsliced) break;
   }
-  int best = 0;
-  for (int r = 1; r < n_refine; ++r)
-    if (refined[r].score < refined[best].score) best = r;
-  Tree best_tree = std::move(refined[best].tree);
-  std::vector<LSet> s = std::move(refined[best].sets);
+  Tree best_tree = std::move(best.tree);
+  std::vector<LSet> s = std::move(best.sets);
   SliceResult best_sl;
-  best_sl.sliced = refined[best].sliced;
-  if (best_sl.sliced.size() > 62)
-    throw Error{RQC_EUNSUPPORTED, "the width bound needs more than 62 sliced wires (2^62 slices)"};
+  best_sl.sliced = best.sliced;
+
+  if (best_sl.sliced.size() > 62 && p.opts.n_local == 0)
+    throw Error{RQC_EUNSUPPORTED,
+                "the width bound needs more than 62 sliced wires: use a slice share (n_local_sliced)"};
+  if (p.opts.n_local > (int)best_sl.sliced.size())
+    throw Error{RQC_EINVAL, "n_local_sliced exceeds the number of sliced wires"};
   p.tree = std::move(best_tree);
   p.sliced = best_sl.sliced;
+  p.fixed.clear();
+  if (p.opts.n_local > 0) {
+    // Wires beyond the share's enumerated ones take the share's bits and
+    // are projected out of the leaves now.
+    for (size_t j = p.opts.n_local; j < p.sliced.size(); ++j) {
+      const size_t i = j - p.opts.n_local;
+      const int v = i < p.opts.share_bits.size() ? (int)p.opts.share_bits[i] : 0;
+      p.fixed.push_back({p.sliced[j], v});
+    }
+    p.sliced.resize(p.opts.n_local);
+    for (Leaf& leaf : net.leaves)
+      for (const auto& fv : p.fixed) project_leaf(leaf, fv.first, fv.second);
+  }
   p.node_labels = s;
   p.cost = tree_cost(p.tree, s);
   build_steps(p);
@@ -598,6 +736,16 @@ std::string plan_json(const PlanData& p) {
   for (size_t j = 0; j < p.sliced.size(); ++j) {
     const Label& L = net.labels[p.sliced[j]];
     o << (j ? "," : "") << '[' << L.q << ',' << L.seg << ']';
+  }
+  o << "],\"fixed_wires\":[";
+  for (size_t j = 0; j < p.fixed.size(); ++j) {
+    const Label& L = net.labels[p.fixed[j].first];
+    o << (j ? "," : "") << '[' << L.q << ',' << L.seg << ',' << p.fixed[j].second << ']';
+  }
+  o << "],\"pruned_wires\":[";
+  for (size_t j = 0; j < p.pruned.size(); ++j) {
+    const Label& L = net.labels[p.pruned[j].first];
+    o << (j ? "," : "") << '[' << L.q << ',' << L.seg << ',' << p.pruned[j].second << ']';
   }
   o << "],\"labels\":[";
   for (size_t i = 0; i < net.labels.size(); ++i) {

@@ -1,0 +1,138 @@
+"""A slice share of a 10x10 (1+20+1) circuit: 256 slices (eight enumerated
+sliced wires, every other sliced wire fixed to 0) under a 2^26 per-slice
+bound, all 256 in one call per precision.  (The benchmark runs the
+1024-slice share at 2^28; this size keeps each call to seconds.)
+
+The oracle cannot contract one of these slices in seconds, and its own
+greedy order does not fit in memory, so the share is checked by:
+* 32 checked slices, FP16 and BF16 against FP32 within the reduced-precision
+  tolerance;
+* sub-slices of the 32 checked slices (up to 40 more wires fixed) against the
+  oracle, which contracts its own gate tensors in the plan's order given as
+  data (the order changes cost, never the value);
+* additivity: a checked slice equals the sum of its 256 sub-slices over 8
+  more wires, computed by another plan with another tree;
+* a second plan with another tree and the same wires gives the same slices.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import rqcgen
+import oracle
+from plan_order import oracle_order, oracle_wires_and_ids
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2110_14502_amd")
+
+ROWS, COLS, DEPTH, SEED, BOUND, LOCAL, TRIALS = 10, 10, 20, 4, 26, 8, 64
+N = ROWS * COLS
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def share():
+    _say("share plan + FP32 over 256 slices")
+    circ = rqcgen.grid_rqc(ROWS, COLS, DEPTH, SEED)
+    bits = rqcgen.random_bits(N, SEED)
+    net = R.Network(R.Circuit.from_rqcgen(circ), [])
+    plan = R.Plan(net, max_log2_elems=BOUND, path_trials=TRIALS, seed=SEED,
+                  n_local_sliced=LOCAL).bind()
+    free, _ = torch.cuda.mem_get_info()
+    ws = torch.empty(int(min(free * 0.6, 160 << 30)), dtype=torch.uint8, device="cuda")
+    _, per = plan.contract(bits, per_slice=True, workspace=ws)
+    per32 = R.to_complex(per)[:, 0, 0]
+    checked = sorted(int(x) for x in np.random.default_rng(SEED).choice(1 << LOCAL, 32, replace=False))
+    yield circ, bits, net, plan, ws, per32, checked
+    del ws
+
+
+def _wires(plan):
+    return plan.sliced_wires(), [w[:2] for w in plan.fixed_wires()]
+
+
+def _err(got, ref):
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    assert rms > 0, "every checked value is zero"
+    return np.max(np.abs(got - ref)) / rms
+
+
+def test_share_values_are_finite_and_not_all_zero(share):
+    _, _, _, plan, _, per32, checked = share
+    assert np.all(np.isfinite(per32))
+    assert np.count_nonzero(per32) > 0
+    assert plan.last_report["fp32_reruns"] == 0
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_share_reduced_precision_vs_fp32(share, prec):
+    _, bits, _, plan, ws, per32, checked = share
+    _say("share", prec)
+    _, per = plan.contract(bits, per_slice=True, prec=R.PRECISIONS[prec], workspace=ws)
+    lp = R.to_complex(per)[:, 0, 0]
+    assert np.all(np.isfinite(lp))
+    assert _err(lp[checked], per32[checked]) < 2e-2
+    assert oracle.linear_fidelity(lp[checked], per32[checked]) > 0.99
+
+
+def test_share_subslices_vs_oracle(share):
+    circ, bits, net, plan, ws, _, checked = share
+    _say("share sub-slices vs oracle")
+    loc, fixed = _wires(plan)
+    q = R.Plan(net, max_log2_elems=21, path_trials=16, seed=SEED, forced_wires=loc + fixed,
+               n_local_sliced=LOCAL)
+    extra = [w[:2] for w in q.fixed_wires()[len(fixed):]]
+    x = min(40, len(extra))
+    wires = loc + extra[:x] + fixed + extra[x:]
+    fine = R.Plan(net, n_sliced=len(wires), forced_wires=wires, path_trials=16, seed=SEED,
+                  n_local_sliced=LOCAL + x).bind()
+    assert fine.sliced_wires() == loc + extra[:x]
+    rng = np.random.default_rng(7)
+    # Half of the sub-slices keep the extra wires at 0, half draw them.
+    ids = [s + ((int(rng.integers(1 << x)) if i % 2 else 0) << LOCAL) for i, s in enumerate(checked)]
+    _, per = fine.contract(bits, slice_ids=ids, per_slice=True, workspace=ws)
+    got = R.to_complex(per)[:, 0, 0]
+    e = fine.export()
+    groups, pairs = oracle_order(circ, [], e)
+    ow, oids = oracle_wires_and_ids(e, ids)
+    assert ow[:len(wires)] == wires
+    ref = oracle.slice_values_ordered(circ, [], bits, ow, oids, groups, pairs)[:, 0]
+    assert _err(got, ref) < 1e-4
+
+
+def test_share_slice_is_sum_of_subslices(share):
+    _, bits, net, plan, ws, per32, checked = share
+    _say("share additivity")
+    loc, fixed = _wires(plan)
+    q = R.Plan(net, max_log2_elems=BOUND - 4, path_trials=16, seed=SEED, forced_wires=loc + fixed,
+               n_local_sliced=LOCAL)
+    extra = [w[:2] for w in q.fixed_wires()[len(fixed):]][:8]
+    assert len(extra) == 8
+    wires = loc + extra + fixed
+    fine = R.Plan(net, max_log2_elems=BOUND, n_sliced=len(wires), forced_wires=wires,
+                  path_trials=16, seed=SEED + 1, n_local_sliced=LOCAL + 8).bind()
+    scale = np.sqrt(np.mean(np.abs(per32[checked]) ** 2))
+    for s in checked[:4]:
+        ids = [s + (e << LOCAL) for e in range(256)]
+        _, per = fine.contract(bits, slice_ids=ids, per_slice=True, workspace=ws)
+        total = R.to_complex(per)[:, 0, 0].sum()
+        assert abs(total - per32[s]) / scale < 1e-4
+
+
+def test_share_two_plans_agree(share):
+    _, bits, net, plan, ws, per32, checked = share
+    _say("share two plans")
+    loc, fixed = _wires(plan)
+    other = R.Plan(net, max_log2_elems=BOUND, n_sliced=len(loc) + len(fixed),
+                   forced_wires=loc + fixed, path_trials=32, seed=SEED + 9,
+                   n_local_sliced=LOCAL).bind()
+    _, per = other.contract(bits, slice_ids=checked, per_slice=True, workspace=ws)
+    got = R.to_complex(per)[:, 0, 0]
+    assert _err(got, per32[checked]) < 1e-4
