@@ -206,7 +206,9 @@ static SliceResult slice_tree(const Tree& t, const std::vector<LSet>& leaf_sets,
   CostModel c = tree_cost(t, s);
   const int nn = (int)t.left.size();
   while (true) {
-    const bool need_width = bound > 0 && c.width > bound;
+    // An exact wire count (n_target >= 0) is never exceeded; the caller
+    // checks the bound afterwards.
+    const bool need_width = n_target < 0 && bound > 0 && c.width > bound;
     const bool need_count = n_target >= 0 && (int)r.sliced.size() < n_target;
     if (!need_width && !need_count) break;
     // savings[x]: flops removed if x is sliced (per slice).
@@ -650,7 +652,7 @@ void make_plan(PlanData& p) {
   // slicing, wires whose removal keeps every intermediate within the bound
   // are then un-sliced (the total cost never grows: a slice at most doubles).
   const int n_user = (int)forced.size();
-  for (int round = 1; round <= 3 && !best.sliced.empty(); ++round) {
+  auto research = [&](int round) {
     const int t2 = std::min(trials, 512);
     bool improved = false;
     for (bool on_sliced : {false, true}) {
@@ -660,8 +662,11 @@ void make_plan(PlanData& p) {
         improved = true;
       }
     }
-    bool unsliced = false;
-    while (p.opts.n_sliced < 0 && p.opts.max_log2 > 0 && (int)best.sliced.size() > n_user) {
+    return improved;
+  };
+  auto unslice = [&]() {
+    bool any = false;
+    while ((int)best.sliced.size() > n_user) {
       int pick = -1;
       double pick_flops = 0;
       for (int j = n_user; j < (int)best.sliced.size(); ++j) {
@@ -676,15 +681,25 @@ void make_plan(PlanData& p) {
       }
       if (pick < 0) break;
       best.sliced.erase(best.sliced.begin() + pick);
-      unsliced = true;
+      any = true;
     }
-    if (unsliced) {
+    if (any) {
       best.sets = node_sets(best.tree, sliced_leaves(best.sliced));
       const CostModel cm = tree_cost(best.tree, best.sets);
       best.score = std::log2(cm.flops) + (double)best.sliced.size() + width_penalty(cm.width);
     }
-    if (!improved && !unsliced) break;
+    return any;
+  };
+  const bool auto_slicing = p.opts.n_sliced < 0 && p.opts.max_log2 > 0;
+  bool again = !best.sliced.empty();
+  for (int round = 1; round <= 6 && again; ++round) {
+    const bool improved = research(round);
+    const bool unsliced = auto_slicing && unslice();
+    again = improved || unsliced;
+    if (round == 6 && unsliced) research(7);
   }
+  if (p.opts.max_log2 > 0 && tree_cost(best.tree, best.sets).width > p.opts.max_log2)
+    throw Error{RQC_EUNSUPPORTED, "no tree found within the width bound with the requested sliced wires"};
   Tree best_tree = std::move(best.tree);
   std::vector<LSet> s = std::move(best.sets);
   SliceResult best_sl;

@@ -1,18 +1,17 @@
 """A slice share of a 10x10 (1+20+1) circuit: 256 slices (eight enumerated
-sliced wires, every other sliced wire fixed to 0) under a 2^26 per-slice
-bound, all 256 in one call per precision.  (The benchmark runs the
-1024-slice share at 2^28; this size keeps each call to seconds.)
+sliced wires, every other sliced wire fixed to 0, single-valued wires
+pruned) under a 2^24 per-slice bound, all 256 in one call per precision.
+(The benchmark runs the 1024-slice share at 2^28; this size keeps the
+oracle's work to seconds per slice.)
 
-The oracle cannot contract one of these slices in seconds, and its own
-greedy order does not fit in memory, so the share is checked by:
+The oracle's own greedy order does not fit in memory on this network, so it
+contracts its own gate tensors in the plan's order given as data (the order
+changes cost, never the value).  Checked:
+* 4 of the slices against the oracle;
 * 32 checked slices, FP16 and BF16 against FP32 within the reduced-precision
   tolerance;
-* sub-slices of the 32 checked slices (up to 40 more wires fixed) against the
-  oracle, which contracts its own gate tensors in the plan's order given as
-  data (the order changes cost, never the value);
-* additivity: a checked slice equals the sum of its 256 sub-slices over 8
-  more wires, computed by another plan with another tree;
-* a second plan with another tree and the same wires gives the same slices.
+* sub-slices of the 32 checked slices (up to 40 more wires fixed, half of
+  them drawn at random) against the oracle.
 """
 import sys
 
@@ -28,7 +27,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 R = pytest.importorskip("paper_2110_14502_amd")
 
-ROWS, COLS, DEPTH, SEED, BOUND, LOCAL, TRIALS = 10, 10, 20, 4, 26, 8, 64
+ROWS, COLS, DEPTH, SEED, BOUND, LOCAL, TRIALS = 10, 10, 20, 4, 24, 8, 64
 N = ROWS * COLS
 
 
@@ -71,6 +70,17 @@ def test_share_values_are_finite_and_not_all_zero(share):
     assert plan.last_report["fp32_reruns"] == 0
 
 
+def test_share_slices_vs_oracle(share):
+    circ, bits, _, plan, _, per32, checked = share
+    _say("share slices vs oracle")
+    e = plan.export()
+    groups, pairs = oracle_order(circ, [], e)
+    ids = checked[:4]
+    ow, oids = oracle_wires_and_ids(e, ids)
+    ref = oracle.slice_values_ordered(circ, [], bits, ow, oids, groups, pairs)[:, 0]
+    assert _err(per32[ids], ref) < 1e-4
+
+
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
 def test_share_reduced_precision_vs_fp32(share, prec):
     _, bits, _, plan, ws, per32, checked = share
@@ -105,34 +115,3 @@ def test_share_subslices_vs_oracle(share):
     assert ow[:len(wires)] == wires
     ref = oracle.slice_values_ordered(circ, [], bits, ow, oids, groups, pairs)[:, 0]
     assert _err(got, ref) < 1e-4
-
-
-def test_share_slice_is_sum_of_subslices(share):
-    _, bits, net, plan, ws, per32, checked = share
-    _say("share additivity")
-    loc, fixed = _wires(plan)
-    q = R.Plan(net, max_log2_elems=BOUND - 4, path_trials=16, seed=SEED, forced_wires=loc + fixed,
-               n_local_sliced=LOCAL)
-    extra = [w[:2] for w in q.fixed_wires()[len(fixed):]][:8]
-    assert len(extra) == 8
-    wires = loc + extra + fixed
-    fine = R.Plan(net, max_log2_elems=BOUND, n_sliced=len(wires), forced_wires=wires,
-                  path_trials=16, seed=SEED + 1, n_local_sliced=LOCAL + 8).bind()
-    scale = np.sqrt(np.mean(np.abs(per32[checked]) ** 2))
-    for s in checked[:4]:
-        ids = [s + (e << LOCAL) for e in range(256)]
-        _, per = fine.contract(bits, slice_ids=ids, per_slice=True, workspace=ws)
-        total = R.to_complex(per)[:, 0, 0].sum()
-        assert abs(total - per32[s]) / scale < 1e-4
-
-
-def test_share_two_plans_agree(share):
-    _, bits, net, plan, ws, per32, checked = share
-    _say("share two plans")
-    loc, fixed = _wires(plan)
-    other = R.Plan(net, max_log2_elems=BOUND, n_sliced=len(loc) + len(fixed),
-                   forced_wires=loc + fixed, path_trials=32, seed=SEED + 9,
-                   n_local_sliced=LOCAL).bind()
-    _, per = other.contract(bits, slice_ids=checked, per_slice=True, workspace=ws)
-    got = R.to_complex(per)[:, 0, 0]
-    assert _err(got, per32[checked]) < 1e-4
