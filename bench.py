@@ -26,9 +26,19 @@ METRIC = "amplitudes/s + contraction TFLOP/s vs plain FP32 path at stated error;
 PEAK_MFMA_FP32 = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_MFMA_16 = 2500.0    # TFLOP/s, MI355X dense FP16 / BF16 matrix
 PEAK_HBM = 8000.0        # GB/s
-# Counter summary (FETCH_SIZE / WRITE_SIZE) of the FP32 MFMA launches of the
-# default amplitude workload.
-TRAFFIC_PROFILE = "k_mfma32_config2_6x6x14_fp32_traffic.md"
+# Kernel kinds of the timing probe: 0 generic SIMT, 1 FP32/16-bit MFMA, 2 rows.
+KIND_NAMES = {0: "k_simt", 1: "k_mfma32", 2: "k_rows"}
+KIND_SOURCES = {0: "k_simt.hip", 1: "k_mfma32.hip", 2: "k_rows.hip"}
+KIND_LABELS = {
+    0: "k_simt (generic table-driven contraction, split-K)",
+    1: "k_mfma32 (fused permute + complex GEMM, FP32 MFMA 32x32x2)",
+    2: "k_rows (row-streaming stem step, FP32 MFMA 16x16x4, LDS-staged stores)",
+}
+# Counter summaries (FETCH_SIZE / WRITE_SIZE) of the dominant kernel of the
+# default amplitude workload, per kernel kind.
+TRAFFIC_PROFILES = {1: "k_mfma32_config2_6x6x14_fp32_traffic.md",
+                    2: "k_rows_config2_6x6x14_fp32_traffic.md",
+                    0: "k_simt_config2_6x6x14_fp32_traffic.md"}
 
 
 def parse():
@@ -54,6 +64,9 @@ def parse():
     ap.add_argument("--share-local", type=int, default=10,
                     help="share mode: enumerated sliced wires (2^L slices)")
     ap.add_argument("--share-trials", type=int, default=256)
+    ap.add_argument("--share-bf16-min-log2", type=int, default=0,
+                    help="share mode: smallest intermediate (log2 elements) stored in BF16; 0 = default")
+    ap.add_argument("--share-precs", default="f32,f16,bf16", help="share mode: precisions to run")
     ap.add_argument("--share-f32-parts", type=int, default=2,
                     help="share mode: FP32 baseline calls (each prints a progress line)")
     ap.add_argument("--steps", type=int, default=2)
@@ -70,6 +83,8 @@ def parse():
     ap.add_argument("--ws-fraction", type=float, default=0.85)
     ap.add_argument("--slices", type=int, default=0,
                     help="contract only the first N slice ids (profiling); 0 = all")
+    ap.add_argument("--max-group", type=int, default=0,
+                    help="bound on the slices per batched group (0 = workspace only)")
     ap.add_argument("--graph-steps", type=int, default=1)
     ap.add_argument("--lp-steps", type=int, default=1,
                     help="timed steps of the reduced-precision (f16) comparison, 0 = skip")
@@ -126,34 +141,65 @@ def _fidelity(a, ref):
     return float(num / (np.vdot(ref, ref).real * np.vdot(a, a).real))
 
 
-def kernel_source_hash(root):
-    """SHA-256 over the sources of the FP32 MFMA kernel and its headers."""
+def kernel_source_hash(root, kind):
+    """SHA-256 over the sources of one kernel kind and the shared headers."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_mfma32.hip", "kernels_dev.h", "kernels.h"):
+    for f in (KIND_SOURCES[kind], "kernels_dev.h", "kernels.h"):
         h.update(open(os.path.join(root, "paper_2110_14502_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
-def _profile_traffic(name, flops_per_launch):
+def _profile_traffic(kind, flops_per_launch, bytes_per_launch):
     """HBM bytes per launch of the dominant kernel from a committed counter
     summary, or None when the summary does not match: the kernel sources
     changed since the counters were taken, or its launches were different."""
     root = os.path.dirname(os.path.abspath(__file__))
     try:
-        text = open(os.path.join(root, "profiles", name)).read()
-    except OSError:
+        text = open(os.path.join(root, "profiles", TRAFFIC_PROFILES[kind])).read()
+    except (OSError, KeyError):
         return None
     vals = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
-    sha = kernel_source_hash(root)
     try:
-        if vals.get("kernel_source_sha256") != sha:
+        if vals.get("kernel_source_sha256") != kernel_source_hash(root, kind):
             return None
         if abs(float(vals["flops_per_launch"]) / flops_per_launch - 1) > 1e-6:
+            return None
+        if abs(float(vals["algorithmic_bytes_per_launch"]) / bytes_per_launch - 1) > 1e-6:
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError, ZeroDivisionError):
         return None
+
+
+def roofline(kind, tim, a, flops_total, kind_ms):
+    """Roofline entry of the dominant kernel kind from the timing probe."""
+    n = max(1, tim["launches"])
+    secs = tim["total_ms"] / 1000.0
+    fpl, bpl = tim["flops"] / n, tim["bytes"] / n
+    if kind == 1:
+        peak = PEAK_MFMA_FP32 if a.prec == "f32" else PEAK_MFMA_16
+        achieved = tim["flops"] / secs / 1e12 if secs > 0 else 0.0
+        bound, unit = "mfma", "TFLOP/s"
+    else:
+        peak = PEAK_HBM
+        achieved = tim["bytes"] / secs / 1e9 if secs > 0 else 0.0
+        bound, unit = "hbm", "GB/s"
+    label = KIND_LABELS[kind]
+    if kind == 1 and a.prec != "f32":
+        label = "k_mfma32 + k_mfma16 (fused permute + complex GEMM, FP32 and FP16/BF16 MFMA)"
+    return {
+        "bound": bound, "kernel": label, "achieved": achieved, "peak": peak, "unit": unit,
+        "frac": achieved / peak,
+        "traffic": _profile_traffic(kind, fpl, bpl) if a.prec == "f32" else None,
+        "algorithmic_bytes_per_launch": bpl,
+        "flops_per_launch": fpl,
+        "launches": tim["launches"],
+        "avg_launch_ms": tim["total_ms"] / n,
+        "achieved_tflops": tim["flops"] / secs / 1e12 if secs > 0 else 0.0,
+        "share_of_step_flops": tim["flops"] / flops_total,
+        "probe_ms_per_step_by_kernel": kind_ms,
+    }
 
 
 def log(*msg):
@@ -368,7 +414,8 @@ def share_mode(a):
     bits = rqcgen.random_bits(n, seed)
     t = time.perf_counter()
     plan = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), []), max_log2_elems=a.share_bound,
-                  path_trials=a.share_trials, seed=seed, n_local_sliced=a.share_local)
+                  path_trials=a.share_trials, seed=seed, n_local_sliced=a.share_local,
+                  bf16_min_log2=a.share_bf16_min_log2)
     t_plan = time.perf_counter() - t
     info = plan.info()
     n_sl = info["n_slices"]
@@ -395,7 +442,10 @@ def share_mode(a):
                       "invariant_log2_flops": math.log2(info["flops_invariant"] + 1.0)},
            "unit": "slices/s"}
     vals = {}
-    for prec in ("f32", "f16", "bf16"):
+    precs = [p for p in ("f32", "f16", "bf16") if p in a.share_precs.split(",")]
+    if "f32" not in precs:
+        raise SystemExit("share mode needs f32 (the comparison baseline)")
+    for prec in precs:
         pc = R.PRECISIONS[prec]
         parts = a.share_f32_parts if prec == "f32" else 1
         # Timed: the product path, each call one graph launch of its slices.
@@ -431,13 +481,14 @@ def share_mode(a):
                               "launches": tim["launches"],
                               "share_of_flops": tim["flops"] / (info["flops_per_slice"] * max(1, n_sl // 8))}}
     plan.set_timing(-1)
-    for prec in ("f16", "bf16"):
+    for prec in [p for p in precs if p != "f32"]:
         ref, got = vals["f32"][checked], vals[prec][checked]
         rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
         res[prec]["speedup_vs_f32"] = res["f32"]["seconds"] / res[prec]["seconds"]
         res[prec]["per_slice_error_vs_f32"] = float(np.max(np.abs(got - ref)) / rms) if rms > 0 else None
         res[prec]["fidelity_vs_f32"] = _fidelity(got, ref)
-    best = max(("f16", "bf16"), key=lambda p: res[p]["slices_per_s"])
+    lp_precs = [p for p in precs if p != "f32"] or ["f32"]
+    best = max(lp_precs, key=lambda p: res[p]["slices_per_s"])
     res["metric"] = "share slices/s (reduced precision) and contraction TFLOP/s"
     res["value"] = res[best]["slices_per_s"]
     res["dtype"] = best
@@ -447,14 +498,24 @@ def share_mode(a):
 
 
 def copy_mode(a):
-    """A plain device copy of 1 GiB (calibration of the traffic counters)."""
+    """Plain device copies, reads and writes (calibration of the traffic
+    counters and of the achievable HBM rate)."""
     import torch
-    n = 1 << 30
-    x = torch.ones(n, dtype=torch.uint8, device="cuda")
-    y = torch.empty_like(x)
-    ms = _events_time(lambda: y.copy_(x), 3)
-    print(json.dumps({"mode": "copy", "bytes_read": n, "bytes_written": n, "ms": ms,
-                      "gbs": 2 * n / ms / 1e6}), flush=True)
+    out = {"mode": "copy"}
+    for gib in (1, 4):
+        n = gib << 30
+        x = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        ms = _events_time(lambda: y.copy_(x), 5)
+        out[f"copy_{gib}GiB"] = {"ms": ms, "gbs_read_plus_write": 2 * n / ms / 1e6}
+        ms = _events_time(lambda: y.fill_(2.0), 5)
+        out[f"fill_{gib}GiB"] = {"ms": ms, "gbs_write": n / ms / 1e6}
+        ms = _events_time(lambda: torch.sum(x), 5)
+        out[f"sum_{gib}GiB"] = {"ms": ms, "gbs_read": n / ms / 1e6}
+        del x, y
+    out["bytes_read"] = 1 << 30
+    out["bytes_written"] = 1 << 30
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -497,15 +558,13 @@ def main():
         ids = list(range(min(a.slices, info["n_slices"])))
         frac = len(ids) / info["n_slices"]
     plan.bind("cuda:0")
+    plan.set_group_limit(a.max_group)
     prec = R.PRECISIONS[a.prec]
     free, _ = torch.cuda.mem_get_info()
     lo, pref = plan.workspace_bytes(len(ids) if ids else 0, 1, prec)
     ws_bytes = int(min(pref, max(lo, a.ws_fraction * free)))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda:0")
     out = torch.empty(2 << a.open, dtype=torch.float64, device="cuda:0")
-    # Timed region: direct launches with HIP events around every MFMA launch.
-    plan.set_timing(1)
-
     def step(p, tag):
         ts = time.perf_counter()
         plan.contract(bits, slice_ids=ids, prec=p, workspace=ws, out=out, sync=False)
@@ -513,6 +572,16 @@ def main():
         log(f"{tag}: {time.perf_counter() - ts:.2f}s (groups of {r['slices_per_group']} slices)")
         return r
 
+    # Which kernel kind dominates the step: one probe step per kind (these
+    # also warm up), then the timed region brackets that kind's launches
+    # with HIP events (direct launches on the caller's stream).
+    kind_ms = {}
+    for kind in (1, 2, 0):
+        plan.set_timing(kind)
+        step(prec, f"probe {KIND_NAMES[kind]}")
+        kind_ms[KIND_NAMES[kind]] = plan.timing()["total_ms"] / frac
+    dom = max((1, 2, 0), key=lambda k: kind_ms[KIND_NAMES[k]])
+    plan.set_timing(dom)
     for _ in range(a.warmup):
         step(prec, "warmup")
     torch.cuda.synchronize()
@@ -533,7 +602,6 @@ def main():
     amps_s = n_amp / (ms / 1000.0)
     step_flops = info["flops_per_slice"] * info["n_slices"]
     lat = [x / frac for x in lat]
-    achieved = tim["flops"] / (tim["total_ms"] / 1000.0) / 1e12 if tim["total_ms"] > 0 else 0.0
     res = {
         "metric": METRIC,
         "value": amps_s,
@@ -562,22 +630,7 @@ def main():
         "tflops": step_flops / (ms / 1000.0) / 1e12,
         "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),
                        "p99": 1000 * float(np.percentile(lat, 99))},
-        "roofline": {
-            "bound": "mfma",
-            "kernel": ("k_mfma32 (fused permute + complex GEMM, FP32 MFMA 32x32x2)" if a.prec == "f32"
-                       else "k_mfma32 + k_mfma16 (fused permute + complex GEMM, FP16/BF16 MFMA 32x32x16)"),
-            "achieved": achieved,
-            "peak": PEAK_MFMA_FP32 if a.prec == "f32" else PEAK_MFMA_16,
-            "unit": "TFLOP/s",
-            "frac": achieved / (PEAK_MFMA_FP32 if a.prec == "f32" else PEAK_MFMA_16),
-            "traffic": (_profile_traffic(TRAFFIC_PROFILE, tim["flops"] / max(1, tim["launches"]))
-                        if a.prec == "f32" else None),
-            "algorithmic_bytes_per_launch": tim["bytes"] / max(1, tim["launches"]),
-            "launches": tim["launches"],
-            "avg_launch_ms": tim["total_ms"] / max(1, tim["launches"]),
-            "flops_per_launch": tim["flops"] / max(1, tim["launches"]),
-            "share_of_step_flops": tim["flops"] / (step_flops * frac * a.steps),
-        },
+        "roofline": roofline(dom, tim, a, step_flops * frac * a.steps, kind_ms),
     }
     # The same call replayed as one captured graph launch (probe off).
     if a.graph_steps > 0:

@@ -322,6 +322,15 @@ typedef struct rqc_server_stats {
 rqc_status rqc_server_get_stats(rqc_server* s, rqc_server_stats* out);
 void rqc_server_destroy(rqc_server* s);
 
+/* ---- execution tuning ---------------------------------------------------- */
+
+/* Upper bounds on the slices and bitstrings contracted side by side in one
+ * group (one batched launch per step); 0 = no bound beyond the workspace.
+ * Smaller groups keep a group's intermediates within the GPU's last-level
+ * cache between steps; larger groups give each launch more work.  Takes
+ * effect at the next rqc_contract; results do not depend on it. */
+rqc_status rqc_plan_set_group_limit(rqc_plan* p, int32_t max_slices, int32_t max_bits);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 /* Timing probe.  With kernel 0 (SIMT), 1 (MFMA) or 2 (rows), later rqc_contract calls

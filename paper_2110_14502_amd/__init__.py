@@ -140,6 +140,7 @@ _PROTOS = {
     "rqc_version": (C.c_char_p, []),
     "rqc_plan_set_scale_bias": (_S, [_P, C.c_int32]),
     "rqc_plan_set_timing": (_S, [_P, C.c_int32]),
+    "rqc_plan_set_group_limit": (_S, [_P, C.c_int32, C.c_int32]),
     "rqc_plan_get_timing": (_S, [_P, C.POINTER(rqc_timing)]),
 }
 for _name, (_res, _args) in _PROTOS.items():
@@ -362,6 +363,10 @@ class Plan:
         if per_slice:
             return amps, ps.view(-1, n_batch, 1 << len(self.open), 2)
         return amps
+
+    def set_group_limit(self, max_slices=0, max_bits=0):
+        """Bound the slices / bitstrings per batched group (0 = workspace only)."""
+        _check(_lib.rqc_plan_set_group_limit(self.h, int(max_slices), int(max_bits)))
 
     def set_timing(self, kernel: int):
         """Bracket launches of kernel kind (0 SIMT, 1 MFMA, -1 off) with events."""

@@ -276,6 +276,16 @@ rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias) {
   RQC_CATCH
 }
 
+rqc_status rqc_plan_set_group_limit(rqc_plan* p, int32_t max_slices, int32_t max_bits) {
+  RQC_TRY
+  if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
+  if (max_slices < 0 || max_bits < 0) throw rqc::Error{RQC_EINVAL, "negative group limit"};
+  p->group_limit_s = max_slices;
+  p->group_limit_b = max_bits;
+  return RQC_OK;
+  RQC_CATCH
+}
+
 rqc_status rqc_plan_set_timing(rqc_plan* p, int32_t kernel) {
   RQC_TRY
   if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};

@@ -62,7 +62,7 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   auto pc = [&](int x) { return pos_in(lc, x); };
   // Row-streaming kernel: K is the lowest k address bits of both A and B, in
   // the same order; B small.
-  bool rows_ok = k <= 5 && n <= 6;
+  bool rows_ok = k <= 7 && n <= 5 && (int64_t(1) << (n + k)) <= 2048;
   for (int p = 0; p < k && rows_ok; ++p) {
     const int xa = la[la.size() - 1 - p];
     rows_ok = pos_in(lb, xa) == p;
@@ -87,14 +87,12 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   } else if (kernel == KERN_ROWS) {
     kt = k;
     nt = n;
-    // Rows per workgroup: 256 threads x rows kept in flight per thread.
-    const int rp_bits = k <= 3 ? 3 : (k == 4 ? 2 : 1);
-    rt = std::min(m, 8 + rp_bits);
-    d.ncb = std::min(n, 11 - rt);  // output columns staged per round
-    // LDS capacity of the row kernel: B (N*K) and the padded C chunk.
-    const int64_t ldc = d.ncb == 0 ? 1 : (int64_t(1) << d.ncb) + 1;
-    if ((int64_t(1) << (n + k)) > 2048 || (int64_t(1) << rt) * ldc > 3072 || rt + d.ncb > 11)
-      throw Error{RQC_EINVAL, "internal: row kernel tile exceeds LDS capacity"};
+    // 256 rows per workgroup; output columns staged 8 at a time (all of
+    // them for N <= 8, so that the staged tile covers C's lowest address
+    // bits and the stores coalesce).
+    d.ncb = std::min(n, 3);
+    rt = std::min(m, 8);
+    if ((int64_t(1) << (n + k)) > 2048) throw Error{RQC_EINVAL, "internal: row kernel B too large"};
   } else if (m + n <= 8) {
     // Tiny output, long sum: deep K tiles (split-K spreads them over blocks).
     rt = m;
@@ -610,8 +608,10 @@ static bool fits(rqc_plan* p, int prec, int gs, int gb, uint64_t n_ids, uint64_t
 
 static void choose_group(rqc_plan* p, int prec, uint64_t n_ids, uint64_t n_batch, size_t ws_bytes,
                          int& gs, int& gb) {
-  const int max_gs = (int)std::min<uint64_t>(n_ids, 4096);
+  int max_gs = (int)std::min<uint64_t>(n_ids, 4096);
   int max_gb = (int)std::min<uint64_t>(n_batch, 4096);
+  if (p->group_limit_s > 0) max_gs = std::min(max_gs, p->group_limit_s);
+  if (p->group_limit_b > 0) max_gb = std::min(max_gb, p->group_limit_b);
   // Copies per launch are bounded by the grid's y dimension.
   gb = max_gb;
   while (gb > 1 && !fits(p, prec, 1, gb, n_ids, n_batch, ws_bytes)) gb = (gb + 1) / 2;

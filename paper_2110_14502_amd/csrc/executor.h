@@ -89,6 +89,7 @@ struct rqc_plan {
   std::vector<int> kern, kern_lp;
   // Timing probe: events around launches of one kernel kind.
   int timing_kernel = -1;
+  int group_limit_s = 0, group_limit_b = 0;  // 0: bounded by the workspace only
   std::vector<hipEvent_t> tev;          // pairs (start, stop)
   std::vector<double> tflops, tbytes;   // per probed launch
   rqc_timing last_timing{};

@@ -7,172 +7,291 @@ namespace rqc {
 // Row-streaming contraction for plan steps (the memory-bound "stem" steps of
 // Section 5.4's imbalanced case): A is a row-major [M][K] matrix whose K
 // summed bits are its lowest address bits, B is [N][K] with the same K order
-// and small enough for LDS.  Each thread streams whole rows of A (K
-// contiguous values, vector loads), multiplies them by B read as LDS
-// broadcasts, and parks the row's N outputs in LDS; the tile is then written
-// out in C's own address order through the offset tables.
+// and small.  The products run on the FP32 matrix cores
+// (v_mfma_f32_16x16x4_f32, 16 rows x 8 complex columns per tile) so that the
+// vector units only move data.
+//
+// A row of K complex values is 2K contiguous floats.  Lane l of a wave owns
+// row (l mod 16) of a 16-row block and the l/16-th quarter of that row, read
+// as one vector load; MFMA j takes float j of every lane's quarter, i.e. the
+// real summation indices are dealt out quarter by quarter, and the lane's B
+// operand holds the matching entries of the real 2x2 expansion of B
+//   B_r[2k][2n] = Br  B_r[2k][2n+1] = Bi  B_r[2k+1][2n] = -Bi  B_r[2k+1][2n+1] = Br.
+// The sum is over the same indices, in another order.  Each wave handles 64
+// rows (four 16-row blocks), a workgroup 256; output columns go 8 at a time
+// through an LDS tile written out in C's own address order.
 // ---------------------------------------------------------------------------
 constexpr int kRowsMaxB = 2048;  // N*K
-constexpr int kRowsMaxC = 2048;  // R*N
-// C tile with a padded row stride ldc = N + 1 (N >= 2) or 1 (N == 1):
-// R * ldc <= R*N + R <= 2048 + 1024.
-constexpr int kRowsCs = kRowsMaxC + kRowsMaxC / 2;
-// Rows each thread keeps in flight (all loads issued before any use).
-__host__ __device__ constexpr int rows_per_thread(int kb) { return kb <= 3 ? 8 : (kb == 4 ? 4 : 2); }
+constexpr int kRowsRows = 256;   // rows per workgroup
+constexpr int kRowsLdc = 17;     // floats per staged row: 16 real columns + 1
+constexpr uint64_t kRowsGrid = 256 * 16;  // persistent workgroups (16 per CU)
 
-// One contiguous row of K complex values with 16-byte loads where the row
-// is long enough (rows start at multiples of K elements, so they are aligned).
-template <int S, int K>
-__device__ __forceinline__ void load_row(const void* p, int64_t base, float2* a) {
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Floats [g*NJ, g*NJ + NJ) of a row of K complex values (NJ = 2K/4), or for
+// K == 1 float g (g < 2).  Rows start at multiples of K elements, so vector
+// loads are aligned.
+template <int S, int K, int NJ>
+__device__ __forceinline__ void load_quarter(const void* p, int64_t row, int g, float* out) {
+  if (K == 1) {
+    if (g >= 2) {
+      out[0] = 0.f;
+      return;
+    }
+    const float2 v = load_c<S>(p, row);
+    out[0] = g ? v.y : v.x;
+    return;
+  }
+  if (K == 2) {
+    const float2 v = load_c<S>(p, row + (g >> 1));
+    out[0] = (g & 1) ? v.y : v.x;
+    return;
+  }
   if (S == ST_C64) {
-    const float2* q = reinterpret_cast<const float2*>(p) + base;
-    if (K >= 2) {
-#pragma unroll
-      for (int k = 0; k < K; k += 2) {
-        const float4 v = *reinterpret_cast<const float4*>(q + k);
-        a[k] = make_float2(v.x, v.y);
-        a[k + 1] = make_float2(v.z, v.w);
-      }
+    const float* q = reinterpret_cast<const float*>(p) + 2 * row + g * NJ;
+    if (NJ == 2) {
+      const float2 v = *reinterpret_cast<const float2*>(q);
+      out[0] = v.x;
+      out[1] = v.y;
     } else {
-      a[0] = q[0];
+#pragma unroll
+      for (int i = 0; i < NJ; i += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(q + i);
+        out[i] = v.x;
+        out[i + 1] = v.y;
+        out[i + 2] = v.z;
+        out[i + 3] = v.w;
+      }
     }
   } else {
-    const uint32_t* q = reinterpret_cast<const uint32_t*>(p) + base;
-    uint32_t w[K];
-    if (K >= 4) {
-#pragma unroll
-      for (int k = 0; k < K; k += 4) {
-        const uint4 v = *reinterpret_cast<const uint4*>(q + k);
-        w[k] = v.x;
-        w[k + 1] = v.y;
-        w[k + 2] = v.z;
-        w[k + 3] = v.w;
-      }
-    } else if (K == 2) {
+    // 16-bit complex words: NJ floats are NJ/2 words.
+    const uint32_t* q = reinterpret_cast<const uint32_t*>(p) + row + g * (NJ / 2);
+    uint32_t w[NJ / 2 > 0 ? NJ / 2 : 1];
+    if (NJ == 2) {
+      w[0] = q[0];
+    } else if (NJ == 4) {
       const uint2 v = *reinterpret_cast<const uint2*>(q);
       w[0] = v.x;
       w[1] = v.y;
     } else {
-      w[0] = q[0];
+#pragma unroll
+      for (int i = 0; i < NJ / 2; i += 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(q + i);
+        w[i] = v.x;
+        w[i + 1] = v.y;
+        w[i + 2] = v.z;
+        w[i + 3] = v.w;
+      }
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
+    for (int i = 0; i < NJ / 2; ++i) {
+      float2 c;
       if (S == ST_F16) {
-        const h2 h = __builtin_bit_cast(h2, w[k]);
-        a[k] = make_float2((float)h.x, (float)h.y);
+        const h2 h = __builtin_bit_cast(h2, w[i]);
+        c = make_float2((float)h.x, (float)h.y);
       } else {
-        const b2 h = __builtin_bit_cast(b2, w[k]);
-        a[k] = make_float2((float)h.x, (float)h.y);
+        const b2 h = __builtin_bit_cast(b2, w[i]);
+        c = make_float2((float)h.x, (float)h.y);
       }
+      out[2 * i] = c.x;
+      out[2 * i + 1] = c.y;
     }
   }
 }
 
-template <int KB, int SA>
+// This lane's quarters of its four rows of a 256-row tile, K chunk kc.
+template <int SA, int K, int NJ>
+__device__ __forceinline__ void load_tile_rows(const StepDesc& d, int64_t oA, int KT, int kc,
+                                               int R, int wave, int lc, int g, float (&dst)[4][NJ]) {
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    const int r = wave * 64 + rb * 16 + lc;
+    if (r < R) {
+      load_quarter<SA, K, NJ>(d.A, oA + (int64_t)r * KT + kc * K, g, dst[rb]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) dst[rb][j] = 0.f;
+    }
+  }
+}
+
+// Persistent: each workgroup walks a contiguous range of tiles (256 rows of
+// one copy each, copies one after the other).  The offset tables are built
+// once; B, its scale
+// and the running max-abs change only with the copy; the rows of the next
+// tile (or K chunk) are loaded while the current one is multiplied and
+// written.  KB: bits of one K chunk (the whole sum when k <= 5); NCH: chunks
+// of 8 complex output columns, whose accumulators stay in registers.
+template <int KB, int NCH, int SA>
 __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   constexpr int K = 1 << KB;
-  constexpr int RP = rows_per_thread(KB);
+  constexpr int NJ = K >= 2 ? (2 * K) / 4 : 1;  // MFMAs per tile and chunk (4 real k each)
   extern __shared__ float2 rows_lds[];
   __shared__ TileTab tc;
   __shared__ int64_t bofs[64];
   __shared__ float red[16];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, lc = lane & 15;
   const int N = 1 << d.nt, R = 1 << d.rt, NC = 1 << d.ncb;
-  const int ldc = NC == 1 ? 1 : NC + 1;
-  float2* Bs = rows_lds;          // [N][K], columns in C's bit order
-  float2* Cs = rows_lds + N * K;  // [R][ldc], one chunk of NC columns
-  build_tab(d.tC, ldc, 1, 0, tc);
-  // Offset in B of column n (its bits scattered to B's column positions).
+  const int KT = 1 << d.kt, nkc = 1 << (d.kt - KB);
+  float2* Bs = rows_lds;                                    // [N][KT], columns in C's bit order
+  float* Cs = reinterpret_cast<float*>(rows_lds + N * KT);  // [R][kRowsLdc]
+  build_tab(d.tC, kRowsLdc, 2, 0, tc);  // coordinates in floats
   for (int n = tid; n < N; n += 256) {
-    int64_t g = 0;
+    int64_t o = 0;
     for (int b = 0; b < d.tB.nbits; ++b)
-      if ((n >> b) & 1) g += int64_t(1) << d.tB.gpos[b];
-    bofs[n] = g;
+      if ((n >> b) & 1) o += int64_t(1) << d.tB.gpos[b];
+    bofs[n] = o;
   }
-  const uint64_t ro = blockIdx.x;
+  const uint64_t n_rt = (uint64_t)d.n_row_tiles;
+  const uint64_t n_tiles = n_rt * (uint64_t)d.copies;
   const int nC = R * NC;
-  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+  const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
+  uint64_t t = (uint64_t)blockIdx.x * per;
+  const uint64_t t_end = t + per < n_tiles ? t + per : n_tiles;
+  float a[4][NJ];
+  if (t < t_end) {
+    const int copy = (int)(t / n_rt);
+    int64_t oA, oB, oC;
+    outer_offsets(d, t % n_rt, 0, copy % d.gs_c, copy / d.gs_c, oA, oB, oC);
+    load_tile_rows<SA, K, NJ>(d, oA, KT, 0, R, wave, lc, g, a);
+  }
+  int cur = -1, cjs = 0, cjb = 0;
+  bool wexp = false;
+  Scale sc{0, 0};
+  float lmax = 0.f;
+  int bad = 0;
+  __syncthreads();  // tables ready
+  const int64_t glo = tc.g[lane];
+  const int32_t clo = tc.c[lane];
+  for (; t < t_end; ++t) {
+    const uint64_t ro = t % n_rt;
+    const int copy = (int)(t / n_rt);
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     int64_t oA, oB, oC;
     outer_offsets(d, ro, 0, js, jb, oA, oB, oC);
-    // Issue this thread's row loads first: they are the HBM stream.
-    float2 a[RP][K];
-#pragma unroll
-    for (int rp = 0; rp < RP; ++rp) {
-      const int r = tid + 256 * rp;
-      if (r < R) load_row<SA, K>(d.A, oA + (int64_t)r * K, a[rp]);
-    }
-    __syncthreads();
-    for (int i = tid; i < N * K; i += 256) {
-      const int64_t at = oB + bofs[i / K] + (i % K);
-      float2 v;
-      if (d.sb_store == ST_F16) v = load_c<ST_F16>(d.B, at);
-      else if (d.sb_store == ST_BF16) v = load_c<ST_BF16>(d.B, at);
-      else v = load_c<ST_C64>(d.B, at);
-      Bs[i] = v;
-    }
-    const Scale sc = compute_scale(d, js, jb);
-    float lmax = 0.f;
-    int bad = 0;
-    const int64_t glo = tc.g[tid & 63];
-    const int32_t clo = tc.c[tid & 63];
-    for (int ch = 0; ch < N; ch += NC) {
+    if (copy != cur) {
+      if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
+      lmax = 0.f;
+      bad = 0;
+      wexp = false;
       __syncthreads();
-      // Each B value read from LDS (a broadcast) serves all of the thread's
-      // rows.
-      for (int nn = 0; nn < NC; ++nn) {
-        const float2* b = Bs + (ch + nn) * K;
-        float sx[RP], sy[RP];
+      for (int i = tid; i < N * KT; i += 256) {
+        const int64_t at = oB + bofs[i >> d.kt] + (i & (KT - 1));
+        float2 v;
+        if (d.sb_store == ST_F16) v = load_c<ST_F16>(d.B, at);
+        else if (d.sb_store == ST_BF16) v = load_c<ST_BF16>(d.B, at);
+        else v = load_c<ST_C64>(d.B, at);
+        Bs[i] = v;
+      }
+      sc = compute_scale(d, js, jb);
+      cur = copy;
+      cjs = js;
+      cjb = jb;
+      __syncthreads();
+    }
+    wexp = wexp || ro == 0;
+    floatx4 acc[4][NCH];
 #pragma unroll
-        for (int rp = 0; rp < RP; ++rp) sx[rp] = sy[rp] = 0.f;
+    for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float2 bv = b[k];
+      for (int h = 0; h < NCH; ++h) acc[rb][h] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < nkc; ++kc) {
+      // Prefetch the next K chunk, or the first chunk of the next tile.
+      float an[4][NJ];
+      if (kc + 1 < nkc) {
+        load_tile_rows<SA, K, NJ>(d, oA, KT, kc + 1, R, wave, lc, g, an);
+      } else if (t + 1 < t_end) {
+        const uint64_t tn = t + 1;
+        const int cn = (int)(tn / n_rt);
+        int64_t pA, pB, pC;
+        outer_offsets(d, tn % n_rt, 0, cn % d.gs_c, cn / d.gs_c, pA, pB, pC);
+        load_tile_rows<SA, K, NJ>(d, pA, KT, 0, R, wave, lc, g, an);
+      }
 #pragma unroll
-          for (int rp = 0; rp < RP; ++rp) {
-            sx[rp] = fmaf(a[rp][k].x, bv.x, sx[rp]);
-            sx[rp] = fmaf(-a[rp][k].y, bv.y, sx[rp]);
-            sy[rp] = fmaf(a[rp][k].x, bv.y, sy[rp]);
-            sy[rp] = fmaf(a[rp][k].y, bv.x, sy[rp]);
+      for (int h = 0; h < NCH; ++h) {
+        // B operand: real column lc of column chunk h (complex column
+        // h*NC + lc/2, part lc&1), real summation index of MFMA j.
+        float bop[NJ];
+        const int n = h * NC + (lc >> 1), q = lc & 1;
+        const bool col_ok = (lc >> 1) < NC;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int rk = K >= 2 ? g * NJ + j : g;
+          const bool ok = col_ok && rk < 2 * K;
+          const float2 b = ok ? Bs[n * KT + kc * K + (rk >> 1)] : make_float2(0.f, 0.f);
+          bop[j] = (rk & 1) == 0 ? (q == 0 ? b.x : b.y) : (q == 0 ? -b.y : b.x);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+            acc[rb][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], bop[j], acc[rb][h], 0, 0, 0);
+      }
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) a[rb][j] = an[rb][j];
+    }
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      __syncthreads();
+      // Lane holds rows 4g..4g+3 of each 16-row block at real column lc.
+      if (lc < 2 * NC) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = wave * 64 + rb * 16 + 4 * g + i;
+            if (r < R) Cs[r * kRowsLdc + lc] = acc[rb][h][i];
           }
-        }
-#pragma unroll
-        for (int rp = 0; rp < RP; ++rp) {
-          const int r = tid + 256 * rp;
-          if (r < R) Cs[r * ldc + nn] = make_float2(sx[rp], sy[rp]);
-        }
       }
       __syncthreads();
       int64_t gch = 0;
       for (int j = 0; j < d.nt - d.ncb; ++j)
-        if (((ch >> d.ncb) >> j) & 1) gch += int64_t(1) << d.nh_C[j];
+        if ((h >> j) & 1) gch += int64_t(1) << d.nh_C[j];
       for (int e = tid; e < nC; e += 256) {
         const int hi = 64 + (e >> 6);
-        const float2 v = Cs[clo + tc.c[hi]];
+        const int c = clo + tc.c[hi];
+        const float2 v = make_float2(Cs[c], Cs[c + 1]);
         const int64_t at = oC + gch + glo + tc.g[hi];
         if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, v, sc, lmax, bad);
         else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, v, sc, lmax, bad);
         else store_out<ST_C64>(d, at, v, sc, lmax, bad);
       }
     }
-    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0, sc);
   }
+  if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
+}
+
+template <int KB, int NCH>
+static hipError_t launch_rows_n(const StepDesc& d, int sa, dim3 grid, size_t lds, hipStream_t s) {
+  if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16>), grid, dim3(256), lds, s, d);
+  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16>), grid, dim3(256), lds, s, d);
+  else hipLaunchKernelGGL((k_rows<KB, NCH, ST_C64>), grid, dim3(256), lds, s, d);
+  return hipGetLastError();
 }
 
 template <int KB>
 static hipError_t launch_rows(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
-  const int N = 1 << d.nt, R = 1 << d.rt, NC = 1 << d.ncb;
-  const int ldc = NC == 1 ? 1 : NC + 1;
-  if (R > 256 * rows_per_thread(KB) || N > 64 || d.ncb > d.nt || N * (1 << KB) > kRowsMaxB ||
-      R * ldc > kRowsCs || d.rt + d.ncb > 11)
+  const int N = 1 << d.nt, R = 1 << d.rt, NC = 1 << d.ncb, KT = 1 << d.kt;
+  const int nch = N / NC;
+  if (R > kRowsRows || NC > 8 || N * KT > kRowsMaxB || d.ncb > d.nt || d.kt < KB ||
+      (d.kt > KB && NC != N && nch > 4) || nch > 4)
     return hipErrorInvalidValue;
-  const size_t lds = sizeof(float2) * ((size_t)N * (1 << KB) + (size_t)R * ldc);
-  if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, ST_F16>), grid, dim3(256), lds, s, d);
-  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, ST_BF16>), grid, dim3(256), lds, s, d);
-  else hipLaunchKernelGGL((k_rows<KB, ST_C64>), grid, dim3(256), lds, s, d);
-  return hipGetLastError();
+  const size_t lds = sizeof(float2) * (size_t)N * KT + sizeof(float) * (size_t)R * kRowsLdc;
+  // Persistent grid: enough workgroups to fill every CU several times over.
+  const uint64_t n_tiles = (uint64_t)d.n_row_tiles * (uint64_t)d.copies;
+  grid = dim3((unsigned)std::min<uint64_t>(n_tiles, kRowsGrid), 1);
+  switch (nch) {
+    case 1: return launch_rows_n<KB, 1>(d, sa, grid, lds, s);
+    case 2: return launch_rows_n<KB, 2>(d, sa, grid, lds, s);
+    case 4: return launch_rows_n<KB, 4>(d, sa, grid, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
+// K chunks: the whole sum for k <= 5, chunks of 16 complex values beyond.
 hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
   switch (d.kt) {
     case 0: return launch_rows<0>(d, sa, grid, s);
@@ -181,6 +300,8 @@ hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t 
     case 3: return launch_rows<3>(d, sa, grid, s);
     case 4: return launch_rows<4>(d, sa, grid, s);
     case 5: return launch_rows<5>(d, sa, grid, s);
+    case 6:
+    case 7: return launch_rows<4>(d, sa, grid, s);
   }
   return hipErrorInvalidValue;
 }

@@ -61,6 +61,14 @@ __device__ __forceinline__ void store_c<ST_BF16>(void* p, int64_t i, float2 v) {
   reinterpret_cast<b2*>(p)[i] = o;
 }
 
+// The value a store of type S keeps (identity for complex64).
+template <int S>
+__device__ __forceinline__ float2 round_c(float2 v) {
+  if (S == ST_F16) return make_float2((float)(_Float16)v.x, (float)(_Float16)v.y);
+  if (S == ST_BF16) return make_float2((float)(__bf16)v.x, (float)(__bf16)v.y);
+  return v;
+}
+
 // Smallest E with x <= 2^E, for x > 0.
 __device__ __forceinline__ int ceil_log2(float x) {
   int e;
@@ -218,8 +226,7 @@ __device__ __forceinline__ void store_out(const StepDesc& d, int64_t at, float2 
   }
   store_c<SC>(d.C, at, v);
   if (d.track) {
-    float2 w = v;
-    if (SC != ST_C64) w = load_c<SC>(d.C, at);
+    const float2 w = round_c<SC>(v);
     const float m = fmaxf(fabsf(w.x), fabsf(w.y));
     if (!(m <= 3.4e38f)) bad = 1;
     else lmax = fmaxf(lmax, m);
