@@ -172,6 +172,10 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
     for (int j = 0; j < d.ncb; ++j) bcr.push_back({Nt[j], 1});
     tile(d.tC, bcr, pc);
     for (int j = d.ncb; j < n; ++j) d.nh_C[j - d.ncb] = (int8_t)pc(Nt[j]);
+    // Vector stores need C's two lowest address bits to be the tile's
+    // lowest bits, and whole groups of four per thread.
+    d.vec_c = (d.tC.nbits >= 2 && d.tC.gpos[0] == 0 && d.tC.gpos[1] == 1 &&
+               d.tC.nbits >= 8) ? 1 : 0;
   }
   d.rt = rt;
   d.nt = nt;

@@ -28,89 +28,103 @@ constexpr uint64_t kRowsGrid = 256 * 16;  // persistent workgroups (16 per CU)
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Floats [g*NJ, g*NJ + NJ) of a row of K complex values (NJ = 2K/4), or for
-// K == 1 float g (g < 2).  Rows start at multiples of K elements, so vector
-// loads are aligned.
+// Raw words of this lane's quarter of a row of K complex values: floats
+// [g*NJ, g*NJ + NJ) (NJ = 2K/4), or for K <= 2 the complex value holding
+// float g.  Kept raw while in flight and converted only when multiplied, so
+// that a prefetch does not wait for its data.  Rows start at multiples of K
+// elements, so vector loads are aligned.
 template <int S, int K, int NJ>
-__device__ __forceinline__ void load_quarter(const void* p, int64_t row, int g, float* out) {
-  if (K == 1) {
-    if (g >= 2) {
-      out[0] = 0.f;
+struct RawRow {
+  static constexpr int W = S == ST_C64 ? (K <= 2 ? 2 : NJ) : (K <= 2 ? 1 : NJ / 2);
+  uint32_t w[W];
+};
+
+template <int S, int K, int NJ>
+__device__ __forceinline__ void load_raw(const void* p, int64_t row, int g, RawRow<S, K, NJ>& r) {
+  if (K <= 2) {
+    const int64_t at = row + (K == 2 ? (g >> 1) : 0);
+    if (K == 1 && g >= 2) {
+#pragma unroll
+      for (int i = 0; i < RawRow<S, K, NJ>::W; ++i) r.w[i] = 0u;
       return;
     }
-    const float2 v = load_c<S>(p, row);
-    out[0] = g ? v.y : v.x;
+    if (S == ST_C64) {
+      const uint2 v = reinterpret_cast<const uint2*>(p)[at];
+      r.w[0] = v.x;
+      r.w[RawRow<S, K, NJ>::W - 1] = v.y;
+    } else {
+      r.w[0] = reinterpret_cast<const uint32_t*>(p)[at];
+    }
     return;
   }
-  if (K == 2) {
-    const float2 v = load_c<S>(p, row + (g >> 1));
-    out[0] = (g & 1) ? v.y : v.x;
+  constexpr int W = RawRow<S, K, NJ>::W;
+  const uint32_t* q = reinterpret_cast<const uint32_t*>(p) + (S == ST_C64 ? 2 * row : row) + g * W;
+  if (W == 1) {
+    r.w[0] = q[0];
+  } else if (W == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(q);
+    r.w[0] = v.x;
+    r.w[1] = v.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; i += 4) {
+      const uint4 v = *reinterpret_cast<const uint4*>(q + i);
+      r.w[i] = v.x;
+      r.w[i + 1] = v.y;
+      r.w[i + 2] = v.z;
+      r.w[i + 3] = v.w;
+    }
+  }
+}
+
+template <int S>
+__device__ __forceinline__ float2 unpack_word(uint32_t w) {
+  if (S == ST_F16) {
+    const h2 h = __builtin_bit_cast(h2, w);
+    return make_float2((float)h.x, (float)h.y);
+  }
+  const b2 h = __builtin_bit_cast(b2, w);
+  return make_float2((float)h.x, (float)h.y);
+}
+
+template <int S, int K, int NJ>
+__device__ __forceinline__ void unpack_raw(const RawRow<S, K, NJ>& r, int g, float (&out)[NJ]) {
+  if (K <= 2) {
+    if (S == ST_C64) {
+      out[0] = __uint_as_float((g & 1) ? r.w[1] : r.w[0]);
+    } else {
+      const float2 c = unpack_word<S>(r.w[0]);
+      out[0] = (g & 1) ? c.y : c.x;
+    }
     return;
   }
   if (S == ST_C64) {
-    const float* q = reinterpret_cast<const float*>(p) + 2 * row + g * NJ;
-    if (NJ == 2) {
-      const float2 v = *reinterpret_cast<const float2*>(q);
-      out[0] = v.x;
-      out[1] = v.y;
-    } else {
 #pragma unroll
-      for (int i = 0; i < NJ; i += 4) {
-        const float4 v = *reinterpret_cast<const float4*>(q + i);
-        out[i] = v.x;
-        out[i + 1] = v.y;
-        out[i + 2] = v.z;
-        out[i + 3] = v.w;
-      }
-    }
+    for (int j = 0; j < NJ; ++j) out[j] = __uint_as_float(r.w[j]);
   } else {
-    // 16-bit complex words: NJ floats are NJ/2 words.
-    const uint32_t* q = reinterpret_cast<const uint32_t*>(p) + row + g * (NJ / 2);
-    uint32_t w[NJ / 2 > 0 ? NJ / 2 : 1];
-    if (NJ == 2) {
-      w[0] = q[0];
-    } else if (NJ == 4) {
-      const uint2 v = *reinterpret_cast<const uint2*>(q);
-      w[0] = v.x;
-      w[1] = v.y;
-    } else {
-#pragma unroll
-      for (int i = 0; i < NJ / 2; i += 4) {
-        const uint4 v = *reinterpret_cast<const uint4*>(q + i);
-        w[i] = v.x;
-        w[i + 1] = v.y;
-        w[i + 2] = v.z;
-        w[i + 3] = v.w;
-      }
-    }
 #pragma unroll
     for (int i = 0; i < NJ / 2; ++i) {
-      float2 c;
-      if (S == ST_F16) {
-        const h2 h = __builtin_bit_cast(h2, w[i]);
-        c = make_float2((float)h.x, (float)h.y);
-      } else {
-        const b2 h = __builtin_bit_cast(b2, w[i]);
-        c = make_float2((float)h.x, (float)h.y);
-      }
+      const float2 c = unpack_word<S>(r.w[i]);
       out[2 * i] = c.x;
       out[2 * i + 1] = c.y;
     }
   }
 }
 
-// This lane's quarters of its four rows of a 256-row tile, K chunk kc.
+// This lane's raw quarters of its four rows of a 256-row tile, K chunk kc
+// (zeros past the tile's rows).
 template <int SA, int K, int NJ>
 __device__ __forceinline__ void load_tile_rows(const StepDesc& d, int64_t oA, int KT, int kc,
-                                               int R, int wave, int lc, int g, float (&dst)[4][NJ]) {
+                                               int R, int wave, int lc, int g,
+                                               RawRow<SA, K, NJ> (&dst)[4]) {
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     const int r = wave * 64 + rb * 16 + lc;
     if (r < R) {
-      load_quarter<SA, K, NJ>(d.A, oA + (int64_t)r * KT + kc * K, g, dst[rb]);
+      load_raw<SA, K, NJ>(d.A, oA + (int64_t)r * KT + kc * K, g, dst[rb]);
     } else {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) dst[rb][j] = 0.f;
+      for (int i = 0; i < RawRow<SA, K, NJ>::W; ++i) dst[rb].w[i] = 0u;
     }
   }
 }
@@ -129,11 +143,23 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   extern __shared__ float2 rows_lds[];
   __shared__ TileTab tc;
   __shared__ int64_t bofs[64];
+  __shared__ int64_t stepA[kMaxOuter], stepC[kMaxOuter];
   __shared__ float red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, lc = lane & 15;
   const int N = 1 << d.nt, R = 1 << d.rt, NC = 1 << d.ncb;
   const int KT = 1 << d.kt, nkc = 1 << (d.kt - KB);
+  // Row tile ro -> ro + 1 sets the lowest zero bit b of ro and clears the
+  // bits below it: the offsets move by stepA[b] / stepC[b].
+  for (int b = tid; b < d.n_ro; b += 256) {
+    int64_t sa = int64_t(1) << d.ro_A[b], sc = int64_t(1) << d.ro_C[b];
+    for (int j = 0; j < b; ++j) {
+      sa -= int64_t(1) << d.ro_A[j];
+      sc -= int64_t(1) << d.ro_C[j];
+    }
+    stepA[b] = sa;
+    stepC[b] = sc;
+  }
   float2* Bs = rows_lds;                                    // [N][KT], columns in C's bit order
   float* Cs = reinterpret_cast<float*>(rows_lds + N * KT);  // [R][kRowsLdc]
   build_tab(d.tC, kRowsLdc, 2, 0, tc);  // coordinates in floats
@@ -149,7 +175,7 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
   uint64_t t = (uint64_t)blockIdx.x * per;
   const uint64_t t_end = t + per < n_tiles ? t + per : n_tiles;
-  float a[4][NJ];
+  RawRow<SA, K, NJ> a[4], an[4];
   if (t < t_end) {
     const int copy = (int)(t / n_rt);
     int64_t oA, oB, oC;
@@ -164,12 +190,18 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   __syncthreads();  // tables ready
   const int64_t glo = tc.g[lane];
   const int32_t clo = tc.c[lane];
+  int64_t oA = 0, oB = 0, oC = 0;
   for (; t < t_end; ++t) {
     const uint64_t ro = t % n_rt;
     const int copy = (int)(t / n_rt);
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
-    int64_t oA, oB, oC;
-    outer_offsets(d, ro, 0, js, jb, oA, oB, oC);
+    if (copy != cur || ro == 0) {
+      outer_offsets(d, ro, 0, js, jb, oA, oB, oC);
+    } else {
+      const int b = __builtin_ctzll(~(ro - 1));
+      oA += stepA[b];
+      oC += stepC[b];
+    }
     if (copy != cur) {
       if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
       lmax = 0.f;
@@ -197,17 +229,26 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
 #pragma unroll
       for (int h = 0; h < NCH; ++h) acc[rb][h] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < nkc; ++kc) {
-      // Prefetch the next K chunk, or the first chunk of the next tile.
-      float an[4][NJ];
+      // Prefetch the next K chunk, or the first chunk of the next tile; the
+      // registers are handed over only after this chunk (or, for the next
+      // tile, after the stores), so the loads stay in flight meanwhile.
       if (kc + 1 < nkc) {
         load_tile_rows<SA, K, NJ>(d, oA, KT, kc + 1, R, wave, lc, g, an);
       } else if (t + 1 < t_end) {
         const uint64_t tn = t + 1;
-        const int cn = (int)(tn / n_rt);
-        int64_t pA, pB, pC;
-        outer_offsets(d, tn % n_rt, 0, cn % d.gs_c, cn / d.gs_c, pA, pB, pC);
+        int64_t pA;
+        if (tn % n_rt != 0) {
+          pA = oA + stepA[__builtin_ctzll(~ro)];
+        } else {
+          const int cn = (int)(tn / n_rt);
+          int64_t pB, pC;
+          outer_offsets(d, 0, 0, cn % d.gs_c, cn / d.gs_c, pA, pB, pC);
+        }
         load_tile_rows<SA, K, NJ>(d, pA, KT, 0, R, wave, lc, g, an);
       }
+      float af[4][NJ];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) unpack_raw<SA, K, NJ>(a[rb], g, af[rb]);
 #pragma unroll
       for (int h = 0; h < NCH; ++h) {
         // B operand: real column lc of column chunk h (complex column
@@ -226,12 +267,12 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
           for (int j = 0; j < NJ; ++j)
-            acc[rb][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb][j], bop[j], acc[rb][h], 0, 0, 0);
+            acc[rb][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][j], bop[j], acc[rb][h], 0, 0, 0);
       }
+      if (kc + 1 < nkc) {
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) a[rb][j] = an[rb][j];
+        for (int rb = 0; rb < 4; ++rb) a[rb] = an[rb];
+      }
     }
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
@@ -250,16 +291,36 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
       int64_t gch = 0;
       for (int j = 0; j < d.nt - d.ncb; ++j)
         if ((h >> j) & 1) gch += int64_t(1) << d.nh_C[j];
-      for (int e = tid; e < nC; e += 256) {
-        const int hi = 64 + (e >> 6);
-        const int c = clo + tc.c[hi];
-        const float2 v = make_float2(Cs[c], Cs[c + 1]);
-        const int64_t at = oC + gch + glo + tc.g[hi];
-        if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, v, sc, lmax, bad);
-        else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, v, sc, lmax, bad);
-        else store_out<ST_C64>(d, at, v, sc, lmax, bad);
+      if (d.vec_c) {
+        // Four consecutive elements per thread: C addresses at..at+3.
+        for (int v = tid; v < (nC >> 2); v += 256) {
+          const int lo = (v & 15) << 2, hi = 64 + (v >> 4);
+          const int64_t at = oC + gch + tc.g[lo] + tc.g[hi];
+          float2 x[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = tc.c[lo + i] + tc.c[hi];
+            x[i] = make_float2(Cs[c], Cs[c + 1]);
+          }
+          if (d.sc_store == ST_F16) store_out4<ST_F16>(d, at, x, sc, lmax, bad);
+          else if (d.sc_store == ST_BF16) store_out4<ST_BF16>(d, at, x, sc, lmax, bad);
+          else store_out4<ST_C64>(d, at, x, sc, lmax, bad);
+        }
+      } else {
+        for (int e = tid; e < nC; e += 256) {
+          const int hi = 64 + (e >> 6);
+          const int c = clo + tc.c[hi];
+          const float2 v = make_float2(Cs[c], Cs[c + 1]);
+          const int64_t at = oC + gch + glo + tc.g[hi];
+          if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, v, sc, lmax, bad);
+          else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, v, sc, lmax, bad);
+          else store_out<ST_C64>(d, at, v, sc, lmax, bad);
+        }
       }
     }
+    // The next tile's rows (loaded during this tile) become current.
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) a[rb] = an[rb];
   }
   if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
 }

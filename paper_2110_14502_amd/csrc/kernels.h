@@ -63,6 +63,7 @@ struct StepDesc {
   // Row kernel: output columns staged 2^ncb at a time; the remaining column
   // bits (their C positions in nh_C) select the chunk.
   int32_t ncb;
+  int32_t vec_c;      // 1: tile bits 0 and 1 are C's address bits 0 and 1 (4-element stores)
   int8_t nh_C[16];
   int8_t ro_A[kMaxOuter], ro_C[kMaxOuter];
   int8_t no_B[kMaxOuter], no_C[kMaxOuter];

@@ -233,6 +233,50 @@ __device__ __forceinline__ void store_out(const StepDesc& d, int64_t at, float2 
   }
 }
 
+// Four consecutive output elements (C addresses at, at+1, at+2, at+3; at a
+// multiple of 4) in one 16-byte (16-bit storage) or two 16-byte stores.
+template <int SC>
+__device__ __forceinline__ void store_out4(const StepDesc& d, int64_t at, float2 (&v)[4],
+                                           const Scale& sc, float& lmax, int& bad) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (sc.shift) {
+      v[i].x = ldexpf(v[i].x, -sc.shift);
+      v[i].y = ldexpf(v[i].y, -sc.shift);
+    }
+  }
+  if (SC == ST_C64) {
+    float4* q = reinterpret_cast<float4*>(reinterpret_cast<float2*>(d.C) + at);
+    q[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    q[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+  } else {
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (SC == ST_F16) {
+        h2 o;
+        o.x = (_Float16)v[i].x;
+        o.y = (_Float16)v[i].y;
+        w[i] = __builtin_bit_cast(uint32_t, o);
+      } else {
+        b2 o;
+        o.x = (__bf16)v[i].x;
+        o.y = (__bf16)v[i].y;
+        w[i] = __builtin_bit_cast(uint32_t, o);
+      }
+    }
+    *reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(d.C) + at) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  if (d.track) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float2 r = round_c<SC>(v[i]);
+      const float m = fmaxf(fabsf(r.x), fabsf(r.y));
+      if (!(m <= 3.4e38f)) bad = 1;
+      else lmax = fmaxf(lmax, m);
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Tile constants of the MFMA kernels and the C staging table builder.
