@@ -78,8 +78,12 @@ def parse():
     ap.add_argument("--open", type=int, default=6)
     ap.add_argument("--sliced", type=int, default=8)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--trials", type=int, default=4096)
+    ap.add_argument("--trials", type=int, default=1024)
     ap.add_argument("--plan-seed", type=int, default=2)
+    ap.add_argument("--plan-candidates", type=int, default=8,
+                    help="plans searched with seeds plan-seed.. and timed on a sample of "
+                         "slices; the fastest is benchmarked (1 = no selection)")
+    ap.add_argument("--probe-slices", type=int, default=32)
     ap.add_argument("--ws-fraction", type=float, default=0.85)
     ap.add_argument("--slices", type=int, default=0,
                     help="contract only the first N slice ids (profiling); 0 = all")
@@ -170,6 +174,38 @@ def _profile_traffic(kind, flops_per_launch, bytes_per_launch):
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError, ZeroDivisionError):
         return None
+
+
+def select_plan(R, net, bits, a):
+    """Plan autotuning: search plan-candidates plans (planner seeds
+    plan-seed, plan-seed+1, ...), time each on the device on a sample of
+    probe-slices slices (one captured-graph call, after a warm call), and
+    return the seed of the fastest with the measured times."""
+    import torch
+    seeds = [a.plan_seed + i for i in range(max(1, a.plan_candidates))]
+    if len(seeds) == 1:
+        return seeds[0], {"candidates": 1}
+    times = {}
+    for sd in seeds:
+        p = R.Plan(net, n_sliced=a.sliced, path_trials=a.trials, seed=sd)
+        n_ids = min(a.probe_slices, p.info()["n_slices"])
+        p.bind("cuda:0")
+        lo, pref = p.workspace_bytes(n_ids, 1, R.PRECISIONS[a.prec])
+        free, _ = torch.cuda.mem_get_info()
+        ws = torch.empty(int(min(pref, max(lo, 0.5 * free))), dtype=torch.uint8, device="cuda:0")
+        ids = list(range(n_ids))
+        p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[a.prec], workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[a.prec], workspace=ws)
+        torch.cuda.synchronize()
+        times[sd] = 1000.0 * (time.perf_counter() - t0) / n_ids
+        log(f"plan seed {sd}: {times[sd]:.3f} ms per slice on {n_ids} slices")
+        del p, ws
+    best = min(times, key=times.get)
+    return best, {"candidates": len(seeds), "probe_slices": a.probe_slices,
+                  "ms_per_slice_by_seed": {str(k): round(v, 4) for k, v in times.items()},
+                  "chosen_seed": best}
 
 
 def roofline(kind, tim, a, flops_total, kind_ms):
@@ -481,12 +517,18 @@ def share_mode(a):
                               "launches": tim["launches"],
                               "share_of_flops": tim["flops"] / (info["flops_per_slice"] * max(1, n_sl // 8))}}
     plan.set_timing(-1)
+    # Per-slice errors in units of the larger of the checked slices' RMS and
+    # the natural scale of one slice, 2^-(n+S)/2 (S sliced wires in all).
+    n_sliced_all = len(plan.sliced_wires()) + len(plan.fixed_wires())
+    natural = 2.0 ** (-(n + n_sliced_all) / 2)
     for prec in [p for p in precs if p != "f32"]:
         ref, got = vals["f32"][checked], vals[prec][checked]
         rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
         res[prec]["speedup_vs_f32"] = res["f32"]["seconds"] / res[prec]["seconds"]
-        res[prec]["per_slice_error_vs_f32"] = float(np.max(np.abs(got - ref)) / rms) if rms > 0 else None
+        res[prec]["per_slice_error_vs_f32"] = float(np.max(np.abs(got - ref)) / max(rms, natural))
         res[prec]["fidelity_vs_f32"] = _fidelity(got, ref)
+    res["slice_scale"] = {"checked_rms": float(np.sqrt(np.mean(np.abs(vals["f32"][checked]) ** 2))),
+                          "natural": natural}
     lp_precs = [p for p in precs if p != "f32"] or ["f32"]
     best = max(lp_precs, key=lambda p: res[p]["slices_per_s"])
     res["metric"] = "share slices/s (reduced precision) and contraction TFLOP/s"
@@ -545,9 +587,10 @@ def main():
     circ = rqcgen.grid_rqc(a.rows, a.cols, a.depth, a.seed)
     openq = list(range(n - a.open, n))
     bits = rqcgen.random_bits(n - a.open, a.seed)
+    net = R.Network(R.Circuit.from_rqcgen(circ), openq)
     t = time.perf_counter()
-    plan = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), openq), n_sliced=a.sliced,
-                  path_trials=a.trials, seed=a.plan_seed)
+    chosen, probe = select_plan(R, net, bits, a)
+    plan = R.Plan(net, n_sliced=a.sliced, path_trials=a.trials, seed=chosen)
     t_plan = time.perf_counter() - t
     info = plan.info()
     log(f"plan: {t_plan:.1f}s, log2 flops/slice {math.log2(info['flops_per_slice']):.2f}, "
@@ -626,6 +669,7 @@ def main():
             "plan_max_log2_elems": info["max_log2_elems"],
             "plan_steps": info["n_steps"],
             "plan_seconds": round(t_plan, 2),
+            "plan_selection": probe,
         },
         "tflops": step_flops / (ms / 1000.0) / 1e12,
         "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),

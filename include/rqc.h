@@ -135,6 +135,9 @@ typedef struct rqc_plan_opts {
   int32_t n_local_sliced;
   int32_t n_share_bits;
   const uint8_t* share_bits;
+  int32_t restarts;       /* independent searches with seeds derived from
+                             `seed`; the plan with the lowest estimated time
+                             is kept; 0 = 1 */
 } rqc_plan_opts;
 
 void rqc_plan_opts_default(rqc_plan_opts* o);

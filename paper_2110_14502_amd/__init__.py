@@ -47,7 +47,8 @@ class rqc_plan_opts(C.Structure):
                 ("seed", C.c_uint64), ("n_forced", C.c_int32),
                 ("forced_wires", C.POINTER(C.c_int32)), ("lp_min_log2", C.c_int32),
                 ("bf16_min_log2", C.c_int32), ("n_local_sliced", C.c_int32),
-                ("n_share_bits", C.c_int32), ("share_bits", C.POINTER(C.c_uint8))]
+                ("n_share_bits", C.c_int32), ("share_bits", C.POINTER(C.c_uint8)),
+                ("restarts", C.c_int32)]
 
 
 class rqc_plan_info(C.Structure):
@@ -232,7 +233,7 @@ class Plan:
 
     def __init__(self, network: Network, max_log2_elems=0, n_sliced=-1, path_trials=256,
                  reconf_rounds=-1, seed=0, forced_wires=(), lp_min_log2=0, bf16_min_log2=0,
-                 n_local_sliced=0, share_bits=()):
+                 n_local_sliced=0, share_bits=(), restarts=1):
         o = rqc_plan_opts()
         _lib.rqc_plan_opts_default(C.byref(o))
         o.max_log2_elems = int(max_log2_elems)
@@ -249,6 +250,7 @@ class Plan:
         o.n_local_sliced = int(n_local_sliced)
         self._share = (C.c_uint8 * max(1, len(share_bits)))(*[int(b) for b in share_bits])
         o.n_share_bits = len(share_bits)
+        o.restarts = int(restarts)
         o.share_bits = C.cast(self._share, C.POINTER(C.c_uint8))
         h = C.c_void_p()
         _check(_lib.rqc_plan_create(network.h, C.byref(o), C.byref(h)))

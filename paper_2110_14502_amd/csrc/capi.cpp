@@ -139,6 +139,8 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_
     po.lp_min_log2 = o.lp_min_log2 > 0 ? o.lp_min_log2 : 14;
     po.bf16_min_log2 = o.bf16_min_log2 > 0 ? o.bf16_min_log2 : 24;
     po.n_local = o.n_local_sliced;
+    if (o.restarts < 0 || o.restarts > 1024) throw rqc::Error{RQC_EINVAL, "restarts out of range"};
+    po.restarts = o.restarts > 0 ? o.restarts : 1;
     po.share_bits.assign(o.share_bits, o.share_bits + o.n_share_bits);
     for (auto& b : po.share_bits)
       if (b > 1) throw rqc::Error{RQC_EINVAL, "share bits must be 0 or 1"};

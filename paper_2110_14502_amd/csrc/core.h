@@ -90,6 +90,7 @@ struct PlanOpts {
   int bf16_min_log2 = 24;
   int n_local = 0;            // 0: all sliced wires enumerated by slice ids
   std::vector<uint8_t> share_bits;  // values of the fixed sliced wires
+  int restarts = 1;                 // independent searches, best kept
 };
 
 struct Tree {
@@ -103,6 +104,7 @@ struct Tree {
 // contracted: CLOSED selectors and sliced wires removed.
 struct CostModel {
   double flops = 0;   // complex multiply-adds summed over steps
+  double cost = 0;    // time-like cost (multiply-adds or weighted traffic per step)
   int width = 0;      // largest intermediate, log2 elements
 };
 
@@ -138,6 +140,7 @@ struct PlanData {
   double bytes_per_slice = 0;
   int max_log2 = 0;
   std::vector<std::pair<int, int>> pruned;  // single-valued wires projected out: (label, value)
+  double score = 0;                     // search objective of the chosen plan
 };
 
 // Builds everything in PlanData from the network and options.

@@ -169,11 +169,28 @@ static std::vector<LSet> node_sets(const Tree& t, const std::vector<LSet>& leaf_
   return s;
 }
 
+// Time-like cost of one pairwise step, in complex multiply-adds: the larger
+// of its multiply-adds and its mandatory traffic (each operand read once,
+// the output written once) weighted by the GPU's balance of matrix-core
+// rate to HBM rate, about 20 multiply-adds per complex64 element moved.
+// Trees with similar flop counts differ by several times in traffic, and
+// sliced plans are mostly traffic-bound, so the search ranks by this.
+constexpr double kMacsPerElement = 20.0;
+static double step_cost(int un, int sa, int sb, int sc) {
+  const double macs = std::ldexp(1.0, un);
+  const double elems = std::ldexp(1.0, sa) + std::ldexp(1.0, sb) + std::ldexp(1.0, sc);
+  return std::max(macs, kMacsPerElement * elems);
+}
+
 static CostModel tree_cost(const Tree& t, const std::vector<LSet>& s) {
   CostModel c;
   for (int v = t.n_leaves; v < (int)t.left.size(); ++v) {
     if (t.left[v] < 0) continue;
-    c.flops += std::ldexp(1.0, union_size(s[t.left[v]], s[t.right[v]]));
+    const LSet& a = s[t.left[v]];
+    const LSet& b = s[t.right[v]];
+    const int un = union_size(a, b);
+    c.flops += std::ldexp(1.0, un);
+    c.cost += step_cost(un, (int)a.size(), (int)b.size(), (int)s[v].size());
     c.width = std::max(c.width, (int)s[v].size());
   }
   for (int i = 0; i < t.n_leaves; ++i) c.width = std::max(c.width, (int)s[i].size());
@@ -211,7 +228,7 @@ static SliceResult slice_tree(const Tree& t, const std::vector<LSet>& leaf_sets,
     const bool need_width = n_target < 0 && bound > 0 && c.width > bound;
     const bool need_count = n_target >= 0 && (int)r.sliced.size() < n_target;
     if (!need_width && !need_count) break;
-    // savings[x]: flops removed if x is sliced (per slice).
+    // savings[x]: per-slice cost removed if x is sliced.
     std::vector<double> save(n_labels, 0.0);
     std::vector<int> cnt_max(n_labels, 0);
     int n_max = 0;
@@ -223,10 +240,18 @@ static SliceResult slice_tree(const Tree& t, const std::vector<LSet>& leaf_sets,
       if (v < t.n_leaves || t.left[v] < 0) continue;
       const LSet& a = s[t.left[v]];
       const LSet& b = s[t.right[v]];
-      const double f = std::ldexp(1.0, union_size(a, b) - 1);
-      for (int x : a) save[x] += f;
+      const LSet& cc = s[v];
+      const int un = union_size(a, b), sa = (int)a.size(), sb = (int)b.size(), sc = (int)cc.size();
+      const double now = step_cost(un, sa, sb, sc);
+      auto gain = [&](int x) {
+        const int xa = std::binary_search(a.begin(), a.end(), x) ? 1 : 0;
+        const int xb = std::binary_search(b.begin(), b.end(), x) ? 1 : 0;
+        const int xc = std::binary_search(cc.begin(), cc.end(), x) ? 1 : 0;
+        return now - step_cost(un - 1, sa - xa, sb - xb, sc - xc);
+      };
+      for (int x : a) save[x] += gain(x);
       for (int x : b)
-        if (!std::binary_search(a.begin(), a.end(), x)) save[x] += f;
+        if (!std::binary_search(a.begin(), a.end(), x)) save[x] += gain(x);
     }
     int best = -1;
     double best_cost = 0;
@@ -234,7 +259,7 @@ static SliceResult slice_tree(const Tree& t, const std::vector<LSet>& leaf_sets,
     for (int x = 0; x < n_labels; ++x) {
       if (!sliceable[x] || drop[x] || save[x] <= 0) continue;
       const bool reduces = cnt_max[x] == n_max;
-      const double total = (c.flops - save[x]) * 2.0;  // relative: x2 slices
+      const double total = (c.cost - save[x]) * 2.0;  // relative: x2 slices
       bool better;
       if (best < 0) better = true;
       else if (need_width && reduces != best_w) better = reduces;
@@ -310,7 +335,7 @@ static bool reconf_node(Tree& t, std::vector<LSet>& s, int v, int kmax, int widt
       if (sub > o) continue;
       if (best[sub] >= INF || best[o] >= INF) continue;
       const int un = (int)(L[sub] | L[o]).count();
-      const double c = best[sub] + best[o] + std::ldexp(1.0, un);
+      const double c = best[sub] + best[o] + step_cost(un, Lsz[sub], Lsz[o], Lsz[S]);
       if (c < bc) {
         bc = c;
         bs = sub;
@@ -320,7 +345,9 @@ static bool reconf_node(Tree& t, std::vector<LSet>& s, int v, int kmax, int widt
     split[S] = bs;
   }
   double old = 0;
-  for (int f : internal) old += std::ldexp(1.0, union_size(s[t.left[f]], s[t.right[f]]));
+  for (int f : internal)
+    old += step_cost(union_size(s[t.left[f]], s[t.right[f]]), (int)s[t.left[f]].size(),
+                     (int)s[t.right[f]].size(), (int)s[f].size());
   if (!(best[full] < old * (1 - 1e-12))) return false;
   // Rebuild with the old internal ids (v stays the subtree root).
   std::vector<int> pool(internal.begin(), internal.end());
@@ -521,7 +548,7 @@ static std::vector<std::pair<int, int>> prune_constant_wires(Network& net,
   return pruned;
 }
 
-void make_plan(PlanData& p) {
+static void make_plan_once(PlanData& p) {
   Network& net = p.net;
   const int nlab = (int)net.labels.size();
   const int nl = (int)net.leaves.size();
@@ -597,7 +624,7 @@ void make_plan(PlanData& p) {
       const double temp = tr == 0 ? 0.0 : temps[rng() % 6];
       Tree t = greedy_tree(base, nlab, alpha, temp, rng);
       SliceResult sr = slice_tree(t, leaf_sets, nlab, sliceable, given, p.opts.max_log2, n_target);
-      res[tr].score = std::log2(sr.per_slice.flops) + (double)sr.sliced.size() +
+      res[tr].score = std::log2(sr.per_slice.cost) + (double)sr.sliced.size() +
                       width_penalty(sr.per_slice.width);
       res[tr].tree = std::move(t);
       res[tr].sliced = std::move(sr.sliced);
@@ -627,7 +654,7 @@ void make_plan(PlanData& p) {
         ss = node_sets(c.tree, sl);
       }
       const CostModel cm = tree_cost(c.tree, ss);
-      c.score = std::log2(cm.flops) + (double)c.sliced.size() + width_penalty(cm.width);
+      c.score = std::log2(cm.cost) + (double)c.sliced.size() + width_penalty(cm.width);
       c.sets = std::move(ss);
     };
     {
@@ -674,9 +701,9 @@ void make_plan(PlanData& p) {
         sl.erase(sl.begin() + j);
         const CostModel cm = tree_cost(best.tree, node_sets(best.tree, sliced_leaves(sl)));
         if (cm.width > p.opts.max_log2) continue;
-        if (pick < 0 || cm.flops < pick_flops) {
+        if (pick < 0 || cm.cost < pick_flops) {
           pick = j;
-          pick_flops = cm.flops;
+          pick_flops = cm.cost;
         }
       }
       if (pick < 0) break;
@@ -686,7 +713,7 @@ void make_plan(PlanData& p) {
     if (any) {
       best.sets = node_sets(best.tree, sliced_leaves(best.sliced));
       const CostModel cm = tree_cost(best.tree, best.sets);
-      best.score = std::log2(cm.flops) + (double)best.sliced.size() + width_penalty(cm.width);
+      best.score = std::log2(cm.cost) + (double)best.sliced.size() + width_penalty(cm.width);
     }
     return any;
   };
@@ -727,7 +754,33 @@ void make_plan(PlanData& p) {
   }
   p.node_labels = s;
   p.cost = tree_cost(p.tree, s);
+  p.score = std::log2(p.cost.cost) + (double)(p.sliced.size() + p.fixed.size());
   build_steps(p);
+}
+
+void make_plan(PlanData& p) {
+  const int restarts = std::max(1, p.opts.restarts);
+  if (restarts == 1) {
+    make_plan_once(p);
+    return;
+  }
+  // Independent searches; each starts from the unplanned network.
+  const PlanData start = p;
+  bool have = false;
+  for (int r = 0; r < restarts; ++r) {
+    PlanData q = start;
+    q.opts.seed = start.opts.seed + 0x9E3779B97F4A7C15ull * (uint64_t)r;
+    try {
+      make_plan_once(q);
+    } catch (const Error&) {
+      if (r + 1 == restarts && !have) throw;
+      continue;
+    }
+    if (!have || q.score < p.score) {
+      p = std::move(q);
+      have = true;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
