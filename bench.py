@@ -84,6 +84,9 @@ def parse():
                     help="plans searched with seeds plan-seed.. and timed on a sample of "
                          "slices; the fastest is benchmarked (1 = no selection)")
     ap.add_argument("--probe-slices", type=int, default=32)
+    ap.add_argument("--roofline-kernel", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="kernel kind bracketed in the timed region (0 simt, 1 mfma, 2 rows); "
+                         "-1 = the one that takes longest in a probe step")
     ap.add_argument("--ws-fraction", type=float, default=0.85)
     ap.add_argument("--slices", type=int, default=0,
                     help="contract only the first N slice ids (profiling); 0 = all")
@@ -624,6 +627,8 @@ def main():
         step(prec, f"probe {KIND_NAMES[kind]}")
         kind_ms[KIND_NAMES[kind]] = plan.timing()["total_ms"] / frac
     dom = max((1, 2, 0), key=lambda k: kind_ms[KIND_NAMES[k]])
+    if a.roofline_kernel >= 0:
+        dom = a.roofline_kernel
     plan.set_timing(dom)
     for _ in range(a.warmup):
         step(prec, "warmup")

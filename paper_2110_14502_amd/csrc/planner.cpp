@@ -680,7 +680,7 @@ static void make_plan_once(PlanData& p) {
   // are then un-sliced (the total cost never grows: a slice at most doubles).
   const int n_user = (int)forced.size();
   auto research = [&](int round) {
-    const int t2 = std::min(trials, 512);
+    const int t2 = std::max(8, std::min(512, trials / 2));
     bool improved = false;
     for (bool on_sliced : {false, true}) {
       Candidate c = search(best.sliced, (int)best.sliced.size(), 2 * round + on_sliced, t2, on_sliced);

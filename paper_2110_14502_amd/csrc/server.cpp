@@ -188,7 +188,9 @@ bool rqc_server::admit_one() {
       rqc_plan_opts o;
       rqc_plan_opts_default(&o);
       o.max_log2_elems = r0.max_log2 > 0 ? r0.max_log2 : 26;
-      o.path_trials = 64;
+      // Planning sits on the request's latency path: a short search.
+      o.path_trials = 32;
+      o.reconf_rounds = 1;
       o.seed = r0.seed;
       st = rqc_plan_create(n, &o, &p);
     }
@@ -241,12 +243,31 @@ bool rqc_server::admit_one() {
     return true;
   }
   const uint64_t out_bytes = 16ull * nb << r0.open.size();
-  char* out = pool.alloc(out_bytes);
+  char* out = nullptr;
+  char* ws = nullptr;
   size_t ws_bytes = pref_ws;
-  char* ws = out ? pool.alloc(ws_bytes) : nullptr;
-  if (out && !ws) {
-    ws_bytes = min_ws;
-    ws = pool.alloc(ws_bytes);
+  // Output and workspace; idle resident plans other than this one are
+  // evicted (least recently used first) before giving up.
+  while (true) {
+    out = pool.alloc(out_bytes);
+    ws_bytes = pref_ws;
+    ws = out ? pool.alloc(ws_bytes) : nullptr;
+    if (out && !ws) {
+      ws_bytes = min_ws;
+      ws = pool.alloc(ws_bytes);
+    }
+    if (out && ws) break;
+    if (out) pool.free(out);
+    out = nullptr;
+    auto victim = plans.end();
+    for (auto it = plans.begin(); it != plans.end(); ++it)
+      if (&it->second != pe && it->second.uses == 0 &&
+          (victim == plans.end() || it->second.last < victim->second.last))
+        victim = it;
+    if (victim == plans.end()) break;
+    pool.free(victim->second.res);
+    rqc_plan_destroy(victim->second.plan);
+    plans.erase(victim);
   }
   if (!out || !ws) {
     if (out) pool.free(out);
