@@ -55,6 +55,35 @@ __device__ __forceinline__ uint32_t load_lp(const void* p, int64_t i, int pre) {
   return pack_lp<LP>(v);
 }
 
+// Four consecutive operand elements (16 bytes of packed words in 16-bit
+// storage, 32 bytes of complex64) as packed low-precision words.
+template <int LP, int S>
+__device__ __forceinline__ uint4 load_lp4(const void* p, int64_t i, int pre) {
+  if (S == LP) return *reinterpret_cast<const uint4*>(reinterpret_cast<const uint32_t*>(p) + i);
+  float2 v[4];
+  if (S == ST_C64) {
+    const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(p) + i);
+    const float4 x = q[0], y = q[1];
+    v[0] = make_float2(x.x, x.y);
+    v[1] = make_float2(x.z, x.w);
+    v[2] = make_float2(y.x, y.y);
+    v[3] = make_float2(y.z, y.w);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = load_c<S>(p, i + t);
+  }
+  uint32_t w[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (pre) {
+      v[t].x = ldexpf(v[t].x, pre);
+      v[t].y = ldexpf(v[t].y, pre);
+    }
+    w[t] = pack_lp<LP>(v[t]);
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 template <int LP>
 __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c);
 template <>
@@ -77,9 +106,12 @@ __device__ __forceinline__ u32x4 expand_b(u32x4 w, bool swap_halves) {
   return o;
 }
 
-template <int LP, int SA, int SB, int SC>
-__global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
-  __shared__ __attribute__((aligned(16))) uint32_t lw[kLMainWords + 16];
+// VEC: the two lowest tile bits of A and of B are their two lowest address
+// bits (summed indices, as the planner lays out every step), so four
+// consecutive tile elements are 16 contiguous bytes: one vector load and
+// one 16-byte LDS write per four elements.
+template <int LP, int SA, int SB, int SC, bool VEC>
+__device__ __forceinline__ void mfma16_body(const StepDesc& d, uint32_t* lw) {
   uint32_t* Abuf = lw;                  // [2][kTM][kLRow]
   uint32_t* Bbuf = lw + 2 * kLABuf;     // [2][kTN][kLRow]
   float* lds = reinterpret_cast<float*>(lw);
@@ -93,27 +125,43 @@ __global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
   const uint64_t no = bid % (uint64_t)d.n_col_tiles;
   const uint64_t ro = bid / (uint64_t)d.n_col_tiles;
 
-  // A chunk tile: 128 rows x 32 k (4096 elements, 16 per thread); B chunk
-  // tile: 32 k x 64 columns (2048, 8 per thread).
-  int64_t gA[16];
-  int lA[16];
-  int64_t gB[8];
-  int lB[8];
+  // A chunk tile: 128 rows x 32 k (4096 elements: 16 per thread, or 4
+  // vectors of 4); B chunk tile: 32 k x 64 columns (2048: 8, or 2 vectors).
+  constexpr int NA = VEC ? 4 : 16, NB = VEC ? 2 : 8;
+  int64_t gA[NA];
+  int lA[NA];
+  int64_t gB[NB];
+  int lB[NB];
   {
     TileTab* ta = reinterpret_cast<TileTab*>(lds);
     TileTab* tb = ta + 1;
     build_tab(d.tA, kLRow, 0, 1, *ta);
     build_tab(d.tB, 0, kLRow, 1, *tb);
     __syncthreads();
+    if (VEC) {
+      // Vector v = tid + 256 j covers elements 4v .. 4v+3.
+      const int lo = (tid & 15) << 2, hi0 = 64 + (tid >> 4);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      gA[j] = ta->g[lane] + ta->g[64 + wave + 4 * j];
-      lA[j] = ta->c[lane] + ta->c[64 + wave + 4 * j];
-    }
+      for (int j = 0; j < NA; ++j) {
+        gA[j] = ta->g[lo] + ta->g[hi0 + 16 * j];
+        lA[j] = ta->c[lo] + ta->c[hi0 + 16 * j];
+      }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      gB[j] = tb->g[lane] + tb->g[64 + wave + 4 * j];
-      lB[j] = tb->c[lane] + tb->c[64 + wave + 4 * j];
+      for (int j = 0; j < NB; ++j) {
+        gB[j] = tb->g[lo] + tb->g[hi0 + 16 * j];
+        lB[j] = tb->c[lo] + tb->c[hi0 + 16 * j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        gA[j] = ta->g[lane] + ta->g[64 + wave + 4 * j];
+        lA[j] = ta->c[lane] + ta->c[64 + wave + 4 * j];
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        gB[j] = tb->g[lane] + tb->g[64 + wave + 4 * j];
+        lB[j] = tb->c[lane] + tb->c[64 + wave + 4 * j];
+      }
     }
   }
   int hb = 0;
@@ -159,32 +207,51 @@ __global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     uint32_t ra[16], rb[8];
-    {
+    auto load_chunk = [&](int kc) {
       int64_t kA, kB;
-      k_offsets(d, 0, kA, kB);
+      k_offsets(d, kc, kA, kB);
+      if (VEC) {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
+        for (int j = 0; j < NA; ++j) {
+          const uint4 v = load_lp4<LP, SA>(d.A, oA + kA + gA[j], pA);
+          ra[4 * j] = v.x, ra[4 * j + 1] = v.y, ra[4 * j + 2] = v.z, ra[4 * j + 3] = v.w;
+        }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
-    }
+        for (int j = 0; j < NB; ++j) {
+          const uint4 v = load_lp4<LP, SB>(d.B, oB + kB + gB[j], pB);
+          rb[4 * j] = v.x, rb[4 * j + 1] = v.y, rb[4 * j + 2] = v.z, rb[4 * j + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
+      }
+    };
+    auto store_chunk = [&](uint32_t* An, uint32_t* Bn) {
+      if (VEC) {
+#pragma unroll
+        for (int j = 0; j < NA; ++j)
+          *reinterpret_cast<uint4*>(An + lA[j]) = make_uint4(ra[4 * j], ra[4 * j + 1], ra[4 * j + 2], ra[4 * j + 3]);
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          *reinterpret_cast<uint4*>(Bn + lB[j]) = make_uint4(rb[4 * j], rb[4 * j + 1], rb[4 * j + 2], rb[4 * j + 3]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) An[lA[j]] = ra[j];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) Bn[lB[j]] = rb[j];
+      }
+    };
+    load_chunk(0);
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 16; ++j) Abuf[lA[j]] = ra[j];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) Bbuf[lB[j]] = rb[j];
+    store_chunk(Abuf, Bbuf);
     __syncthreads();
 
     for (int kc = 0; kc < n_kc; ++kc) {
       const int cur = kc & 1;
       const bool more = kc + 1 < n_kc;
-      if (more) {
-        int64_t kA, kB;
-        k_offsets(d, kc + 1, kA, kB);
-#pragma unroll
-        for (int j = 0; j < 16; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
-      }
+      if (more) load_chunk(kc + 1);
       const uint32_t* As = Abuf + cur * kLABuf + (wm * 64 + lrow) * kLRow + kq;
       const uint32_t* Bs = Bbuf + cur * kLBBuf + (wn * 32 + ncol) * kLRow + kq;
 #pragma unroll
@@ -198,14 +265,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
         acc[1][0] = mfma16<LP>(a1, b0, acc[1][0]);
         acc[1][1] = mfma16<LP>(a1, b1, acc[1][1]);
       }
-      if (more) {
-        uint32_t* An = Abuf + (cur ^ 1) * kLABuf;
-        uint32_t* Bn = Bbuf + (cur ^ 1) * kLBBuf;
-#pragma unroll
-        for (int j = 0; j < 16; ++j) An[lA[j]] = ra[j];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) Bn[lB[j]] = rb[j];
-      }
+      if (more) store_chunk(Abuf + (cur ^ 1) * kLABuf, Bbuf + (cur ^ 1) * kLBBuf);
       __syncthreads();
     }
 
@@ -243,6 +303,17 @@ __global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
     finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
     __syncthreads();
   }
+}
+
+template <int LP, int SA, int SB, int SC>
+__global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
+  __shared__ __attribute__((aligned(16))) uint32_t lw[kLMainWords + 16];
+  const bool vec = d.tA.nbits >= 2 && d.tB.nbits >= 2 && d.tA.gpos[0] == 0 && d.tA.gpos[1] == 1 &&
+                   d.tB.gpos[0] == 0 && d.tB.gpos[1] == 1 && d.tA.role[0] == 2 && d.tA.role[1] == 2 &&
+                   d.tB.role[0] == 2 && d.tB.role[1] == 2 && d.tA.cbit[0] == 0 && d.tA.cbit[1] == 1 &&
+                   d.tB.cbit[0] == 0 && d.tB.cbit[1] == 1;
+  if (vec) mfma16_body<LP, SA, SB, SC, true>(d, lw);
+  else mfma16_body<LP, SA, SB, SC, false>(d, lw);
 }
 
 template <int LP>
