@@ -131,7 +131,10 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   Ro = by(Ro, pc);
   No = by(No, pc);
   Ko = by(Ko, pa);
-  if ((int)(Ro.size() + No.size()) > 31) throw Error{RQC_EUNSUPPORTED, "grid too large"};
+  // One workgroup of 256 work-items per output tile, and a launch holds fewer
+  // than 2^32 work-items along x.
+  if ((int)(Ro.size() + No.size()) > 23)
+    throw Error{RQC_EUNSUPPORTED, "step output has more than 2^23 tiles"};
 
   auto tile = [&](TileMap& t, const std::vector<std::pair<int, int>>& bits, auto posf) {
     // bits: (label, role); cbit = index inside the role's tile list

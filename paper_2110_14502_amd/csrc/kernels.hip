@@ -180,12 +180,10 @@ struct PermDesc {
 };
 
 __global__ __launch_bounds__(256) void k_permute(const float2* in, float2* out, PermDesc p,
-                                                 int lo_in, int lo_out, uint32_t lo_in_mask,
-                                                 uint32_t lo_out_mask) {
+                                                 int lo_in, int lo_out, uint64_t n_blocks) {
   // Tile = the lowest `lo_in` input bits  U  the lowest `lo_out` output bits.
+  // Workgroups stride over the tiles (a grid has at most 2^32 work-items).
   __shared__ float2 tile[1024 + 32];
-  (void)lo_in_mask;
-  (void)lo_out_mask;
   const int r = p.rank;
   int out_of_in[48];
   for (int i = 0; i < r; ++i) out_of_in[p.src_of_out[i]] = i;
@@ -200,10 +198,6 @@ __global__ __launch_bounds__(256) void k_permute(const float2* in, float2* out, 
   int ob[48], no = 0;
   for (int i = 0; i < r; ++i)
     if (!((tmask >> i) & 1)) ob[no++] = i;
-  // Block base in output index space.
-  uint64_t base_out = 0;
-  for (int i = 0; i < no; ++i)
-    if ((blockIdx.x >> i) & 1) base_out |= 1ull << ob[i];
   const int nte = 1 << nt;
   // Read phase: element t of the tile in input order (input bits ascending).
   int tin[20], nti = 0;
@@ -220,28 +214,35 @@ __global__ __launch_bounds__(256) void k_permute(const float2* in, float2* out, 
     }
     for (int i = 0; i < nt; ++i) tin[nti++] = tmp_in[i];
   }
-  uint64_t base_in = 0;
-  for (int i = 0; i < r; ++i)
-    if ((base_out >> i) & 1) base_in |= 1ull << p.src_of_out[i];
-  for (int t = threadIdx.x; t < nte; t += blockDim.x) {
-    uint64_t a = base_in;
-    int slot = 0;
-    for (int i = 0; i < nti; ++i)
-      if ((t >> i) & 1) {
-        a |= 1ull << tin[i];
-        // slot index: position of the output bit inside tb[]
-        const int ob_i = out_of_in[tin[i]];
-        for (int j = 0; j < nt; ++j)
-          if (tb[j] == ob_i) slot |= 1 << j;
-      }
-    tile[slot + (slot >> 5)] = in[a];
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nte; t += blockDim.x) {
-    uint64_t a = base_out;
-    for (int j = 0; j < nt; ++j)
-      if ((t >> j) & 1) a |= 1ull << tb[j];
-    out[a] = tile[t + (t >> 5)];
+  for (uint64_t blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
+    // Block base in output index space.
+    uint64_t base_out = 0;
+    for (int i = 0; i < no; ++i)
+      if ((blk >> i) & 1) base_out |= 1ull << ob[i];
+    uint64_t base_in = 0;
+    for (int i = 0; i < r; ++i)
+      if ((base_out >> i) & 1) base_in |= 1ull << p.src_of_out[i];
+    for (int t = threadIdx.x; t < nte; t += blockDim.x) {
+      uint64_t a = base_in;
+      int slot = 0;
+      for (int i = 0; i < nti; ++i)
+        if ((t >> i) & 1) {
+          a |= 1ull << tin[i];
+          // slot index: position of the output bit inside tb[]
+          const int ob_i = out_of_in[tin[i]];
+          for (int j = 0; j < nt; ++j)
+            if (tb[j] == ob_i) slot |= 1 << j;
+        }
+      tile[slot + (slot >> 5)] = in[a];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nte; t += blockDim.x) {
+      uint64_t a = base_out;
+      for (int j = 0; j < nt; ++j)
+        if ((t >> j) & 1) a |= 1ull << tb[j];
+      out[a] = tile[t + (t >> 5)];
+    }
+    __syncthreads();
   }
 }
 
@@ -260,9 +261,10 @@ hipError_t launch_permute(const void* in, void* out, int rank, const int8_t* src
   for (int i = 0; i < lo_in; ++i) tmask |= 1ull << out_of_in[i];
   const int nt = __builtin_popcountll(tmask);
   const uint64_t blocks = 1ull << (rank - nt);
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)blocks), dim3(256), 0, s,
+  const uint64_t grid = blocks < (1ull << 20) ? blocks : (1ull << 20);
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)grid), dim3(256), 0, s,
                      reinterpret_cast<const float2*>(in), reinterpret_cast<float2*>(out), p, lo_in,
-                     lo_out, 0u, 0u);
+                     lo_out, blocks);
   return hipGetLastError();
 }
 

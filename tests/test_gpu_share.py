@@ -127,3 +127,45 @@ def test_share_subslices_vs_oracle(share):
     assert ow[:len(wires)] == wires
     ref = oracle.slice_values_ordered(circ, [], bits, ow, oids, groups, pairs)[:, 0]
     assert _err(got, ref, fine) < 1e-4
+
+
+def test_share_slices_equal_full_plan_slices():
+    """A share with high bits b computes slices b*2^L + i of the full
+    slicing: checked against the full plan and the oracle on a 5x5 circuit."""
+    _say("share vs full plan")
+    c = rqcgen.grid_rqc(5, 5, 8, 2)
+    openq = [23, 24]
+    net = R.Network(R.Circuit.from_rqcgen(c), openq)
+    bits = rqcgen.random_bits(23, 3)
+    full = R.Plan(net, n_sliced=8, path_trials=32, seed=1).bind()
+    wires = full.sliced_wires()
+    _, per_full = full.contract(bits, per_slice=True)
+    per_full = R.to_complex(per_full)[:, 0]
+    for high in ([1, 0, 1], [0, 1, 1]):
+        share = R.Plan(net, n_sliced=8, forced_wires=wires, path_trials=32, seed=5,
+                       n_local_sliced=5, share_bits=high).bind()
+        _, per = share.contract(bits, per_slice=True)
+        per = R.to_complex(per)[:, 0]
+        base = sum(b << i for i, b in enumerate(high)) << 5
+        ref = per_full[base:base + 32]
+        assert np.max(np.abs(per - ref)) * 2 ** 12.5 < 1e-4
+    ids = [base + 3, base + 17]
+    o = oracle.slice_values_tn(c, openq, bits, wires, ids)
+    assert np.max(np.abs(per_full[ids] - o)) * 2 ** 12.5 < 1e-4
+
+
+def test_group_limit_does_not_change_results():
+    _say("group limit")
+    c = rqcgen.grid_rqc(5, 5, 10, 4)
+    openq = [20, 21, 22, 23, 24]
+    net = R.Network(R.Circuit.from_rqcgen(c), openq)
+    bits = rqcgen.random_bits(20, 1)
+    p = R.Plan(net, n_sliced=6, path_trials=32, seed=3).bind()
+    ref = R.to_complex(p.contract(bits))[0]
+    for g in (1, 3, 16):
+        p.set_group_limit(g)
+        got = R.to_complex(p.contract(bits))[0]
+        assert p.last_report["slices_per_group"] <= g
+        assert np.max(np.abs(got - ref)) * 2 ** 12.5 < 1e-5
+    p.set_group_limit(0)
+    assert oracle.normalized_error(ref, oracle.amplitudes_tn(c, openq, bits), 25) < 1e-4

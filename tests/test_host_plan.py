@@ -130,3 +130,18 @@ def test_workspace_sizes_scale_with_group():
     assert P6.workspace_bytes(0, 1, R.F16)[0] < P6.workspace_bytes(0, 1, R.F32)[0]
     lo2, _ = P.workspace_bytes(0, 4, R.F32)
     assert lo2 >= lo
+
+
+def test_restarts_keep_the_cheapest_plan_and_are_deterministic():
+    _, p1 = _plan(5, 5, 10, 2, 2, n_sliced=4, path_trials=16, seed=7)
+    _, p4 = _plan(5, 5, 10, 2, 2, n_sliced=4, path_trials=16, seed=7, restarts=4)
+    _, p4b = _plan(5, 5, 10, 2, 2, n_sliced=4, path_trials=16, seed=7, restarts=4)
+    assert p4.export() == p4b.export()
+    # restart 0 uses the seed itself, so restarts never do worse on the
+    # planner's own objective (traffic-weighted cost; flops as a proxy here)
+    cost = lambda p: sum(max(2.0 ** (s["m"] + s["n"] + s["k"]),
+                             20 * (2.0 ** (s["m"] + s["k"]) + 2.0 ** (s["n"] + s["k"]) + 2.0 ** (s["m"] + s["n"])))
+                         for s in p.steps())
+    assert cost(p4) <= cost(p1) * (1 + 1e-9)
+    with pytest.raises(R.RqcError):
+        _plan(4, 4, 8, 1, 2, restarts=-1)
