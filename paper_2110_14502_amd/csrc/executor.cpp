@@ -62,7 +62,7 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   auto pc = [&](int x) { return pos_in(lc, x); };
   // Row-streaming kernel: K is the lowest k address bits of both A and B, in
   // the same order; B small.
-  bool rows_ok = k <= 7 && n <= 5 && (int64_t(1) << (n + k)) <= 2048;
+  bool rows_ok = k <= 7 && n <= 5 && (int64_t(1) << (n + k)) <= 4096;
   for (int p = 0; p < k && rows_ok; ++p) {
     const int xa = la[la.size() - 1 - p];
     rows_ok = pos_in(lb, xa) == p;
@@ -92,14 +92,14 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
     // bits and the stores coalesce).
     d.ncb = std::min(n, 3);
     rt = std::min(m, 8);
-    if ((int64_t(1) << (n + k)) > 2048) throw Error{RQC_EINVAL, "internal: row kernel B too large"};
+    if ((int64_t(1) << (n + k)) > 4096) throw Error{RQC_EINVAL, "internal: row kernel B too large"};
   } else if (m + n <= 8) {
     // Tiny output, long sum: deep K tiles (split-K spreads them over blocks).
     rt = m;
     nt = n;
     kt = std::min(k, 12 - std::max(m, n));
     while (kt > 0 && (((int64_t(1) << rt) * ((int64_t(1) << kt) + 1) +
-                       (int64_t(1) << kt) * ((int64_t(1) << nt) + 1)) * 8) > 60 * 1024)
+                       (int64_t(1) << kt) * ((int64_t(1) << nt) + 1)) * 8) > 56 * 1024)
       --kt;
   } else {
     kt = std::min(k, 4);

@@ -24,7 +24,8 @@ constexpr int kLRow = kLTK + 4;          // words per LDS row (16-byte aligned)
 constexpr int kLABuf = kTM * kLRow;      // words per A buffer
 constexpr int kLBBuf = kTN * kLRow;      // words per B buffer
 constexpr int kLMainWords = 2 * kLABuf + 2 * kLBBuf;
-static_assert(kCHalf + kTabFloats <= kLMainWords, "C staging must fit the operand buffers");
+static_assert(kCHalf <= kLMainWords, "C staging must fit the operand buffers");
+constexpr unsigned kMfma16Grid = 256 * 2;  // persistent workgroups (two per CU)
 
 template <int LP>
 __device__ __forceinline__ uint32_t pack_lp(float2 v);
@@ -111,19 +112,14 @@ __device__ __forceinline__ u32x4 expand_b(u32x4 w, bool swap_halves) {
 // consecutive tile elements are 16 contiguous bytes: one vector load and
 // one 16-byte LDS write per four elements.
 template <int LP, int SA, int SB, int SC, bool VEC>
-__device__ __forceinline__ void mfma16_body(const StepDesc& d, uint32_t* lw) {
+__device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items, uint32_t* lw,
+                                            TileTab& tcs, OuterTab& ot) {
   uint32_t* Abuf = lw;                  // [2][kTM][kLRow]
   uint32_t* Bbuf = lw + 2 * kLABuf;     // [2][kTN][kLRow]
   float* lds = reinterpret_cast<float*>(lw);
   float* red = lds + kLMainWords;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-
-  uint64_t bid = blockIdx.x;
-  const uint64_t nblk = gridDim.x;
-  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
-  const uint64_t no = bid % (uint64_t)d.n_col_tiles;
-  const uint64_t ro = bid / (uint64_t)d.n_col_tiles;
 
   // A chunk tile: 128 rows x 32 k (4096 elements: 16 per thread, or 4
   // vectors of 4); B chunk tile: 32 k x 64 columns (2048: 8, or 2 vectors).
@@ -137,6 +133,7 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint32_t* lw) {
     TileTab* tb = ta + 1;
     build_tab(d.tA, kLRow, 0, 1, *ta);
     build_tab(d.tB, 0, kLRow, 1, *tb);
+    build_outer(d, ot);
     __syncthreads();
     if (VEC) {
       // Vector v = tid + 256 j covers elements 4v .. 4v+3.
@@ -168,36 +165,125 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint32_t* lw) {
   for (int b = 0; b < d.tC.nbits; ++b)
     if (d.tC.role[b] == 0 && d.tC.cbit[b] == 6) hb = b;
   const int64_t g_half = int64_t(1) << d.tC.gpos[hb];
+  build_tab_skip(d.tC, hb, kCStride, 2, tcs);
+  __syncthreads();  // operand tables copied out; the buffers are free
+  const int64_t g_lane = tcs.g[lane];
+  const int c_lane = tcs.c[lane];
 
   const int lrow = lane & 31;
   const int kq = (lane >> 5) * 4;      // first complex k of the lane's 8 real k
   const int ncol = (lane & 31) >> 1;
   const bool bswap = (lane & 1) != 0;  // C_r column parity 1: (im, re)
 
-  const int n_kc = 1 << d.n_ko;
-  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
-    const int js = copy % d.gs_c, jb = copy / d.gs_c;
-    int64_t oA, oB, oC;
-    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
-    // Pre-scales of complex64 operands and the output scale.
+  // Pre-scales of complex64 operands (to 2^14) and the output scale of a
+  // copy: the accumulator holds the product times 2^(pA+pB); the output
+  // shift maps the bound to the storage target (as in compute_scale).
+  struct CopyScale {
+    int pA, pB;
+    Scale sc;
+  };
+  auto copy_scale = [&](int js, int jb) {
     const float mA = d.maxA ? d.maxA[js * d.eA_s + jb * d.eA_b] : d.maxA_const;
     const float mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
     const int EA = mA > 0.f ? ceil_log2(mA) : 0, EB = mB > 0.f ? ceil_log2(mB) : 0;
-    const int pA = (SA == LP || mA <= 0.f) ? 0 : 14 - EA;
-    const int pB = (SB == LP || mB <= 0.f) ? 0 : 14 - EB;
-    // The accumulator holds the product times 2^(pA+pB); the output shift
-    // maps the bound to the storage target (as in compute_scale).
-    Scale sc{pA + pB, 0};
-    {
-      const int eA = (d.track && d.expA) ? d.expA[js * d.eA_s + jb * d.eA_b] : 0;
-      const int eB = (d.track && d.expB) ? d.expB[js * d.eB_s + jb * d.eB_b] : 0;
-      sc.expC = eA + eB;
-      if (d.track && mA > 0.f && mB > 0.f && mA <= 3.0e38f && mB <= 3.0e38f) {
-        const int t = d.k_total + 1 + (EA + pA) + (EB + pB) - target_log2(d);
-        sc.shift = t;
-        sc.expC = eA - pA + eB - pB + t;
-      }
+    CopyScale r;
+    r.pA = (SA == LP || mA <= 0.f) ? 0 : 14 - EA;
+    r.pB = (SB == LP || mB <= 0.f) ? 0 : 14 - EB;
+    r.sc = Scale{r.pA + r.pB, 0};
+    const int eA = (d.track && d.expA) ? d.expA[js * d.eA_s + jb * d.eA_b] : 0;
+    const int eB = (d.track && d.expB) ? d.expB[js * d.eB_s + jb * d.eB_b] : 0;
+    r.sc.expC = eA + eB;
+    if (d.track && mA > 0.f && mB > 0.f && mA <= 3.0e38f && mB <= 3.0e38f) {
+      const int t = d.k_total + 1 + (EA + r.pA) + (EB + r.pB) - target_log2(d);
+      r.sc.shift = t;
+      r.sc.expC = eA - r.pA + eB - r.pB + t;
     }
+    return r;
+  };
+
+  uint32_t ra[16], rb[8];
+  auto load_chunk = [&](int64_t oA, int64_t oB, int kc, int pA, int pB) {
+    int64_t kA, kB;
+    k_offsets(d, ot, kc, kA, kB);
+    if (VEC) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) {
+        const uint4 v = load_lp4<LP, SA>(d.A, oA + kA + gA[j], pA);
+        ra[4 * j] = v.x, ra[4 * j + 1] = v.y, ra[4 * j + 2] = v.z, ra[4 * j + 3] = v.w;
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const uint4 v = load_lp4<LP, SB>(d.B, oB + kB + gB[j], pB);
+        rb[4 * j] = v.x, rb[4 * j + 1] = v.y, rb[4 * j + 2] = v.z, rb[4 * j + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
+    }
+  };
+  auto store_chunk = [&](int buf) {
+    uint32_t* An = Abuf + buf * kLABuf;
+    uint32_t* Bn = Bbuf + buf * kLBBuf;
+    if (VEC) {
+#pragma unroll
+      for (int j = 0; j < NA; ++j)
+        *reinterpret_cast<uint4*>(An + lA[j]) = make_uint4(ra[4 * j], ra[4 * j + 1], ra[4 * j + 2], ra[4 * j + 3]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        *reinterpret_cast<uint4*>(Bn + lB[j]) = make_uint4(rb[4 * j], rb[4 * j + 1], rb[4 * j + 2], rb[4 * j + 3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) An[lA[j]] = ra[j];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) Bn[lB[j]] = rb[j];
+    }
+  };
+
+  // Persistent walk over (copy, tile) items as in the FP32 kernel: tile
+  // counts are powers of two, column tiles fastest.
+  const int n_kc = 1 << d.n_ko;
+  const int tbits = d.n_ro + d.n_no;
+  const uint64_t tmask = (uint64_t(1) << tbits) - 1, cmask = (uint64_t(1) << d.n_no) - 1;
+  const uint64_t per = (n_items + gridDim.x - 1) / gridDim.x;
+  uint64_t t = (uint64_t)blockIdx.x * per;
+  const uint64_t t_end = t + per < n_items ? t + per : n_items;
+  int cur = -1, cjs = 0, cjb = 0;
+  bool wexp = false;
+  CopyScale cs{0, 0, Scale{0, 0}};
+  float lmax = 0.f;
+  int bad = 0;
+  if (t < t_end) {
+    const int copy = (int)(t >> tbits);
+    const uint64_t bid = t & tmask;
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
+    cs = copy_scale(js, jb);
+    load_chunk(oA, oB, 0, cs.pA, cs.pB);
+    store_chunk(0);
+  }
+  __syncthreads();
+  for (; t < t_end; ++t) {
+    const int copy = (int)(t >> tbits);
+    const uint64_t bid = t & tmask;
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    if (copy != cur) {
+      if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, cs.sc);
+      cs = copy_scale(js, jb);
+      lmax = 0.f;
+      bad = 0;
+      wexp = false;
+      cur = copy;
+      cjs = js;
+      cjb = jb;
+    }
+    wexp = wexp || bid == 0;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
+    const bool next_tile = t + 1 < t_end;
+
     floatx16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -206,54 +292,28 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint32_t* lw) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    uint32_t ra[16], rb[8];
-    auto load_chunk = [&](int kc) {
-      int64_t kA, kB;
-      k_offsets(d, kc, kA, kB);
-      if (VEC) {
-#pragma unroll
-        for (int j = 0; j < NA; ++j) {
-          const uint4 v = load_lp4<LP, SA>(d.A, oA + kA + gA[j], pA);
-          ra[4 * j] = v.x, ra[4 * j + 1] = v.y, ra[4 * j + 2] = v.z, ra[4 * j + 3] = v.w;
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const uint4 v = load_lp4<LP, SB>(d.B, oB + kB + gB[j], pB);
-          rb[4 * j] = v.x, rb[4 * j + 1] = v.y, rb[4 * j + 2] = v.z, rb[4 * j + 3] = v.w;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < NA; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
-#pragma unroll
-        for (int j = 0; j < NB; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
-      }
-    };
-    auto store_chunk = [&](uint32_t* An, uint32_t* Bn) {
-      if (VEC) {
-#pragma unroll
-        for (int j = 0; j < NA; ++j)
-          *reinterpret_cast<uint4*>(An + lA[j]) = make_uint4(ra[4 * j], ra[4 * j + 1], ra[4 * j + 2], ra[4 * j + 3]);
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-          *reinterpret_cast<uint4*>(Bn + lB[j]) = make_uint4(rb[4 * j], rb[4 * j + 1], rb[4 * j + 2], rb[4 * j + 3]);
-      } else {
-#pragma unroll
-        for (int j = 0; j < NA; ++j) An[lA[j]] = ra[j];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) Bn[lB[j]] = rb[j];
-      }
-    };
-    load_chunk(0);
-    __syncthreads();
-    store_chunk(Abuf, Bbuf);
-    __syncthreads();
-
     for (int kc = 0; kc < n_kc; ++kc) {
-      const int cur = kc & 1;
+      const int cb = kc & 1;
       const bool more = kc + 1 < n_kc;
-      if (more) load_chunk(kc + 1);
-      const uint32_t* As = Abuf + cur * kLABuf + (wm * 64 + lrow) * kLRow + kq;
-      const uint32_t* Bs = Bbuf + cur * kLBBuf + (wn * 32 + ncol) * kLRow + kq;
+      // Next chunk of this tile, or the first chunk of the next tile (kept
+      // in registers until this tile's output has left the LDS).
+      if (more) {
+        load_chunk(oA, oB, kc + 1, cs.pA, cs.pB);
+      } else if (next_tile) {
+        const int cn = (int)((t + 1) >> tbits);
+        const uint64_t bn = (t + 1) & tmask;
+        const int jsn = cn % d.gs_c, jbn = cn / d.gs_c;
+        int64_t pA, pB, pC;
+        outer_offsets(d, ot, bn >> d.n_no, bn & cmask, jsn, jbn, pA, pB, pC);
+        if (cn == copy) {
+          load_chunk(pA, pB, 0, cs.pA, cs.pB);
+        } else {
+          const CopyScale csn = copy_scale(jsn, jbn);
+          load_chunk(pA, pB, 0, csn.pA, csn.pB);
+        }
+      }
+      const uint32_t* As = Abuf + cb * kLABuf + (wm * 64 + lrow) * kLRow + kq;
+      const uint32_t* Bs = Bbuf + cb * kLBBuf + (wn * 32 + ncol) * kLRow + kq;
 #pragma unroll
       for (int kk = 0; kk < kLTK / 8; ++kk) {
         const u32x4 a0 = *reinterpret_cast<const u32x4*>(As + kk * 8);
@@ -265,15 +325,11 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint32_t* lw) {
         acc[1][0] = mfma16<LP>(a1, b0, acc[1][0]);
         acc[1][1] = mfma16<LP>(a1, b1, acc[1][1]);
       }
-      if (more) store_chunk(Abuf + (cur ^ 1) * kLABuf, Bbuf + (cur ^ 1) * kLBBuf);
+      if (more) store_chunk(cb ^ 1);
       __syncthreads();
     }
 
     float* Cs = lds;
-    TileTab* tcs = reinterpret_cast<TileTab*>(lds + kCHalf);
-    build_tab_skip(d.tC, hb, kCStride, 2, *tcs);
-    float lmax = 0.f;
-    int bad = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (wm == h) {
@@ -289,40 +345,47 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint32_t* lw) {
             }
       }
       __syncthreads();
-      const int64_t gl = tcs->g[lane] + (h ? g_half : 0);
-      const int32_t cl = tcs->c[lane];
-#pragma unroll 4
-      for (int j = 0; j < 16; ++j) {
-        const int hi = 64 + wave + 4 * j;
-        const int c = cl + tcs->c[hi];
-        const int64_t at = oC + gl + tcs->g[hi];
-        store_out<SC>(d, at, make_float2(Cs[c], Cs[c + 1]), sc, lmax, bad);
-      }
+      store_half<SC, VEC ? 8 : 4>(d, Cs, tcs, oC + g_lane + (h ? g_half : 0), c_lane, wave, cs.sc, lmax, bad);
       __syncthreads();
     }
-    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
-    __syncthreads();
+    if (next_tile) {
+      store_chunk(0);
+      __syncthreads();
+    }
   }
+  if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, cs.sc);
 }
 
-template <int LP, int SA, int SB, int SC>
-__global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d) {
+template <int LP, int SA, int SB, int SC, bool VEC>
+__global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d, uint64_t n_items) {
   __shared__ __attribute__((aligned(16))) uint32_t lw[kLMainWords + 16];
-  const bool vec = d.tA.nbits >= 2 && d.tB.nbits >= 2 && d.tA.gpos[0] == 0 && d.tA.gpos[1] == 1 &&
-                   d.tB.gpos[0] == 0 && d.tB.gpos[1] == 1 && d.tA.role[0] == 2 && d.tA.role[1] == 2 &&
-                   d.tB.role[0] == 2 && d.tB.role[1] == 2 && d.tA.cbit[0] == 0 && d.tA.cbit[1] == 1 &&
-                   d.tB.cbit[0] == 0 && d.tB.cbit[1] == 1;
-  if (vec) mfma16_body<LP, SA, SB, SC, true>(d, lw);
-  else mfma16_body<LP, SA, SB, SC, false>(d, lw);
+  __shared__ TileTab tcs;
+  __shared__ OuterTab ot;
+  mfma16_body<LP, SA, SB, SC, VEC>(d, n_items, lw, tcs, ot);
+}
+
+// The vector path needs the two lowest tile bits of A and of B to be their
+// two lowest address bits and summed indices 0 and 1 of the chunk.
+static bool mfma16_vec(const StepDesc& d) {
+  return d.tA.nbits >= 2 && d.tB.nbits >= 2 && d.tA.gpos[0] == 0 && d.tA.gpos[1] == 1 &&
+         d.tB.gpos[0] == 0 && d.tB.gpos[1] == 1 && d.tA.role[0] == 2 && d.tA.role[1] == 2 &&
+         d.tB.role[0] == 2 && d.tB.role[1] == 2 && d.tA.cbit[0] == 0 && d.tA.cbit[1] == 1 &&
+         d.tB.cbit[0] == 0 && d.tB.cbit[1] == 1;
 }
 
 template <int LP>
 static hipError_t launch_mfma16(const StepDesc& d, int sa, int sb, int sc, dim3 grid,
                                 hipStream_t s) {
   constexpr int C = ST_C64;
+  const uint64_t n_items = (uint64_t)grid.x * (uint64_t)d.copies;
+  grid = dim3((unsigned)(n_items < kMfma16Grid ? n_items : kMfma16Grid), 1);
+  const bool vec = mfma16_vec(d);
 #define RQC_LP_CASE(a, b, c)                                                        \
   if (sa == a && sb == b && sc == c) {                                              \
-    hipLaunchKernelGGL((k_mfma16<LP, a, b, c>), grid, dim3(256), 0, s, d);         \
+    if (vec)                                                                        \
+      hipLaunchKernelGGL((k_mfma16<LP, a, b, c, true>), grid, dim3(256), 0, s, d, n_items); \
+    else                                                                            \
+      hipLaunchKernelGGL((k_mfma16<LP, a, b, c, false>), grid, dim3(256), 0, s, d, n_items); \
     return hipGetLastError();                                                       \
   }
   RQC_LP_CASE(LP, LP, LP)

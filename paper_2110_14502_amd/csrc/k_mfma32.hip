@@ -5,40 +5,47 @@ namespace rqc {
 
 // ---------------------------------------------------------------------------
 // MFMA contraction (FP32 matrix cores, v_mfma_f32_32x32x2_f32): 128 rows x
-// 64 complex columns per workgroup, 16 complex k per LDS chunk, double
-// buffered; 4 waves in a 2x2 grid, each 64 rows x 64 real columns.  The
-// operand offsets come from LDS tables built once per workgroup; the output
-// tile is staged through LDS in two halves of 64 rows (inside the operand
-// buffers) and stored in C's address order.  49.7 KB of LDS: three
-// workgroups per CU.
+// 64 complex columns per tile, 16 complex k per LDS chunk, double buffered;
+// 4 waves in a 2x2 grid, each 64 rows x 64 real columns.  The operand
+// offsets come from LDS tables built once per workgroup; the output tile is
+// staged through LDS in two halves of 64 rows (inside the operand buffers)
+// and stored in C's address order.
+//
+// Persistent: each workgroup walks a contiguous range of (copy, tile) items,
+// column tiles fastest, so consecutive tiles share the rows of A.  The first
+// chunk of the next tile is loaded while the current tile's last chunk is
+// multiplied and its output stored; the scale and the running max-abs change
+// only with the copy.  53 KB of LDS; two workgroups per CU.
 // ---------------------------------------------------------------------------
+constexpr unsigned kMfmaGrid = 256 * 2;
+
 template <int SA, int SB, int SC>
-__global__ __launch_bounds__(256, 3) void k_mfma32(StepDesc d) {
+__global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items) {
   __shared__ float lds[kMainFloats + 16];
+  __shared__ TileTab tcs;
+  __shared__ OuterTab ot;
   float* Abuf = lds;                                          // [2][kTK][2][kAPlane]
   float2* Bbuf = reinterpret_cast<float2*>(lds + 2 * kABuf);  // [2][kTK][kBStride]
   float* red = lds + kMainFloats;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // XCD-aware block order: consecutive logical tiles share the row tile of A
-  // and land on the same XCD (blocks are dealt round-robin to the 8 XCDs).
-  uint64_t bid = blockIdx.x;
-  const uint64_t nblk = gridDim.x;
-  if ((nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
-  const uint64_t no = bid % (uint64_t)d.n_col_tiles;
-  const uint64_t ro = bid / (uint64_t)d.n_col_tiles;
-
   // Per-thread element offsets of the A (2048) and B (1024) chunk tiles.
   int64_t gA[8];
   int lA[8];
   int64_t gB[4];
   int lB[4];
+  // The C tile bit that carries row bit 6 (which half of the tile).
+  int hb = 0;
+  for (int b = 0; b < d.tC.nbits; ++b)
+    if (d.tC.role[b] == 0 && d.tC.cbit[b] == 6) hb = b;
   {
     TileTab* ta = reinterpret_cast<TileTab*>(lds);
     TileTab* tb = ta + 1;
     build_tab(d.tA, 1, 0, kAStride, *ta);
     build_tab(d.tB, 0, 1, kBStride, *tb);
+    build_tab_skip(d.tC, hb, kCStride, 2, tcs);
+    build_outer(d, ot);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -50,12 +57,11 @@ __global__ __launch_bounds__(256, 3) void k_mfma32(StepDesc d) {
       gB[j] = tb->g[lane] + tb->g[64 + wave + 4 * j];
       lB[j] = tb->c[lane] + tb->c[64 + wave + 4 * j];
     }
+    __syncthreads();
   }
-  // The C tile bit that carries row bit 6 (which half of the tile).
-  int hb = 0;
-  for (int b = 0; b < d.tC.nbits; ++b)
-    if (d.tC.role[b] == 0 && d.tC.cbit[b] == 6) hb = b;
   const int64_t g_half = int64_t(1) << d.tC.gpos[hb];
+  const int64_t g_lane = tcs.g[lane];
+  const int c_lane = tcs.c[lane];
 
   // Lane roles inside the real-expanded operands.
   const int lrow = lane & 31;          // row inside a 32-row block
@@ -66,10 +72,72 @@ __global__ __launch_bounds__(256, 3) void k_mfma32(StepDesc d) {
   const float bsign = (cpart == 1 && dpart == 0) ? -1.f : 1.f;
 
   const int n_kc = 1 << d.n_ko;
-  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
-    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+  // Tile counts are powers of two: item t is copy t >> tb, row tile
+  // (t & tmask) >> n_no, column tile t & cmask.
+  const int tb = d.n_ro + d.n_no;
+  const uint64_t tmask = (uint64_t(1) << tb) - 1, cmask = (uint64_t(1) << d.n_no) - 1;
+  const uint64_t per = (n_items + gridDim.x - 1) / gridDim.x;
+  uint64_t t = (uint64_t)blockIdx.x * per;
+  const uint64_t t_end = t + per < n_items ? t + per : n_items;
+
+  auto item_offsets = [&](uint64_t it, int64_t& oA, int64_t& oB, int64_t& oC) {
+    const int copy = (int)(it >> tb);
+    const uint64_t bid = it & tmask;
+    outer_offsets(d, ot, bid >> d.n_no, bid & cmask, copy % d.gs_c, copy / d.gs_c, oA, oB, oC);
+  };
+  float2 ra[8], rb[4];
+  auto load_chunk = [&](int64_t oA, int64_t oB, int kc) {
+    int64_t kA, kB;
+    k_offsets(d, ot, kc, kA, kB);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ra[j] = load_c<SA>(d.A, oA + kA + gA[j]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rb[j] = load_c<SB>(d.B, oB + kB + gB[j]);
+  };
+  auto store_chunk = [&](int buf) {
+    float* An = Abuf + buf * kABuf;
+    float2* Bn = Bbuf + buf * kBBuf;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      An[lA[j]] = ra[j].x;
+      An[lA[j] + kAPlane] = ra[j].y;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) Bn[lB[j]] = rb[j];
+  };
+
+  if (t < t_end) {
     int64_t oA, oB, oC;
-    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    item_offsets(t, oA, oB, oC);
+    load_chunk(oA, oB, 0);
+    store_chunk(0);
+  }
+  __syncthreads();
+  int cur = -1;
+  int cjs = 0, cjb = 0;
+  bool wexp = false;
+  Scale sc{0, 0};
+  float lmax = 0.f;
+  int bad = 0;
+  for (; t < t_end; ++t) {
+    const int copy = (int)(t >> tb);
+    const uint64_t bid = t & tmask;
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    if (copy != cur) {
+      if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
+      sc = compute_scale(d, js, jb);
+      lmax = 0.f;
+      bad = 0;
+      wexp = false;
+      cur = copy;
+      cjs = js;
+      cjb = jb;
+    }
+    wexp = wexp || bid == 0;
+    int64_t oA, oB, oC;
+    outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
+    const bool next_tile = t + 1 < t_end;
+
     floatx16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -78,38 +146,20 @@ __global__ __launch_bounds__(256, 3) void k_mfma32(StepDesc d) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-    float2 ra[8], rb[4];
-    {
-      int64_t kA, kB;
-      k_offsets(d, 0, kA, kB);
-#pragma unroll
-      for (int j = 0; j < 8; ++j) ra[j] = load_c<SA>(d.A, oA + kA + gA[j]);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) rb[j] = load_c<SB>(d.B, oB + kB + gB[j]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      Abuf[lA[j]] = ra[j].x;
-      Abuf[lA[j] + kAPlane] = ra[j].y;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Bbuf[lB[j]] = rb[j];
-    __syncthreads();
-
     for (int kc = 0; kc < n_kc; ++kc) {
-      const int cur = kc & 1;
+      const int cb = kc & 1;
       const bool more = kc + 1 < n_kc;
+      // Next chunk of this tile, or the first chunk of the next tile (kept
+      // in registers until the output of this tile has left the LDS).
       if (more) {
-        int64_t kA, kB;
-        k_offsets(d, kc + 1, kA, kB);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) ra[j] = load_c<SA>(d.A, oA + kA + gA[j]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) rb[j] = load_c<SB>(d.B, oB + kB + gB[j]);
+        load_chunk(oA, oB, kc + 1);
+      } else if (next_tile) {
+        int64_t pA, pB, pC;
+        item_offsets(t + 1, pA, pB, pC);
+        load_chunk(pA, pB, 0);
       }
-      const float* As = Abuf + cur * kABuf + cpart * kAPlane + wm * 64 + lrow;
-      const float2* Bs = Bbuf + cur * kBBuf + wn * 32 + ncol;
+      const float* As = Abuf + cb * kABuf + cpart * kAPlane + wm * 64 + lrow;
+      const float2* Bs = Bbuf + cb * kBBuf + wn * 32 + ncol;
       // Operands of step k+1 are read from LDS while the MFMAs of step k run.
       float a0 = As[0], a1 = As[32];
       float2 b0 = Bs[0], b1 = Bs[16];
@@ -134,27 +184,12 @@ __global__ __launch_bounds__(256, 3) void k_mfma32(StepDesc d) {
         b0 = b0n;
         b1 = b1n;
       }
-      if (more) {
-        float* An = Abuf + (cur ^ 1) * kABuf;
-        float2* Bn = Bbuf + (cur ^ 1) * kBBuf;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          An[lA[j]] = ra[j].x;
-          An[lA[j] + kAPlane] = ra[j].y;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) Bn[lB[j]] = rb[j];
-      }
+      if (more) store_chunk(cb ^ 1);
       __syncthreads();
     }
 
     // Epilogue: two halves of 64 rows staged in the operand buffers.
     float* Cs = lds;
-    TileTab* tcs = reinterpret_cast<TileTab*>(lds + kCHalf);
-    build_tab_skip(d.tC, hb, kCStride, 2, *tcs);
-    const Scale sc = compute_scale(d, js, jb);
-    float lmax = 0.f;
-    int bad = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (wm == h) {
@@ -170,31 +205,28 @@ __global__ __launch_bounds__(256, 3) void k_mfma32(StepDesc d) {
             }
       }
       __syncthreads();
-      const int64_t gl = tcs->g[lane] + (h ? g_half : 0);
-      const int32_t cl = tcs->c[lane];
-#pragma unroll 4
-      for (int j = 0; j < 16; ++j) {
-        const int hi = 64 + wave + 4 * j;
-        const int c = cl + tcs->c[hi];
-        const int64_t at = oC + gl + tcs->g[hi];
-        store_out<SC>(d, at, make_float2(Cs[c], Cs[c + 1]), sc, lmax, bad);
-      }
+      store_half<SC, 8>(d, Cs, tcs, oC + g_lane + (h ? g_half : 0), c_lane, wave, sc, lmax, bad);
       __syncthreads();
     }
-    finish_scale<256>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
-    __syncthreads();
+    if (next_tile) {
+      store_chunk(0);
+      __syncthreads();
+    }
   }
+  if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
 }
 
 #define RQC_MFMA_CASE(a, b, c)                                                         \
   if (sa == a && sb == b && sc == c) {                                                 \
-    hipLaunchKernelGGL((k_mfma32<a, b, c>), grid, dim3(256), 0, s, d);                \
+    hipLaunchKernelGGL((k_mfma32<a, b, c>), grid, dim3(256), 0, s, d, n_items);       \
     return hipGetLastError();                                                          \
   }
 
 hipError_t launch_mfma32_kernel(const StepDesc& d, int sa, int sb, int sc, dim3 grid,
                                 hipStream_t s) {
   if (d.rt != 7 || d.nt != 6 || d.kt != 4) return hipErrorInvalidValue;
+  const uint64_t n_items = (uint64_t)grid.x * (uint64_t)d.copies;
+  grid = dim3((unsigned)(n_items < kMfmaGrid ? n_items : kMfmaGrid), 1);
   RQC_MFMA_CASE(ST_C64, ST_C64, ST_C64)
   RQC_MFMA_CASE(ST_C64, ST_C64, ST_F16)
   RQC_MFMA_CASE(ST_C64, ST_C64, ST_BF16)

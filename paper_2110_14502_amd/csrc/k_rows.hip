@@ -20,13 +20,48 @@ namespace rqc {
 // The sum is over the same indices, in another order.  Each wave handles 64
 // rows (four 16-row blocks), a workgroup 256; output columns go 8 at a time
 // through an LDS tile written out in C's own address order.
+//
+// When A is stored in FP16 / BF16 and a K chunk holds 16 or 32 complex
+// values, the products run on the 16-bit matrix cores instead
+// (v_mfma_f32_16x16x32_{f16,bf16}, FP32 accumulation): each MFMA takes 8
+// consecutive real k of a lane's quarter, which are the raw stored words,
+// and B is staged once per copy as packed 16-bit words (pre-scaled by a
+// power of two when it is stored in complex64, as in the 16-bit GEMM).
 // ---------------------------------------------------------------------------
-constexpr int kRowsMaxB = 2048;  // N*K
+constexpr int kRowsMaxB = 4096;  // N*K
 constexpr int kRowsRows = 256;   // rows per workgroup
 constexpr int kRowsLdc = 17;     // floats per staged row: 16 real columns + 1
 constexpr uint64_t kRowsGrid = 256 * 16;  // persistent workgroups (16 per CU)
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4r __attribute__((ext_vector_type(4)));
+typedef _Float16 halfx8r __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8r __attribute__((ext_vector_type(8)));
+
+template <int S>
+__device__ __forceinline__ floatx4 mfma_lp16(u32x4r a, u32x4r b, floatx4 c) {
+  if constexpr (S == ST_F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(halfx8r, a),
+                                                  __builtin_bit_cast(halfx8r, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8r, a),
+                                                   __builtin_bit_cast(bf16x8r, b), c, 0, 0, 0);
+}
+
+template <int S>
+__device__ __forceinline__ uint32_t pack_word(float2 v) {
+  if constexpr (S == ST_F16) {
+    h2 o;
+    o.x = (_Float16)v.x;
+    o.y = (_Float16)v.y;
+    return __builtin_bit_cast(uint32_t, o);
+  } else {
+    b2 o;
+    o.x = (__bf16)v.x;
+    o.y = (__bf16)v.y;
+    return __builtin_bit_cast(uint32_t, o);
+  }
+}
 
 // Raw words of this lane's quarter of a row of K complex values: floats
 // [g*NJ, g*NJ + NJ) (NJ = 2K/4), or for K <= 2 the complex value holding
@@ -139,11 +174,13 @@ __device__ __forceinline__ void load_tile_rows(const StepDesc& d, int64_t oA, in
 template <int KB, int NCH, int SA>
 __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   constexpr int K = 1 << KB;
-  constexpr int NJ = K >= 2 ? (2 * K) / 4 : 1;  // MFMAs per tile and chunk (4 real k each)
+  constexpr int NJ = K >= 2 ? (2 * K) / 4 : 1;  // real k per lane quarter (FP32 MFMAs per chunk)
+  constexpr bool LPM = SA != ST_C64 && KB >= 4;  // 16-bit matrix cores
   extern __shared__ float2 rows_lds[];
   __shared__ TileTab tc;
   __shared__ int64_t bofs[64];
   __shared__ int64_t stepA[kMaxOuter], stepC[kMaxOuter];
+  __shared__ int64_t gch_tab[4];  // C offset of column chunk h
   __shared__ float red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, lc = lane & 15;
@@ -160,6 +197,12 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
     stepA[b] = sa;
     stepC[b] = sc;
   }
+  if (tid < NCH) {
+    int64_t g = 0;
+    for (int j = 0; j < d.nt - d.ncb; ++j)
+      if ((tid >> j) & 1) g += int64_t(1) << d.nh_C[j];
+    gch_tab[tid] = g;
+  }
   float2* Bs = rows_lds;                                    // [N][KT], columns in C's bit order
   float* Cs = reinterpret_cast<float*>(rows_lds + N * KT);  // [R][kRowsLdc]
   build_tab(d.tC, kRowsLdc, 2, 0, tc);  // coordinates in floats
@@ -169,7 +212,9 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
       if ((n >> b) & 1) o += int64_t(1) << d.tB.gpos[b];
     bofs[n] = o;
   }
-  const uint64_t n_rt = (uint64_t)d.n_row_tiles;
+  const uint64_t n_rt = (uint64_t)d.n_row_tiles;  // 2^n_ro
+  const uint64_t rmask = n_rt - 1;
+  const int rsh = d.n_ro;
   const uint64_t n_tiles = n_rt * (uint64_t)d.copies;
   const int nC = R * NC;
   const uint64_t per = (n_tiles + gridDim.x - 1) / gridDim.x;
@@ -177,9 +222,9 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   const uint64_t t_end = t + per < n_tiles ? t + per : n_tiles;
   RawRow<SA, K, NJ> a[4], an[4];
   if (t < t_end) {
-    const int copy = (int)(t / n_rt);
+    const int copy = (int)(t >> rsh);
     int64_t oA, oB, oC;
-    outer_offsets(d, t % n_rt, 0, copy % d.gs_c, copy / d.gs_c, oA, oB, oC);
+    outer_offsets(d, t & rmask, 0, copy % d.gs_c, copy / d.gs_c, oA, oB, oC);
     load_tile_rows<SA, K, NJ>(d, oA, KT, 0, R, wave, lc, g, a);
   }
   int cur = -1, cjs = 0, cjb = 0;
@@ -190,10 +235,17 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   __syncthreads();  // tables ready
   const int64_t glo = tc.g[lane];
   const int32_t clo = tc.c[lane];
+  // Vector stores: this thread's four consecutive low elements (the same
+  // for every group it stores).
+  const int lo4 = (tid & 15) << 2;
+  const int64_t glo4 = tc.g[lo4];
+  int32_t clo4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) clo4[i] = tc.c[lo4 + i];
   int64_t oA = 0, oB = 0, oC = 0;
   for (; t < t_end; ++t) {
-    const uint64_t ro = t % n_rt;
-    const int copy = (int)(t / n_rt);
+    const uint64_t ro = t & rmask;
+    const int copy = (int)(t >> rsh);
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     if (copy != cur || ro == 0) {
       outer_offsets(d, ro, 0, js, jb, oA, oB, oC);
@@ -208,15 +260,32 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
       bad = 0;
       wexp = false;
       __syncthreads();
+      // 16-bit path: B complex64 is pre-scaled so that its max-abs is below
+      // 2^15; the accumulator then carries 2^pB, which the output shift
+      // removes (the stored exponent is unchanged).
+      int pB = 0;
+      if (LPM && d.sb_store == ST_C64) {
+        const float mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
+        if (mB > 0.f && mB <= 3.0e38f) pB = 14 - ceil_log2(mB);
+      }
       for (int i = tid; i < N * KT; i += 256) {
         const int64_t at = oB + bofs[i >> d.kt] + (i & (KT - 1));
         float2 v;
         if (d.sb_store == ST_F16) v = load_c<ST_F16>(d.B, at);
         else if (d.sb_store == ST_BF16) v = load_c<ST_BF16>(d.B, at);
         else v = load_c<ST_C64>(d.B, at);
-        Bs[i] = v;
+        if (LPM) {
+          if (pB) {
+            v.x = ldexpf(v.x, pB);
+            v.y = ldexpf(v.y, pB);
+          }
+          reinterpret_cast<uint32_t*>(Bs)[i] = pack_word<LPM ? SA : ST_F16>(v);
+        } else {
+          Bs[i] = v;
+        }
       }
       sc = compute_scale(d, js, jb);
+      sc.shift += pB;
       cur = copy;
       cjs = js;
       cjb = jb;
@@ -237,37 +306,64 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
       } else if (t + 1 < t_end) {
         const uint64_t tn = t + 1;
         int64_t pA;
-        if (tn % n_rt != 0) {
+        if ((tn & rmask) != 0) {
           pA = oA + stepA[__builtin_ctzll(~ro)];
         } else {
-          const int cn = (int)(tn / n_rt);
+          const int cn = (int)(tn >> rsh);
           int64_t pB, pC;
           outer_offsets(d, 0, 0, cn % d.gs_c, cn / d.gs_c, pA, pB, pC);
         }
         load_tile_rows<SA, K, NJ>(d, pA, KT, 0, R, wave, lc, g, an);
       }
-      float af[4][NJ];
+      if constexpr (LPM) {
+        // MFMA j takes real k g*NJ + 8j .. +7 of every lane quarter: the raw
+        // words 4j .. 4j+3 of A, and four packed complex values of B
+        // expanded to (Br, -Bi) (column parity 0) or (Bi, Br) (parity 1).
+        const uint32_t* Bw = reinterpret_cast<const uint32_t*>(Bs);
 #pragma unroll
-      for (int rb = 0; rb < 4; ++rb) unpack_raw<SA, K, NJ>(a[rb], g, af[rb]);
+        for (int h = 0; h < NCH; ++h) {
+          const int n = h * NC + (lc >> 1), q = lc & 1;
+          const bool col_ok = (lc >> 1) < NC;
 #pragma unroll
-      for (int h = 0; h < NCH; ++h) {
-        // B operand: real column lc of column chunk h (complex column
-        // h*NC + lc/2, part lc&1), real summation index of MFMA j.
-        float bop[NJ];
-        const int n = h * NC + (lc >> 1), q = lc & 1;
-        const bool col_ok = (lc >> 1) < NC;
+          for (int j = 0; j < NJ / 8; ++j) {
+            u32x4r bw = {0u, 0u, 0u, 0u};
+            if (col_ok)
+              bw = *reinterpret_cast<const u32x4r*>(Bw + n * KT + kc * K + g * (NJ / 2) + 4 * j);
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int rk = K >= 2 ? g * NJ + j : g;
-          const bool ok = col_ok && rk < 2 * K;
-          const float2 b = ok ? Bs[n * KT + kc * K + (rk >> 1)] : make_float2(0.f, 0.f);
-          bop[j] = (rk & 1) == 0 ? (q == 0 ? b.x : b.y) : (q == 0 ? -b.y : b.x);
+            for (int i = 0; i < 4; ++i)
+              bw[i] = q ? ((bw[i] >> 16) | (bw[i] << 16)) : (bw[i] ^ 0x80000000u);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+              const u32x4r aw = {a[rb].w[4 * j], a[rb].w[4 * j + 1], a[rb].w[4 * j + 2],
+                                 a[rb].w[4 * j + 3]};
+              acc[rb][h] = mfma_lp16<LPM ? SA : ST_F16>(aw, bw, acc[rb][h]);
+            }
+          }
         }
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-          for (int j = 0; j < NJ; ++j)
-            acc[rb][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][j], bop[j], acc[rb][h], 0, 0, 0);
+      } else {
+        float af[4][NJ];
+  #pragma unroll
+        for (int rb = 0; rb < 4; ++rb) unpack_raw<SA, K, NJ>(a[rb], g, af[rb]);
+  #pragma unroll
+        for (int h = 0; h < NCH; ++h) {
+          // B operand: real column lc of column chunk h (complex column
+          // h*NC + lc/2, part lc&1), real summation index of MFMA j.
+          float bop[NJ];
+          const int n = h * NC + (lc >> 1), q = lc & 1;
+          const bool col_ok = (lc >> 1) < NC;
+  #pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int rk = K >= 2 ? g * NJ + j : g;
+            const bool ok = col_ok && rk < 2 * K;
+            const float2 b = ok ? Bs[n * KT + kc * K + (rk >> 1)] : make_float2(0.f, 0.f);
+            bop[j] = (rk & 1) == 0 ? (q == 0 ? b.x : b.y) : (q == 0 ? -b.y : b.x);
+          }
+  #pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+  #pragma unroll
+            for (int j = 0; j < NJ; ++j)
+              acc[rb][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][j], bop[j], acc[rb][h], 0, 0, 0);
+        }
       }
       if (kc + 1 < nkc) {
 #pragma unroll
@@ -288,33 +384,56 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
           }
       }
       __syncthreads();
-      int64_t gch = 0;
-      for (int j = 0; j < d.nt - d.ncb; ++j)
-        if ((h >> j) & 1) gch += int64_t(1) << d.nh_C[j];
+      const int64_t gch = gch_tab[h];
+      // At most 2048 staged elements (256 rows x 8 columns): eight per
+      // thread, or two groups of four.  Table and staging reads are issued
+      // together before the stores so that their latencies overlap.
       if (d.vec_c) {
-        // Four consecutive elements per thread: C addresses at..at+3.
-        for (int v = tid; v < (nC >> 2); v += 256) {
-          const int lo = (v & 15) << 2, hi = 64 + (v >> 4);
-          const int64_t at = oC + gch + tc.g[lo] + tc.g[hi];
-          float2 x[4];
+        int64_t g[2];
+        int32_t cc[2];
+        float2 x[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int v = tid + 256 * u;
+          const int hi = 64 + (v < (nC >> 2) ? (v >> 4) : 0);
+          g[u] = tc.g[hi];
+          cc[u] = tc.c[hi];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int c = tc.c[lo + i] + tc.c[hi];
-            x[i] = make_float2(Cs[c], Cs[c + 1]);
+            const int c = clo4[i] + cc[u];
+            x[u][i] = make_float2(Cs[c], Cs[c + 1]);
           }
-          if (d.sc_store == ST_F16) store_out4<ST_F16>(d, at, x, sc, lmax, bad);
-          else if (d.sc_store == ST_BF16) store_out4<ST_BF16>(d, at, x, sc, lmax, bad);
-          else store_out4<ST_C64>(d, at, x, sc, lmax, bad);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          if (tid + 256 * u >= (nC >> 2)) break;
+          const int64_t at = oC + gch + glo4 + g[u];
+          if (d.sc_store == ST_F16) store_out4<ST_F16>(d, at, x[u], sc, lmax, bad);
+          else if (d.sc_store == ST_BF16) store_out4<ST_BF16>(d, at, x[u], sc, lmax, bad);
+          else store_out4<ST_C64>(d, at, x[u], sc, lmax, bad);
         }
       } else {
-        for (int e = tid; e < nC; e += 256) {
-          const int hi = 64 + (e >> 6);
-          const int c = clo + tc.c[hi];
-          const float2 v = make_float2(Cs[c], Cs[c + 1]);
-          const int64_t at = oC + gch + glo + tc.g[hi];
-          if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, v, sc, lmax, bad);
-          else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, v, sc, lmax, bad);
-          else store_out<ST_C64>(d, at, v, sc, lmax, bad);
+        int64_t g[8];
+        int32_t cc[8];
+        float2 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = tid + 256 * u;
+          const int hi = 64 + (e < nC ? (e >> 6) : 0);
+          g[u] = tc.g[hi];
+          cc[u] = clo + tc.c[hi];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = make_float2(Cs[cc[u]], Cs[cc[u] + 1]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (tid + 256 * u >= nC) break;
+          const int64_t at = oC + gch + glo + g[u];
+          if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, x[u], sc, lmax, bad);
+          else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, x[u], sc, lmax, bad);
+          else store_out<ST_C64>(d, at, x[u], sc, lmax, bad);
         }
       }
     }

@@ -40,11 +40,15 @@ __device__ __forceinline__ float2 load_c<ST_BF16>(const void* p, int64_t i) {
   return make_float2((float)v.x, (float)v.y);
 }
 
+// Step outputs are written with nontemporal stores: they are read back by a
+// later step, mostly after far more data than the caches hold has passed.
 template <int S>
 __device__ __forceinline__ void store_c(void* p, int64_t i, float2 v);
 template <>
 __device__ __forceinline__ void store_c<ST_C64>(void* p, int64_t i, float2 v) {
-  reinterpret_cast<float2*>(p)[i] = v;
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  f2v w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<f2v*>(p) + i);
 }
 template <>
 __device__ __forceinline__ void store_c<ST_F16>(void* p, int64_t i, float2 v) {
@@ -183,6 +187,57 @@ __device__ __forceinline__ void k_offsets(const StepDesc& d, uint32_t kc, int64_
     }
 }
 
+// Outer-bit weights of a step, copied into LDS once per workgroup.  The
+// descriptor's bit positions are bytes in the kernel-argument segment: a loop
+// over them reads them with vector loads, and each such load waits for every
+// load and store the wave has in flight (the counter is in order), which
+// would stall the prefetches and output stores of a tile loop.
+struct OuterTab {
+  int64_t rA[kMaxOuter], rC[kMaxOuter];  // row tile bit i
+  int64_t nB[kMaxOuter], nC[kMaxOuter];  // column tile bit i
+  int64_t kA[kMaxOuter], kB[kMaxOuter];  // K chunk bit i
+};
+
+__device__ __forceinline__ void build_outer(const StepDesc& d, OuterTab& o) {
+  for (int i = threadIdx.x; i < kMaxOuter; i += blockDim.x) {
+    o.rA[i] = i < d.n_ro ? int64_t(1) << d.ro_A[i] : 0;
+    o.rC[i] = i < d.n_ro ? int64_t(1) << d.ro_C[i] : 0;
+    o.nB[i] = i < d.n_no ? int64_t(1) << d.no_B[i] : 0;
+    o.nC[i] = i < d.n_no ? int64_t(1) << d.no_C[i] : 0;
+    o.kA[i] = i < d.n_ko ? int64_t(1) << d.ko_A[i] : 0;
+    o.kB[i] = i < d.n_ko ? int64_t(1) << d.ko_B[i] : 0;
+  }
+}
+
+__device__ __forceinline__ void outer_offsets(const StepDesc& d, const OuterTab& o, uint64_t ro,
+                                              uint64_t no, int js, int jb, int64_t& oA,
+                                              int64_t& oB, int64_t& oC) {
+  oA = js * d.sA_s + jb * d.sA_b;
+  oB = js * d.sB_s + jb * d.sB_b;
+  oC = js * d.sC_s + jb * d.sC_b;
+  for (int i = 0; i < d.n_ro; ++i)
+    if ((ro >> i) & 1) {
+      oA += o.rA[i];
+      oC += o.rC[i];
+    }
+  for (int i = 0; i < d.n_no; ++i)
+    if ((no >> i) & 1) {
+      oB += o.nB[i];
+      oC += o.nC[i];
+    }
+}
+
+__device__ __forceinline__ void k_offsets(const StepDesc& d, const OuterTab& o, uint32_t kc,
+                                          int64_t& kA, int64_t& kB) {
+  kA = 0;
+  kB = 0;
+  for (int i = 0; i < d.n_ko; ++i)
+    if ((kc >> i) & 1) {
+      kA += o.kA[i];
+      kB += o.kB[i];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Offset tables of a tile: element e (bits in increasing address order) sits
 // at global offset g_lo[e & 63] + g_hi[e >> 6] and at LDS coordinate
@@ -246,9 +301,11 @@ __device__ __forceinline__ void store_out4(const StepDesc& d, int64_t at, float2
     }
   }
   if (SC == ST_C64) {
-    float4* q = reinterpret_cast<float4*>(reinterpret_cast<float2*>(d.C) + at);
-    q[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-    q[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    f4v* q = reinterpret_cast<f4v*>(reinterpret_cast<float2*>(d.C) + at);
+    f4v w0 = {v[0].x, v[0].y, v[1].x, v[1].y}, w1 = {v[2].x, v[2].y, v[3].x, v[3].y};
+    __builtin_nontemporal_store(w0, q);
+    __builtin_nontemporal_store(w1, q + 1);
   } else {
     uint32_t w[4];
 #pragma unroll
@@ -321,6 +378,33 @@ __device__ __forceinline__ void build_tab_skip(const TileMap& t, int skip, int r
   }
 }
 
+
+// Stores one staged half (64 rows) of a 128 x 64 output tile: thread
+// (wave, lane) writes C-order elements lane + 64 (wave + 4 j), j < 16.  The
+// table and staging reads go out in groups of G so that their latencies
+// overlap instead of adding up per element.  `base` is the tile's C offset
+// plus this lane's low-bit offset, `cl` the lane's staging coordinate.
+template <int SC, int G>
+__device__ __forceinline__ void store_half(const StepDesc& d, const float* Cs, const TileTab& tcs,
+                                           int64_t base, int cl, int wave, const Scale& sc,
+                                           float& lmax, int& bad) {
+#pragma unroll
+  for (int j0 = 0; j0 < 16; j0 += G) {
+    int32_t c[G];
+    int64_t g[G];
+    float2 v[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int hi = 64 + wave + 4 * (j0 + j);
+      c[j] = cl + tcs.c[hi];
+      g[j] = tcs.g[hi];
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) v[j] = make_float2(Cs[c[j]], Cs[c[j] + 1]);
+#pragma unroll
+    for (int j = 0; j < G; ++j) store_out<SC>(d, base + g[j], v[j], sc, lmax, bad);
+  }
+}
 
 // Per-kernel launchers (one translation unit each).
 hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t s);
