@@ -246,32 +246,37 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
   const int n_kc = 1 << d.n_ko;
   const int tbits = d.n_ro + d.n_no;
   const uint64_t tmask = (uint64_t(1) << tbits) - 1, cmask = (uint64_t(1) << d.n_no) - 1;
-  const uint64_t per = (n_items + gridDim.x - 1) / gridDim.x;
-  uint64_t t = (uint64_t)blockIdx.x * per;
-  const uint64_t t_end = t + per < n_items ? t + per : n_items;
+  // Step i of the walk covers items i*G .. i*G + G - 1, dealt so that the
+  // workgroups of one XCD (blocks go round-robin to the 8 XCDs) take
+  // consecutive items: they share rows of A in that XCD's L2.
+  const uint64_t G = gridDim.x;
+  uint64_t t = (G & 7) == 0 ? (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : blockIdx.x;
   int cur = -1, cjs = 0, cjb = 0;
   bool wexp = false;
-  CopyScale cs{0, 0, Scale{0, 0}};
+  // A copy's scales are read when its first tile is prefetched (before those
+  // loads are issued), not at the top of the tile, where the wait for them
+  // would also wait for the previous tile's output stores.
+  CopyScale cs{0, 0, Scale{0, 0}}, ncs{0, 0, Scale{0, 0}};
   float lmax = 0.f;
   int bad = 0;
-  if (t < t_end) {
+  if (t < n_items) {
     const int copy = (int)(t >> tbits);
     const uint64_t bid = t & tmask;
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     int64_t oA, oB, oC;
     outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
-    cs = copy_scale(js, jb);
-    load_chunk(oA, oB, 0, cs.pA, cs.pB);
+    ncs = copy_scale(js, jb);
+    load_chunk(oA, oB, 0, ncs.pA, ncs.pB);
     store_chunk(0);
   }
   __syncthreads();
-  for (; t < t_end; ++t) {
+  for (; t < n_items; t += G) {
     const int copy = (int)(t >> tbits);
     const uint64_t bid = t & tmask;
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     if (copy != cur) {
       if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, cs.sc);
-      cs = copy_scale(js, jb);
+      cs = ncs;
       lmax = 0.f;
       bad = 0;
       wexp = false;
@@ -282,7 +287,7 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
     wexp = wexp || bid == 0;
     int64_t oA, oB, oC;
     outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
-    const bool next_tile = t + 1 < t_end;
+    const bool next_tile = t + G < n_items;
 
     floatx16 acc[2][2];
 #pragma unroll
@@ -300,17 +305,13 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
       if (more) {
         load_chunk(oA, oB, kc + 1, cs.pA, cs.pB);
       } else if (next_tile) {
-        const int cn = (int)((t + 1) >> tbits);
-        const uint64_t bn = (t + 1) & tmask;
+        const int cn = (int)((t + G) >> tbits);
+        const uint64_t bn = (t + G) & tmask;
         const int jsn = cn % d.gs_c, jbn = cn / d.gs_c;
         int64_t pA, pB, pC;
         outer_offsets(d, ot, bn >> d.n_no, bn & cmask, jsn, jbn, pA, pB, pC);
-        if (cn == copy) {
-          load_chunk(pA, pB, 0, cs.pA, cs.pB);
-        } else {
-          const CopyScale csn = copy_scale(jsn, jbn);
-          load_chunk(pA, pB, 0, csn.pA, csn.pB);
-        }
+        if (cn != copy) ncs = copy_scale(jsn, jbn);
+        load_chunk(pA, pB, 0, ncs.pA, ncs.pB);
       }
       const uint32_t* As = Abuf + cb * kLABuf + (wm * 64 + lrow) * kLRow + kq;
       const uint32_t* Bs = Bbuf + cb * kLBBuf + (wn * 32 + ncol) * kLRow + kq;

@@ -11,11 +11,13 @@ namespace rqc {
 // staged through LDS in two halves of 64 rows (inside the operand buffers)
 // and stored in C's address order.
 //
-// Persistent: each workgroup walks a contiguous range of (copy, tile) items,
-// column tiles fastest, so consecutive tiles share the rows of A.  The first
-// chunk of the next tile is loaded while the current tile's last chunk is
-// multiplied and its output stored; the scale and the running max-abs change
-// only with the copy.  53 KB of LDS; two workgroups per CU.
+// Persistent: the (copy, tile) items, column tiles fastest, are walked in
+// steps of one item per workgroup, the workgroups of an XCD taking
+// consecutive items, so that the tiles in flight on an XCD share rows of A.
+// A workgroup loads the first chunk of its next tile while its current
+// tile's last chunk is multiplied and the output stored; the scale and the
+// running max-abs are flushed when the copy changes.  53 KB of LDS; two
+// workgroups per CU.
 // ---------------------------------------------------------------------------
 constexpr unsigned kMfmaGrid = 256 * 2;
 
@@ -76,9 +78,11 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
   // (t & tmask) >> n_no, column tile t & cmask.
   const int tb = d.n_ro + d.n_no;
   const uint64_t tmask = (uint64_t(1) << tb) - 1, cmask = (uint64_t(1) << d.n_no) - 1;
-  const uint64_t per = (n_items + gridDim.x - 1) / gridDim.x;
-  uint64_t t = (uint64_t)blockIdx.x * per;
-  const uint64_t t_end = t + per < n_items ? t + per : n_items;
+  // Step i of the walk covers items i*G .. i*G + G - 1, dealt so that the
+  // workgroups of one XCD (blocks go round-robin to the 8 XCDs) take
+  // consecutive items: they share rows of A in that XCD's L2.
+  const uint64_t G = gridDim.x;
+  uint64_t t = (G & 7) == 0 ? (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : blockIdx.x;
 
   auto item_offsets = [&](uint64_t it, int64_t& oA, int64_t& oB, int64_t& oC) {
     const int copy = (int)(it >> tb);
@@ -106,8 +110,14 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
     for (int j = 0; j < 4; ++j) Bn[lB[j]] = rb[j];
   };
 
-  if (t < t_end) {
+  // The scale of a copy is read when its first tile is prefetched (before
+  // those loads are issued), not at the top of the tile, where the wait for
+  // it would also wait for the previous tile's output stores.
+  Scale sc{0, 0}, nsc{0, 0};
+  if (t < n_items) {
     int64_t oA, oB, oC;
+    const int copy = (int)(t >> tb);
+    nsc = compute_scale(d, copy % d.gs_c, copy / d.gs_c);
     item_offsets(t, oA, oB, oC);
     load_chunk(oA, oB, 0);
     store_chunk(0);
@@ -116,16 +126,15 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
   int cur = -1;
   int cjs = 0, cjb = 0;
   bool wexp = false;
-  Scale sc{0, 0};
   float lmax = 0.f;
   int bad = 0;
-  for (; t < t_end; ++t) {
+  for (; t < n_items; t += G) {
     const int copy = (int)(t >> tb);
     const uint64_t bid = t & tmask;
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     if (copy != cur) {
       if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
-      sc = compute_scale(d, js, jb);
+      sc = nsc;
       lmax = 0.f;
       bad = 0;
       wexp = false;
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
     wexp = wexp || bid == 0;
     int64_t oA, oB, oC;
     outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
-    const bool next_tile = t + 1 < t_end;
+    const bool next_tile = t + G < n_items;
 
     floatx16 acc[2][2];
 #pragma unroll
@@ -154,8 +163,10 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
       if (more) {
         load_chunk(oA, oB, kc + 1);
       } else if (next_tile) {
+        const int cn = (int)((t + G) >> tb);
+        if (cn != copy) nsc = compute_scale(d, cn % d.gs_c, cn / d.gs_c);
         int64_t pA, pB, pC;
-        item_offsets(t + 1, pA, pB, pC);
+        item_offsets(t + G, pA, pB, pC);
         load_chunk(pA, pB, 0);
       }
       const float* As = Abuf + cb * kABuf + cpart * kAPlane + wm * 64 + lrow;

@@ -1,4 +1,6 @@
 // Generic table-driven SIMT contraction kernel and its split-K reduction.
+#include <type_traits>
+
 #include "kernels_dev.h"
 
 namespace rqc {
@@ -11,11 +13,51 @@ namespace rqc {
 constexpr int kSimtBlock = 256;
 constexpr int kSimtMaxC = 8;  // C tile <= 2048 elements
 
+// Loads elements tid + 256 i (i < 16, below n) of an operand tile, whose
+// offsets come from the table, into the LDS tile at the table coordinates,
+// in rounds of kSimtBatch loads that are all issued before any is written.
+constexpr int kSimtBatch = 8;
+template <int S>
+__device__ __forceinline__ void simt_stage(const void* src, int64_t base, const TileTab& t,
+                                           int c_lo, int n, int tid, float2* dst) {
+  typedef typename std::conditional<S == ST_C64, uint2, uint32_t>::type Raw;
+#pragma unroll
+  for (int r = 0; r < 16; r += kSimtBatch) {
+    if (tid + r * kSimtBlock >= n) break;
+    Raw v[kSimtBatch];
+    int at[kSimtBatch];
+#pragma unroll
+    for (int i = 0; i < kSimtBatch; ++i) {
+      const int e = tid + (r + i) * kSimtBlock;
+      if (e < n) {
+        const int hi = 64 + (e >> 6);
+        at[i] = c_lo + t.c[hi];
+        v[i] = reinterpret_cast<const Raw*>(src)[base + t.g[hi]];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kSimtBatch; ++i) {
+      if (tid + (r + i) * kSimtBlock < n) {
+        if constexpr (S == ST_C64) {
+          dst[at[i]] = make_float2(__uint_as_float(v[i].x), __uint_as_float(v[i].y));
+        } else if constexpr (S == ST_F16) {
+          const h2 h = __builtin_bit_cast(h2, v[i]);
+          dst[at[i]] = make_float2((float)h.x, (float)h.y);
+        } else {
+          const b2 h = __builtin_bit_cast(b2, v[i]);
+          dst[at[i]] = make_float2((float)h.x, (float)h.y);
+        }
+      }
+    }
+  }
+}
+
 template <int SA, int SB, int SC>
 __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
   extern __shared__ float2 smem2[];
   __shared__ TileTab ta, tb, tcc;
   __shared__ float red[16];
+  __shared__ float2 qsum[kSimtBlock];  // quarter sums of a tiny tile
   const int R = 1 << d.rt, N = 1 << d.nt, K = 1 << d.kt;
   const int ldA = K + 1, ldB = N + 1;
   float2* As = smem2;
@@ -52,6 +94,19 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
   }
   const int64_t gAlo = ta.g[lane], gBlo = tb.g[lane];
   const int32_t cAlo = ta.c[lane], cBlo = tb.c[lane];
+  // Tiny tiles (at most 64 outputs, as in the long sums of the last steps):
+  // the four waves take one quarter of each K chunk each, so that every
+  // thread multiplies, and the quarters are added in order at the end.
+  const bool quarters = nC <= 64 && K >= 4;
+  const int qk = K >> 2, q = tid >> 6;
+  int qrow = 0, qcol = 0;
+  int64_t qg = 0;
+  if (quarters) {
+    const int c = clo + tcc.c[64];
+    qrow = c >> 12;
+    qcol = c & 4095;
+    qg = glo + tcc.g[64];
+  }
   for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     int64_t oA, oB, oC;
@@ -62,15 +117,29 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
     for (int kc = kc0; kc < kc0 + n_kc; ++kc) {
       int64_t kA, kB;
       k_offsets(d, kc, kA, kB);
-      for (int e = tid; e < nA; e += kSimtBlock) {
-        const int hi = 64 + (e >> 6);
-        As[cAlo + ta.c[hi]] = load_c<SA>(d.A, oA + kA + gAlo + ta.g[hi]);
-      }
-      for (int e = tid; e < nB; e += kSimtBlock) {
-        const int hi = 64 + (e >> 6);
-        Bs[cBlo + tb.c[hi]] = load_c<SB>(d.B, oB + kB + gBlo + tb.g[hi]);
-      }
+      // Up to 16 elements of each operand per thread (tiles hold at most
+      // 4096): all loads of an operand are issued, as raw stored words,
+      // before any is converted and written.
+      simt_stage<SA>(d.A, oA + kA + gAlo, ta, cAlo, nA, tid, As);
+      simt_stage<SB>(d.B, oB + kB + gBlo, tb, cBlo, nB, tid, Bs);
       __syncthreads();
+      if (quarters) {
+        if (lane < nC) {
+          const float2* ar = As + qrow * ldA + q * qk;
+          const float2* bc = Bs + qcol + q * qk * ldB;
+          float sx = acc[0].x, sy = acc[0].y;
+          for (int k = 0; k < qk; ++k) {
+            const float2 a = ar[k], b = bc[k * ldB];
+            sx = fmaf(a.x, b.x, sx);
+            sx = fmaf(-a.y, b.y, sx);
+            sy = fmaf(a.x, b.y, sy);
+            sy = fmaf(a.y, b.x, sy);
+          }
+          acc[0] = make_float2(sx, sy);
+        }
+        __syncthreads();
+        continue;
+      }
 #pragma unroll
       for (int i = 0; i < kSimtMaxC; ++i) {
         if (tid + i * kSimtBlock < nC) {
@@ -88,6 +157,31 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
         }
       }
       __syncthreads();
+    }
+    if (quarters) {
+      // Output lane of wave 0 = sum of the four quarters, in wave order.
+      qsum[tid] = acc[0];
+      __syncthreads();
+      if (q == 0 && lane < nC) {
+        float sx = 0.f, sy = 0.f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          sx += qsum[w * 64 + lane].x;
+          sy += qsum[w * 64 + lane].y;
+        }
+        acc[0] = make_float2(sx, sy);
+      }
+      __syncthreads();
+      if (d.ksplit) {
+        if (q == 0 && lane < nC) d.P[(int64_t)split * d.p_stride + oC + qg] = acc[0];
+        continue;
+      }
+      const Scale sc = compute_scale(d, js, jb);
+      float lmax = 0.f;
+      int bad = 0;
+      if (q == 0 && lane < nC) store_out<SC>(d, oC + qg, acc[0], sc, lmax, bad);
+      finish_scale<kSimtBlock>(d, js, jb, lmax, bad, red, ro == 0 && no == 0, sc);
+      continue;
     }
     if (d.ksplit) {
       // Partial sums: plain complex64, reduced by k_splitk_reduce.
@@ -151,6 +245,9 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(StepDesc d) {
 
 hipError_t launch_simt_kernel(const StepDesc& d, int sa, int sb, int sc, uint64_t tiles,
                               hipStream_t s) {
+  // Operand tiles of at most 4096 elements (16 per thread) and C tiles of
+  // at most 2048 (kSimtMaxC per thread).
+  if (d.rt + d.kt > 12 || d.kt + d.nt > 12 || d.rt + d.nt > 11) return hipErrorInvalidValue;
   const unsigned gy = (unsigned)(d.copies < 65535 ? d.copies : 65535);
   dim3 grid((unsigned)(tiles << d.ksplit), gy);
   hipError_t e = hipSuccess;
