@@ -169,6 +169,13 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
   __syncthreads();  // operand tables copied out; the buffers are free
   const int64_t g_lane = tcs.g[lane];
   const int c_lane = tcs.c[lane];
+  // Vector stores when C's two lowest address bits are the two lowest
+  // C-order bits of the staged half.
+  const bool vec_c = d.tC.nbits > 2 && hb > 1 && d.tC.gpos[0] == 0 && d.tC.gpos[1] == 1;
+  const int64_t g_lo4 = tcs.g[(tid & 15) << 2];
+  int c_lo4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) c_lo4[i] = tcs.c[((tid & 15) << 2) + i];
 
   const int lrow = lane & 31;
   const int kq = (lane >> 5) * 4;      // first complex k of the lane's 8 real k
@@ -346,7 +353,10 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
             }
       }
       __syncthreads();
-      store_half<SC, VEC ? 8 : 4>(d, Cs, tcs, oC + g_lane + (h ? g_half : 0), c_lane, wave, cs.sc, lmax, bad);
+      if (vec_c)
+        store_half4<SC>(d, Cs, tcs, oC + g_lo4 + (h ? g_half : 0), c_lo4, tid, cs.sc, lmax, bad);
+      else
+        store_half<SC, VEC ? 8 : 4>(d, Cs, tcs, oC + g_lane + (h ? g_half : 0), c_lane, wave, cs.sc, lmax, bad);
       __syncthreads();
     }
     if (next_tile) {

@@ -64,6 +64,13 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
   const int64_t g_half = int64_t(1) << d.tC.gpos[hb];
   const int64_t g_lane = tcs.g[lane];
   const int c_lane = tcs.c[lane];
+  // Vector stores when C's two lowest address bits are the two lowest
+  // C-order bits of the staged half.
+  const bool vec_c = d.tC.nbits > 2 && hb > 1 && d.tC.gpos[0] == 0 && d.tC.gpos[1] == 1;
+  const int64_t g_lo4 = tcs.g[(tid & 15) << 2];
+  int c_lo4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) c_lo4[i] = tcs.c[((tid & 15) << 2) + i];
 
   // Lane roles inside the real-expanded operands.
   const int lrow = lane & 31;          // row inside a 32-row block
@@ -216,7 +223,10 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
             }
       }
       __syncthreads();
-      store_half<SC, 8>(d, Cs, tcs, oC + g_lane + (h ? g_half : 0), c_lane, wave, sc, lmax, bad);
+      if (vec_c)
+        store_half4<SC>(d, Cs, tcs, oC + g_lo4 + (h ? g_half : 0), c_lo4, tid, sc, lmax, bad);
+      else
+        store_half<SC, 8>(d, Cs, tcs, oC + g_lane + (h ? g_half : 0), c_lane, wave, sc, lmax, bad);
       __syncthreads();
     }
     if (next_tile) {

@@ -406,6 +406,32 @@ __device__ __forceinline__ void store_half(const StepDesc& d, const float* Cs, c
   }
 }
 
+// Vector variant of store_half for tiles whose two lowest C-order bits are
+// C's two lowest address bits (and not the half bit): thread t writes the
+// groups of four consecutive elements 4 (t + 256 j), j < 4, with one
+// 16-byte store (16-bit storage) or two (complex64) per group.  `lo4` are
+// the thread's low-bit offset and the staging coordinates of its four.
+template <int SC>
+__device__ __forceinline__ void store_half4(const StepDesc& d, const float* Cs, const TileTab& tcs,
+                                            int64_t base, const int (&lo4)[4], int tid,
+                                            const Scale& sc, float& lmax, int& bad) {
+  int64_t g[4];
+  int c[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int hi = 64 + (tid >> 4) + 16 * j;
+    g[j] = tcs.g[hi];
+    c[j] = tcs.c[hi];
+  }
+  float2 x[4][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x[j][i] = make_float2(Cs[lo4[i] + c[j]], Cs[lo4[i] + c[j] + 1]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) store_out4<SC>(d, base + g[j], x[j], sc, lmax, bad);
+}
+
 // Per-kernel launchers (one translation unit each).
 hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t s);
 hipError_t launch_simt_kernel(const StepDesc& d, int sa, int sb, int sc, uint64_t tiles,
