@@ -169,7 +169,7 @@ __device__ __forceinline__ void load_tile_rows(const StepDesc& d, int64_t oA, in
 // once; B, its scale
 // and the running max-abs change only with the copy; the rows of the next
 // tile (or K chunk) are loaded while the current one is multiplied and
-// written.  KB: bits of one K chunk (the whole sum when k <= 5); NCH: chunks
+// written.  KB: bits of one K chunk (the whole sum when k <= 4); NCH: chunks
 // of 8 complex output columns, whose accumulators stay in registers.
 template <int KB, int NCH, int SA>
 __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
@@ -471,7 +471,9 @@ static hipError_t launch_rows(const StepDesc& d, int sa, dim3 grid, hipStream_t 
   return hipErrorInvalidValue;
 }
 
-// K chunks: the whole sum for k <= 5, chunks of 16 complex values beyond.
+// K chunks: the whole sum for k <= 4, chunks of 16 complex values beyond
+// (a 32-value chunk would hold twice the rows' registers and halve the
+// number of resident waves).
 hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
   switch (d.kt) {
     case 0: return launch_rows<0>(d, sa, grid, s);
@@ -479,7 +481,7 @@ hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t 
     case 2: return launch_rows<2>(d, sa, grid, s);
     case 3: return launch_rows<3>(d, sa, grid, s);
     case 4: return launch_rows<4>(d, sa, grid, s);
-    case 5: return launch_rows<5>(d, sa, grid, s);
+    case 5:
     case 6:
     case 7: return launch_rows<4>(d, sa, grid, s);
   }
