@@ -80,9 +80,12 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--trials", type=int, default=1024)
     ap.add_argument("--plan-seed", type=int, default=2)
-    ap.add_argument("--plan-candidates", type=int, default=8,
-                    help="plans searched with seeds plan-seed.. and timed on a sample of "
-                         "slices; the fastest is benchmarked (1 = no selection)")
+    ap.add_argument("--plan-candidates", type=int, default=256,
+                    help="plans searched with seeds plan-seed.. (in parallel) and ranked by "
+                         "the planner's cost (1 = no selection)")
+    ap.add_argument("--probe-candidates", type=int, default=8,
+                    help="best-ranked plans timed on a sample of slices; the fastest is "
+                         "benchmarked")
     ap.add_argument("--probe-slices", type=int, default=32)
     ap.add_argument("--roofline-kernel", type=int, default=-1, choices=[-1, 0, 1, 2],
                     help="kernel kind bracketed in the timed region (0 simt, 1 mfma, 2 rows); "
@@ -179,18 +182,43 @@ def _profile_traffic(kind, flops_per_launch, bytes_per_launch):
         return None
 
 
+def plan_cost(plan):
+    """The planner's time-like cost of a plan: over the slice-dependent
+    steps, the sum of max(complex multiply-adds, 20 x elements moved)."""
+    return sum(max(s["flops"] / 8.0, 20.0 * s["bytes_c64"] / 8.0)
+               for s in plan.steps() if s["depends_on_slice"])
+
+
 def select_plan(R, net, bits, a):
     """Plan autotuning: search plan-candidates plans (planner seeds
-    plan-seed, plan-seed+1, ...), time each on the device on a sample of
-    probe-slices slices (one captured-graph call, after a warm call), and
-    return the seed of the fastest with the measured times."""
+    plan-seed, plan-seed+1, ...) on host threads in parallel, rank them by
+    the planner's time-like cost, time the probe-candidates best on the
+    device on a sample of probe-slices slices (after a warm call), and return
+    the seed and plan of the fastest with the measured times."""
     import torch
+    from concurrent.futures import ThreadPoolExecutor
     seeds = [a.plan_seed + i for i in range(max(1, a.plan_candidates))]
-    if len(seeds) == 1:
-        return seeds[0], {"candidates": 1}
-    times = {}
-    for sd in seeds:
+    workers = max(1, min(len(seeds), 16, os.cpu_count() or 1))
+
+    def make(sd):
         p = R.Plan(net, n_sliced=a.sliced, path_trials=a.trials, seed=sd)
+        return plan_cost(p), sd, p
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(workers) as ex:  # the planner releases the GIL
+        ranked = sorted(ex.map(make, seeds), key=lambda x: (x[0], x[1]))
+    t_plan = time.perf_counter() - t0
+    log(f"{len(seeds)} plans in {t_plan:.1f} s on {workers} threads")
+    costs = {str(sd): c for c, sd, _ in ranked}
+    ranked = ranked[:max(1, a.probe_candidates)]
+    seeds = [sd for _, sd, _ in ranked]
+    plans = [p for _, _, p in ranked]
+    if len(seeds) == 1:
+        return seeds[0], {"candidates": len(costs), "plan_seconds": round(t_plan, 2)}, plans[0]
+    times = {}
+    best_plan, best_t = None, float("inf")
+    for i, sd in enumerate(seeds):
+        p, plans[i] = plans[i], None
         n_ids = min(a.probe_slices, p.info()["n_slices"])
         p.bind("cuda:0")
         lo, pref = p.workspace_bytes(n_ids, 1, R.PRECISIONS[a.prec])
@@ -199,16 +227,22 @@ def select_plan(R, net, bits, a):
         ids = list(range(n_ids))
         p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[a.prec], workspace=ws)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
         p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[a.prec], workspace=ws)
         torch.cuda.synchronize()
-        times[sd] = 1000.0 * (time.perf_counter() - t0) / n_ids
+        times[sd] = 1000.0 * (time.perf_counter() - t1) / n_ids
         log(f"plan seed {sd}: {times[sd]:.3f} ms per slice on {n_ids} slices")
-        del p, ws
+        del ws
+        if times[sd] < best_t:  # keep only the fastest plan alive
+            best_plan, best_t = p, times[sd]
+        del p
     best = min(times, key=times.get)
-    return best, {"candidates": len(seeds), "probe_slices": a.probe_slices,
+    plan = best_plan
+    return best, {"candidates": len(costs), "probed": len(seeds), "probe_slices": a.probe_slices,
+                  "plan_seconds": round(t_plan, 2),
+                  "cost_rank_of_chosen": seeds.index(best),
                   "ms_per_slice_by_seed": {str(k): round(v, 4) for k, v in times.items()},
-                  "chosen_seed": best}
+                  "chosen_seed": best}, plan
 
 
 def roofline(kind, tim, a, flops_total, kind_ms):
@@ -592,8 +626,7 @@ def main():
     bits = rqcgen.random_bits(n - a.open, a.seed)
     net = R.Network(R.Circuit.from_rqcgen(circ), openq)
     t = time.perf_counter()
-    chosen, probe = select_plan(R, net, bits, a)
-    plan = R.Plan(net, n_sliced=a.sliced, path_trials=a.trials, seed=chosen)
+    chosen, probe, plan = select_plan(R, net, bits, a)
     t_plan = time.perf_counter() - t
     info = plan.info()
     log(f"plan: {t_plan:.1f}s, log2 flops/slice {math.log2(info['flops_per_slice']):.2f}, "
