@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--share-local", type=int, default=10,
                     help="share mode: enumerated sliced wires (2^L slices)")
     ap.add_argument("--share-trials", type=int, default=256)
+    ap.add_argument("--share-candidates", type=int, default=16,
+                    help="share mode: plans searched (seeds from the circuit seed on)")
+    ap.add_argument("--share-probe", type=int, default=4,
+                    help="share mode: best-ranked plans timed on 8 slices")
     ap.add_argument("--share-bf16-min-log2", type=int, default=0,
                     help="share mode: smallest intermediate (log2 elements) stored in BF16; 0 = default")
     ap.add_argument("--share-precs", default="f32,f16,bf16", help="share mode: precisions to run")
@@ -183,10 +187,19 @@ def _profile_traffic(kind, flops_per_launch, bytes_per_launch):
 
 
 def plan_cost(plan):
-    """The planner's time-like cost of a plan: over the slice-dependent
-    steps, the sum of max(complex multiply-adds, 20 x elements moved)."""
-    return sum(max(s["flops"] / 8.0, 20.0 * s["bytes_c64"] / 8.0)
-               for s in plan.steps() if s["depends_on_slice"])
+    """The planner's time-like cost of a plan: per step max(complex
+    multiply-adds, 20 x elements moved), summed over every slice for the
+    steps that depend on the sliced wires and once for those that depend on
+    the closed bits only."""
+    n = plan.info()["n_slices"]
+    cost = 0.0
+    for s in plan.steps():
+        c = max(s["flops"] / 8.0, 20.0 * s["bytes_c64"] / 8.0)
+        if s["depends_on_slice"]:
+            cost += n * c
+        elif s["depends_on_bits"]:
+            cost += c
+    return cost
 
 
 def select_plan(R, net, bits, a):
@@ -469,6 +482,49 @@ def serve_mode(a):
     print(json.dumps(out), flush=True)
 
 
+def select_share_plan(R, net, bits, a, seed):
+    """Share plans for planner seeds seed, seed+1, ... (share-candidates of
+    them, in parallel), ranked by the planner's time-like cost; the
+    share-probe best are timed in FP32 on 8 of their slices and the fastest
+    is returned."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    seeds = [seed + i for i in range(max(1, a.share_candidates))]
+
+    def make(sd):
+        p = R.Plan(net, max_log2_elems=a.share_bound, path_trials=a.share_trials, seed=sd,
+                   n_local_sliced=a.share_local, bf16_min_log2=a.share_bf16_min_log2)
+        return plan_cost(p), sd, p
+
+    with ThreadPoolExecutor(max(1, min(len(seeds), 16, os.cpu_count() or 1))) as ex:
+        ranked = sorted(ex.map(make, seeds), key=lambda x: (x[0], x[1]))[:max(1, a.share_probe)]
+    if len(ranked) == 1:
+        return ranked[0][2], {"candidates": len(seeds), "chosen_seed": ranked[0][1]}
+    times, best, best_t = {}, None, float("inf")
+    for i in range(len(ranked)):
+        _, sd, p = ranked[i]
+        ranked[i] = None
+        ids = list(range(min(8, p.info()["n_slices"])))
+        p.bind("cuda:0")
+        lo, pref = p.workspace_bytes(len(ids), 1, R.F32)
+        free, _ = torch.cuda.mem_get_info()
+        ws = torch.empty(int(min(pref, max(lo, 0.5 * free))), dtype=torch.uint8, device="cuda:0")
+        p.contract(bits, slice_ids=ids, prec=R.F32, workspace=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p.contract(bits, slice_ids=ids, prec=R.F32, workspace=ws)
+        torch.cuda.synchronize()
+        times[sd] = 1000.0 * (time.perf_counter() - t1) / len(ids)
+        log(f"share plan seed {sd}: {times[sd]:.2f} ms per slice")
+        del ws
+        if times[sd] < best_t:
+            best, best_t = (sd, p), times[sd]
+        del p
+    return best[1], {"candidates": len(seeds), "probed": len(times),
+                     "ms_per_slice_by_seed": {str(k): round(v, 3) for k, v in times.items()},
+                     "chosen_seed": best[0]}
+
+
 def share_mode(a):
     """One GPU's share of a 10x10 (1+20+1) circuit: 2^L slices of a plan
     whose other sliced wires are fixed, every intermediate within the bound.
@@ -486,9 +542,8 @@ def share_mode(a):
     circ = rqcgen.grid_rqc(rows, cols, depth, seed)
     bits = rqcgen.random_bits(n, seed)
     t = time.perf_counter()
-    plan = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), []), max_log2_elems=a.share_bound,
-                  path_trials=a.share_trials, seed=seed, n_local_sliced=a.share_local,
-                  bf16_min_log2=a.share_bf16_min_log2)
+    net = R.Network(R.Circuit.from_rqcgen(circ), [])
+    plan, selection = select_share_plan(R, net, bits, a, seed)
     t_plan = time.perf_counter() - t
     info = plan.info()
     n_sl = info["n_slices"]
@@ -502,7 +557,7 @@ def share_mode(a):
     free, _ = torch.cuda.mem_get_info()
     lo, pref = plan.workspace_bytes(n_sl, 1, R.F32)
     ws = torch.empty(int(min(pref, max(lo, a.ws_fraction * free))), dtype=torch.uint8, device="cuda:0")
-    share_flops = info["flops_per_slice"] * n_sl
+    share_flops = info["flops_per_slice"] * n_sl + info["flops_per_bitstring"]
     checked = sorted(int(x) for x in np.random.default_rng(seed).choice(n_sl, 32, replace=False))
     res = {"mode": "share", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": f"{rows}x{cols} grid RQC depth 1+{depth}+1, fSim(pi/2,pi/6) ABCDCDAB, "
@@ -512,6 +567,7 @@ def share_mode(a):
                       "plan_log2_flops_per_slice": math.log2(info["flops_per_slice"]),
                       "plan_max_log2_elems": info["max_log2_elems"],
                       "plan_seconds": round(t_plan, 2), "bind_seconds": round(t_bind, 2),
+                      "plan_selection": selection,
                       "invariant_log2_flops": math.log2(info["flops_invariant"] + 1.0)},
            "unit": "slices/s"}
     vals = {}
@@ -552,7 +608,8 @@ def share_mode(a):
                      "fp32_reruns": reruns,
                      "mfma": {"achieved_tflops": achieved, "peak": peak, "frac": achieved / peak,
                               "launches": tim["launches"],
-                              "share_of_flops": tim["flops"] / (info["flops_per_slice"] * max(1, n_sl // 8))}}
+                              "share_of_flops": tim["flops"] / (info["flops_per_slice"] * max(1, n_sl // 8)
+                                                                 + info["flops_per_bitstring"])}}
     plan.set_timing(-1)
     # Per-slice errors in units of the larger of the checked slices' RMS and
     # the natural scale of one slice, 2^-(n+S)/2 (S sliced wires in all).
@@ -681,7 +738,7 @@ def main():
     ref_amps = out.clone()
     n_amp = 1 << a.open
     amps_s = n_amp / (ms / 1000.0)
-    step_flops = info["flops_per_slice"] * info["n_slices"]
+    step_flops = info["flops_per_slice"] * info["n_slices"] + info["flops_per_bitstring"]
     lat = [x / frac for x in lat]
     res = {
         "metric": METRIC,

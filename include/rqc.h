@@ -153,10 +153,15 @@ typedef struct rqc_plan_info {
   int32_t n_leaves, n_steps;       /* steps = pairwise contractions */
   int32_t n_invariant_steps;       /* steps shared by all slices and bitstrings */
   int32_t max_log2_elems;          /* largest per-slice intermediate */
-  double flops_per_slice;          /* 8 real flops per complex multiply-add */
+  double flops_per_slice;          /* steps that depend on the sliced wires, per slice
+                                      and bitstring; 8 real flops per complex
+                                      multiply-add */
   double flops_invariant;          /* once per plan (slice-invariant subtrees) */
   double bytes_per_slice;          /* complex64 bytes read+written per slice */
-  double log2_total_flops;         /* all slices, one bitstring batch */
+  double log2_total_flops;         /* all slices, one bitstring */
+  double flops_per_bitstring;      /* steps that depend on the closed bits but on
+                                      no sliced wire: once per bitstring, shared
+                                      by all slices */
 } rqc_plan_info;
 
 rqc_status rqc_plan_get_info(const rqc_plan* p, rqc_plan_info* out);

@@ -57,7 +57,7 @@ class rqc_plan_info(C.Structure):
                 ("n_steps", C.c_int32), ("n_invariant_steps", C.c_int32),
                 ("max_log2_elems", C.c_int32), ("flops_per_slice", C.c_double),
                 ("flops_invariant", C.c_double), ("bytes_per_slice", C.c_double),
-                ("log2_total_flops", C.c_double)]
+                ("log2_total_flops", C.c_double), ("flops_per_bitstring", C.c_double)]
 
 
 class rqc_step_info(C.Structure):

@@ -174,7 +174,9 @@ rqc_status rqc_plan_get_info(const rqc_plan* p, rqc_plan_info* out) {
   out->flops_per_slice = pd.flops_per_slice;
   out->flops_invariant = pd.flops_invariant;
   out->bytes_per_slice = pd.bytes_per_slice;
-  out->log2_total_flops = std::log2(pd.flops_per_slice * (double)out->n_slices + pd.flops_invariant + 1e-300);
+  out->flops_per_bitstring = pd.flops_per_bitstring;
+  out->log2_total_flops = std::log2(pd.flops_per_slice * (double)out->n_slices +
+                                    pd.flops_per_bitstring + pd.flops_invariant + 1e-300);
   return RQC_OK;
   RQC_CATCH
 }

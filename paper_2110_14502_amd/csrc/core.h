@@ -136,8 +136,10 @@ struct PlanData {
   std::vector<int> step_of_node;        // node -> step index or -1
   CostModel cost;                       // per slice
   double flops_invariant = 0;
-  double flops_per_slice = 0;
+  double flops_per_slice = 0;      // steps that depend on the sliced wires
   double bytes_per_slice = 0;
+  double flops_per_bitstring = 0;  // steps on the closed bits only: shared by all slices
+  double bytes_per_bitstring = 0;
   int max_log2 = 0;
   std::vector<std::pair<int, int>> pruned;  // single-valued wires projected out: (label, value)
   double score = 0;                     // search objective of the chosen plan

@@ -725,7 +725,7 @@ void contract(rqc_plan* p, const uint64_t* ids_in, uint64_t n_ids, const uint8_t
   r.gs = gs;
   r.gb = gb;
   r.graph_reused = reused;
-  r.flops = (pd.flops_per_slice * (double)n_ids) * (double)n_batch;
+  r.flops = (pd.flops_per_slice * (double)n_ids + pd.flops_per_bitstring) * (double)n_batch;
 }
 
 void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {

@@ -454,6 +454,8 @@ static void build_steps(PlanData& p) {
   p.flops_invariant = 0;
   p.flops_per_slice = 0;
   p.bytes_per_slice = 0;
+  p.flops_per_bitstring = 0;
+  p.bytes_per_bitstring = 0;
   p.max_log2 = 0;
   for (int i = 0; i < t.n_leaves; ++i) p.max_log2 = std::max(p.max_log2, (int)s[i].size());
   for (int v : order) {
@@ -479,10 +481,14 @@ static void build_steps(PlanData& p) {
     const double fl = 8.0 * std::ldexp(1.0, st.m + st.n + st.k);
     const double by = 8.0 * (std::ldexp(1.0, (int)s[a].size()) + std::ldexp(1.0, (int)s[b].size()) +
                              std::ldexp(1.0, (int)s[v].size()));
-    if (st.invariant) p.flops_invariant += fl;
-    else {
+    if (st.invariant) {
+      p.flops_invariant += fl;
+    } else if (st.dep_s) {
       p.flops_per_slice += fl;
       p.bytes_per_slice += by;
+    } else {
+      p.flops_per_bitstring += fl;
+      p.bytes_per_bitstring += by;
     }
     p.max_log2 = std::max(p.max_log2, (int)s[v].size());
     p.step_of_node[v] = (int)p.steps.size();
@@ -839,7 +845,8 @@ std::string plan_json(const PlanData& p) {
     json_list(o, st.lc);
     o << '}';
   }
-  o << "],\"flops_per_slice\":" << p.flops_per_slice << ",\"flops_invariant\":" << p.flops_invariant
+  o << "],\"flops_per_slice\":" << p.flops_per_slice
+    << ",\"flops_per_bitstring\":" << p.flops_per_bitstring << ",\"flops_invariant\":" << p.flops_invariant
     << ",\"max_log2\":" << p.max_log2 << '}';
   return o.str();
 }

@@ -86,8 +86,11 @@ def test_plan_structure_4x4():
     info = P.info()
     assert info["n_leaves"] == 48 and info["n_steps"] == 47 and info["n_sliced"] == 0
     # cost accounting vs a recount from the exported steps
-    fl = sum(8.0 * 2 ** (s["m"] + s["n"] + s["k"]) for s in e["steps"] if s["dep_s"] or s["dep_b"])
-    assert fl == info["flops_per_slice"]
+    fl_s = sum(8.0 * 2 ** (s["m"] + s["n"] + s["k"]) for s in e["steps"] if s["dep_s"])
+    fl_b = sum(8.0 * 2 ** (s["m"] + s["n"] + s["k"]) for s in e["steps"]
+               if s["dep_b"] and not s["dep_s"])
+    assert fl_s == info["flops_per_slice"] and fl_b == info["flops_per_bitstring"]
+    assert fl_s == e["flops_per_slice"] and fl_b == e["flops_per_bitstring"]
     assert info["max_log2_elems"] == max(len(s["lc"]) for s in e["steps"])
 
 
