@@ -574,9 +574,11 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
         const bool timed = kern == p->timing_kernel || (kern == KERN_MFMA16 && p->timing_kernel == KERN_MFMA);
         if (timed) {
           if (p->tev.size() < 2 * (probe + 1)) {
+            // Timing only: no system-scope fence, so that the recorded
+            // interval does not include writing back the caches.
             hipEvent_t a, b;
-            hip_check(hipEventCreate(&a), "event");
-            hip_check(hipEventCreate(&b), "event");
+            hip_check(hipEventCreateWithFlags(&a, hipEventDisableSystemFence), "event");
+            hip_check(hipEventCreateWithFlags(&b, hipEventDisableSystemFence), "event");
             p->tev.push_back(a);
             p->tev.push_back(b);
           }
