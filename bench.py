@@ -227,35 +227,44 @@ def select_plan(R, net, bits, a):
     seeds = [sd for _, sd, _ in ranked]
     plans = [p for _, _, p in ranked]
     if len(seeds) == 1:
-        return seeds[0], {"candidates": len(costs), "plan_seconds": round(t_plan, 2)}, plans[0]
-    times = {}
-    best_plan, best_t = None, float("inf")
+        return seeds[0], {"candidates": len(costs), "plan_seconds": round(t_plan, 2)}, plans[0], None
+    # The reduced-precision run of the FP32 benchmark is autotuned the same
+    # way, on its own precision.
+    precs = [a.prec] + (["f16"] if a.lp_steps > 0 and a.prec == "f32" else [])
+    times = {pr: {} for pr in precs}
+    best = {pr: (None, None, float("inf")) for pr in precs}
     for i, sd in enumerate(seeds):
         p, plans[i] = plans[i], None
         n_ids = min(a.probe_slices, p.info()["n_slices"])
         p.bind("cuda:0")
-        lo, pref = p.workspace_bytes(n_ids, 1, R.PRECISIONS[a.prec])
-        free, _ = torch.cuda.mem_get_info()
-        ws = torch.empty(int(min(pref, max(lo, 0.5 * free))), dtype=torch.uint8, device="cuda:0")
-        ids = list(range(n_ids))
-        p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[a.prec], workspace=ws)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[a.prec], workspace=ws)
-        torch.cuda.synchronize()
-        times[sd] = 1000.0 * (time.perf_counter() - t1) / n_ids
-        log(f"plan seed {sd}: {times[sd]:.3f} ms per slice on {n_ids} slices")
-        del ws
-        if times[sd] < best_t:  # keep only the fastest plan alive
-            best_plan, best_t = p, times[sd]
+        for pr in precs:
+            lo, pref = p.workspace_bytes(n_ids, 1, R.PRECISIONS[pr])
+            free, _ = torch.cuda.mem_get_info()
+            ws = torch.empty(int(min(pref, max(lo, 0.5 * free))), dtype=torch.uint8, device="cuda:0")
+            ids = list(range(n_ids))
+            p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[pr], workspace=ws)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            p.contract(bits, slice_ids=ids, prec=R.PRECISIONS[pr], workspace=ws)
+            torch.cuda.synchronize()
+            times[pr][sd] = 1000.0 * (time.perf_counter() - t1) / n_ids
+            log(f"plan seed {sd} {pr}: {times[pr][sd]:.3f} ms per slice on {n_ids} slices")
+            del ws
+            if times[pr][sd] < best[pr][2]:  # keep only the fastest plans alive
+                best[pr] = (sd, p, times[pr][sd])
         del p
-    best = min(times, key=times.get)
-    plan = best_plan
-    return best, {"candidates": len(costs), "probed": len(seeds), "probe_slices": a.probe_slices,
-                  "plan_seconds": round(t_plan, 2),
-                  "cost_rank_of_chosen": seeds.index(best),
-                  "ms_per_slice_by_seed": {str(k): round(v, 4) for k, v in times.items()},
-                  "chosen_seed": best}, plan
+    chosen, plan, _ = best[a.prec]
+    info = {"candidates": len(costs), "probed": len(seeds), "probe_slices": a.probe_slices,
+            "plan_seconds": round(t_plan, 2),
+            "cost_rank_of_chosen": seeds.index(chosen),
+            "ms_per_slice_by_seed": {str(k): round(v, 4) for k, v in times[a.prec].items()},
+            "chosen_seed": chosen}
+    lp_plan = None
+    if len(precs) > 1:
+        info["f16_ms_per_slice_by_seed"] = {str(k): round(v, 4) for k, v in times["f16"].items()}
+        info["f16_chosen_seed"] = best["f16"][0]
+        lp_plan = best["f16"][1]
+    return chosen, info, plan, lp_plan
 
 
 def roofline(kind, tim, a, flops_total, kind_ms):
@@ -683,7 +692,7 @@ def main():
     bits = rqcgen.random_bits(n - a.open, a.seed)
     net = R.Network(R.Circuit.from_rqcgen(circ), openq)
     t = time.perf_counter()
-    chosen, probe, plan = select_plan(R, net, bits, a)
+    chosen, probe, plan, lp_plan = select_plan(R, net, bits, a)
     t_plan = time.perf_counter() - t
     info = plan.info()
     log(f"plan: {t_plan:.1f}s, log2 flops/slice {math.log2(info['flops_per_slice']):.2f}, "
@@ -782,11 +791,30 @@ def main():
         torch.cuda.synchronize()
         res["graph_ms_per_step"] = 1000.0 * (time.perf_counter() - t0) / a.graph_steps / frac
     if a.lp_steps > 0 and a.prec == "f32":
-        step(R.F16, "f16 warmup")
+        if lp_plan is not None and lp_plan is not plan:
+            # The plan autotuned for FP16 (its own workspace).
+            plan.set_timing(-1)
+            del ws
+            lp_plan.bind("cuda:0")
+            free, _ = torch.cuda.mem_get_info()
+            lo, pref = lp_plan.workspace_bytes(len(ids) if ids else 0, 1, R.F16)
+            ws = torch.empty(int(min(pref, max(lo, a.ws_fraction * free))), dtype=torch.uint8,
+                             device="cuda:0")
+        else:
+            lp_plan = plan
+
+        def step16(tag):
+            ts = time.perf_counter()
+            lp_plan.contract(bits, slice_ids=ids, prec=R.F16, workspace=ws, out=out, sync=False)
+            r = lp_plan.report()
+            log(f"{tag}: {time.perf_counter() - ts:.2f}s (groups of {r['slices_per_group']} slices)")
+            return r
+
+        step16("f16 warmup")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(a.lp_steps):
-            rep16 = step(R.F16, "f16")
+            rep16 = step16("f16")
         torch.cuda.synchronize()
         ms16 = 1000.0 * (time.perf_counter() - t0) / a.lp_steps / frac
         lp_amps = R.to_complex(out.view(-1, 2))
@@ -794,6 +822,7 @@ def main():
         res["reduced_precision"] = {
             "dtype": "f16 (16-bit storage of large intermediates, FP16 MFMA, FP32 accumulate)",
             "ms_per_step": ms16, "value": n_amp / (ms16 / 1000.0), "speedup_vs_f32": ms / ms16,
+            "plan_seed": probe.get("f16_chosen_seed", chosen),
             "fp32_reruns": rep16["fp32_reruns"],
             "normalized_error_vs_f32": _norm_err(lp_amps, f32_amps, n),
             "fidelity_vs_f32": _fidelity(lp_amps, f32_amps)}
