@@ -68,7 +68,7 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
     rows_ok = pos_in(lb, xa) == p;
   }
   const bool mfma_ok = m >= 7 && n >= 6 && k >= 4;
-  const bool mfma16_ok = m >= 7 && n >= 6 && k >= 5;
+  const bool mfma16_ok = m >= 7 && n >= 6 && k >= 4;
   // Short sums (k <= 4) are memory-bound: row streaming beats one MFMA chunk.
   if (kernel < 0)
     kernel = (mfma_ok && !(rows_ok && k <= 4)) ? KERN_MFMA : (rows_ok ? KERN_ROWS : KERN_SIMT);
@@ -83,7 +83,7 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   } else if (kernel == KERN_MFMA16) {
     rt = 7;
     nt = 6;
-    kt = 5;
+    kt = k >= 5 ? 5 : 4;  // sums of 16 fill half of the kernel's 32-term chunk
   } else if (kernel == KERN_ROWS) {
     kt = k;
     nt = n;
@@ -195,6 +195,11 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   d.gs_c = 1;
   d.copies = 1;
   d.flag_n = 1;
+  // The 16-term chunk of the 16-bit kernel exists for the vector layout only.
+  if (kernel == KERN_MFMA16 && kt == 4 && !lp_vec_layout(d)) {
+    kernel = KERN_MFMA;
+    return make_pair_desc(la, lb, lc, kernel);
+  }
   return d;
 }
 
@@ -253,7 +258,8 @@ size_t resident_bytes(rqc_plan* p) {
     int k = -1;
     p->tmpl.push_back(make_pair_desc(st.la, st.lb, st.lc, k));
     p->kern.push_back(k);
-    // Reduced precision: dense steps with k >= 5 go to the FP16/BF16 MFMA.
+    // Reduced precision: dense steps go to the FP16/BF16 MFMA (sums of 16
+    // only with the vector layout; make_pair_desc falls back otherwise).
     int k2 = k == KERN_MFMA ? KERN_MFMA16 : k;
     p->tmpl_lp.push_back(make_pair_desc(st.la, st.lb, st.lc, k2));
     p->kern_lp.push_back(k2);

@@ -111,7 +111,7 @@ __device__ __forceinline__ u32x4 expand_b(u32x4 w, bool swap_halves) {
 // bits (summed indices, as the planner lays out every step), so four
 // consecutive tile elements are 16 contiguous bytes: one vector load and
 // one 16-byte LDS write per four elements.
-template <int LP, int SA, int SB, int SC, bool VEC>
+template <int LP, int SA, int SB, int SC, bool VEC, int KT>
 __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items, uint32_t* lw,
                                             TileTab& tcs, OuterTab& ot) {
   uint32_t* Abuf = lw;                  // [2][kTM][kLRow]
@@ -121,9 +121,11 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  // A chunk tile: 128 rows x 32 k (4096 elements: 16 per thread, or 4
-  // vectors of 4); B chunk tile: 32 k x 64 columns (2048: 8, or 2 vectors).
-  constexpr int NA = VEC ? 4 : 16, NB = VEC ? 2 : 8;
+  // A chunk tile: 128 rows x 2^KT k (KT = 5: 4096 elements, 16 per thread or
+  // 4 vectors of 4); B chunk tile: 2^KT k x 64 columns (KT = 5: 2048, 8 or 2
+  // vectors).  KT = 4 fills half of each LDS row.
+  constexpr int NA = VEC ? (1 << (KT - 3)) : (1 << (KT - 1));
+  constexpr int NB = VEC ? (1 << (KT - 4)) : (1 << (KT - 2));
   int64_t gA[NA];
   int lA[NA];
   int64_t gB[NB];
@@ -323,7 +325,7 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
       const uint32_t* As = Abuf + cb * kLABuf + (wm * 64 + lrow) * kLRow + kq;
       const uint32_t* Bs = Bbuf + cb * kLBBuf + (wn * 32 + ncol) * kLRow + kq;
 #pragma unroll
-      for (int kk = 0; kk < kLTK / 8; ++kk) {
+      for (int kk = 0; kk < (1 << KT) / 8; ++kk) {
         const u32x4 a0 = *reinterpret_cast<const u32x4*>(As + kk * 8);
         const u32x4 a1 = *reinterpret_cast<const u32x4*>(As + 32 * kLRow + kk * 8);
         const u32x4 b0 = expand_b(*reinterpret_cast<const u32x4*>(Bs + kk * 8), bswap);
@@ -367,21 +369,12 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
   if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, cs.sc);
 }
 
-template <int LP, int SA, int SB, int SC, bool VEC>
+template <int LP, int SA, int SB, int SC, bool VEC, int KT>
 __global__ __launch_bounds__(256, 2) void k_mfma16(StepDesc d, uint64_t n_items) {
   __shared__ __attribute__((aligned(16))) uint32_t lw[kLMainWords + 16];
   __shared__ TileTab tcs;
   __shared__ OuterTab ot;
-  mfma16_body<LP, SA, SB, SC, VEC>(d, n_items, lw, tcs, ot);
-}
-
-// The vector path needs the two lowest tile bits of A and of B to be their
-// two lowest address bits and summed indices 0 and 1 of the chunk.
-static bool mfma16_vec(const StepDesc& d) {
-  return d.tA.nbits >= 2 && d.tB.nbits >= 2 && d.tA.gpos[0] == 0 && d.tA.gpos[1] == 1 &&
-         d.tB.gpos[0] == 0 && d.tB.gpos[1] == 1 && d.tA.role[0] == 2 && d.tA.role[1] == 2 &&
-         d.tB.role[0] == 2 && d.tB.role[1] == 2 && d.tA.cbit[0] == 0 && d.tA.cbit[1] == 1 &&
-         d.tB.cbit[0] == 0 && d.tB.cbit[1] == 1;
+  mfma16_body<LP, SA, SB, SC, VEC, KT>(d, n_items, lw, tcs, ot);
 }
 
 template <int LP>
@@ -390,13 +383,16 @@ static hipError_t launch_mfma16(const StepDesc& d, int sa, int sb, int sc, dim3 
   constexpr int C = ST_C64;
   const uint64_t n_items = (uint64_t)grid.x * (uint64_t)d.copies;
   grid = dim3((unsigned)(n_items < kMfma16Grid ? n_items : kMfma16Grid), 1);
-  const bool vec = mfma16_vec(d);
+  const bool vec = lp_vec_layout(d);
+  if (d.kt == 4 && !vec) return hipErrorInvalidValue;  // the planner's layouts only
 #define RQC_LP_CASE(a, b, c)                                                        \
   if (sa == a && sb == b && sc == c) {                                              \
-    if (vec)                                                                        \
-      hipLaunchKernelGGL((k_mfma16<LP, a, b, c, true>), grid, dim3(256), 0, s, d, n_items); \
+    if (d.kt == 4)                                                                  \
+      hipLaunchKernelGGL((k_mfma16<LP, a, b, c, true, 4>), grid, dim3(256), 0, s, d, n_items); \
+    else if (vec)                                                                   \
+      hipLaunchKernelGGL((k_mfma16<LP, a, b, c, true, 5>), grid, dim3(256), 0, s, d, n_items); \
     else                                                                            \
-      hipLaunchKernelGGL((k_mfma16<LP, a, b, c, false>), grid, dim3(256), 0, s, d, n_items); \
+      hipLaunchKernelGGL((k_mfma16<LP, a, b, c, false, 5>), grid, dim3(256), 0, s, d, n_items); \
     return hipGetLastError();                                                       \
   }
   RQC_LP_CASE(LP, LP, LP)
@@ -412,7 +408,7 @@ static hipError_t launch_mfma16(const StepDesc& d, int sa, int sb, int sc, dim3 
 }
 hipError_t launch_mfma16_kernel(const StepDesc& d, int sa, int sb, int sc, int lp_kind, dim3 grid,
                                 hipStream_t s) {
-  if (d.rt != 7 || d.nt != 6 || d.kt != 5) return hipErrorInvalidValue;
+  if (d.rt != 7 || d.nt != 6 || (d.kt != 5 && d.kt != 4)) return hipErrorInvalidValue;
   if (lp_kind == ST_F16) return launch_mfma16<ST_F16>(d, sa, sb, sc, grid, s);
   if (lp_kind == ST_BF16) return launch_mfma16<ST_BF16>(d, sa, sb, sc, grid, s);
   return hipErrorInvalidValue;

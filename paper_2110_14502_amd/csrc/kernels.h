@@ -91,6 +91,15 @@ struct LeafJob {
 enum Kernel : int { KERN_SIMT = 0, KERN_MFMA = 1, KERN_ROWS = 2, KERN_MFMA16 = 3 };
 
 // Launchers (kernels.hip).  All return hipError_t of the launch.
+// The 16-bit matrix-core kernel's vector path: the two lowest tile bits of A
+// and of B are their two lowest address bits and summed indices 0 and 1.
+inline bool lp_vec_layout(const StepDesc& d) {
+  return d.tA.nbits >= 2 && d.tB.nbits >= 2 && d.tA.gpos[0] == 0 && d.tA.gpos[1] == 1 &&
+         d.tB.gpos[0] == 0 && d.tB.gpos[1] == 1 && d.tA.role[0] == 2 && d.tA.role[1] == 2 &&
+         d.tB.role[0] == 2 && d.tB.role[1] == 2 && d.tA.cbit[0] == 0 && d.tA.cbit[1] == 1 &&
+         d.tB.cbit[0] == 0 && d.tB.cbit[1] == 1;
+}
+
 hipError_t launch_step(const StepDesc& d, int kernel, int sa, int sb, int sc, int lp_kind,
                        hipStream_t s);
 hipError_t launch_leaves(const LeafJob* jobs_dev, int n_jobs, const void* leaf_store,

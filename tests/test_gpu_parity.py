@@ -254,3 +254,26 @@ def test_lp_mfma_kernel_vs_einsum(prec, tol):
         assert err < tol, err
         # and it is not the FP32 path: the error is at the 16-bit level
         assert err > 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [("f16", 6e-3), ("bf16", 4e-2)])
+def test_lp_mfma_short_sum_vs_einsum(prec, tol):
+    """FP16 / BF16 matrix-core contraction of a sum of 16 (half of the
+    kernel's chunk) on the planner's layout: summed labels lowest in both
+    operands, in the same order."""
+    _say("lp mfma short sum", prec)
+    for (m, n, k, seed) in ((10, 8, 4, 41), (9, 7, 4, 42)):
+        M, N, K = list(range(m)), list(range(100, 100 + n)), list(range(200, 200 + k))
+        rng = np.random.default_rng(seed)
+        la = [M[i] for i in rng.permutation(m)] + K
+        lb = [N[i] for i in rng.permutation(n)] + K
+        lc = [x for x in (M + N)]
+        lc = [lc[i] for i in rng.permutation(len(lc))]
+        a = rqcgen.random_complex(1 << (m + k), seed)
+        b = rqcgen.random_complex(1 << (n + k), seed + 1)
+        ref = oracle.einsum_step(a, b, la, lb, lc)
+        c = R.pair_contract(_dev_c64(a), _dev_c64(b), la, lb, lc, prec=R.PRECISIONS[prec])
+        torch.cuda.synchronize()
+        err = _rel_rms(c.cpu().numpy().astype(np.complex128), ref)
+        assert err < tol, (m, n, k, err)
+        assert err > 1e-6  # the 16-bit path ran
