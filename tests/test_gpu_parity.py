@@ -44,6 +44,8 @@ STEP_CASES = [
     (15, 15, 4, 5, -1),
     (6, 6, 6, 6, 0),     # full contraction to a scalar
     (5, 3, 0, 7, 0),     # outer product
+    (18, 16, 9, 8, 1),   # long sum: one tile per workgroup (k >= 8)
+    (17, 17, 8, 9, -1),
 ]
 
 
@@ -277,3 +279,29 @@ def test_lp_mfma_short_sum_vs_einsum(prec, tol):
         err = _rel_rms(c.cpu().numpy().astype(np.complex128), ref)
         assert err < tol, (m, n, k, err)
         assert err > 1e-6  # the 16-bit path ran
+
+
+
+def test_config3_full_rank_steps_sampled():
+    """Two of the rank-24..32 synthetic steps at full size (random index
+    orders of both operands and the output), 256 sampled outputs each vs
+    direct complex128 sums."""
+    cases = rqcgen.synthetic_step_cases(3, n_cases=2)
+    for i, st in enumerate(cases):
+        la, lb, lc = st.labels_a, st.labels_b, st.labels_c
+        k = len([x for x in la if x in lb])
+        _say("config3 step", len(la), len(lb), k)
+        g = torch.Generator(device="cuda").manual_seed(11 + i)
+        A = torch.randn(1 << len(la), dtype=torch.complex64, device="cuda", generator=g)
+        B = torch.randn(1 << len(lb), dtype=torch.complex64, device="cuda", generator=g)
+        C = R.pair_contract(A, B, la, lb, lc)
+        torch.cuda.synchronize()
+        coords = np.random.default_rng(20 + i).integers(0, 1 << len(lc), size=256)
+
+        def get(T):
+            return lambda idx: T[torch.from_numpy(np.asarray(idx)).cuda()].cpu().numpy()
+        ref = oracle.sampled_step(get(A), get(B), la, lb, lc, coords)
+        got = C[torch.from_numpy(coords).cuda()].cpu().numpy()
+        scale = np.sqrt(2.0 ** k)  # RMS of a sum of 2^k unit-variance products
+        assert np.max(np.abs(got - ref)) / scale < 2e-5
+        del A, B, C
