@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--cases", type=int, default=12, help="steps mode: number of synthetic cases")
     ap.add_argument("--requests", type=int, default=600, help="serve mode: Poisson requests")
     ap.add_argument("--load", type=float, default=0.8, help="serve mode: rate / saturation rate")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve mode: device pool")
+    ap.add_argument("--budget-gb", type=float, default=192.0,
+                    help="serve mode: device pool (plans, workspaces, outputs)")
     ap.add_argument("--share-bound", type=int, default=28,
                     help="share mode: per-slice bound, log2 elements")
     ap.add_argument("--share-local", type=int, default=10,
