@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   constexpr int K = 1 << KB;
   constexpr int NJ = K >= 2 ? (2 * K) / 4 : 1;  // real k per lane quarter (FP32 MFMAs per chunk)
   constexpr bool LPM = SA != ST_C64 && KB >= 4;  // 16-bit matrix cores
-  extern __shared__ float2 rows_lds[];
+  extern __shared__ __attribute__((aligned(16))) float2 rows_lds[];  // 16-byte B reads
   __shared__ TileTab tc;
   __shared__ int64_t bofs[64];
   __shared__ int64_t stepA[kMaxOuter], stepC[kMaxOuter];
