@@ -178,9 +178,9 @@ def _profile_traffic(kind, flops_per_launch, bytes_per_launch):
     try:
         if vals.get("kernel_source_sha256") != kernel_source_hash(root, kind):
             return None
-        if abs(float(vals["flops_per_launch"]) / flops_per_launch - 1) > 1e-6:
+        if abs(float(vals["flops_per_launch"]) / flops_per_launch - 1) > 1e-5:
             return None
-        if abs(float(vals["algorithmic_bytes_per_launch"]) / bytes_per_launch - 1) > 1e-6:
+        if abs(float(vals["algorithmic_bytes_per_launch"]) / bytes_per_launch - 1) > 1e-5:
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError, ZeroDivisionError):
