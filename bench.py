@@ -26,14 +26,18 @@ METRIC = "amplitudes/s + contraction TFLOP/s vs plain FP32 path at stated error;
 PEAK_MFMA_FP32 = 157.3   # TFLOP/s, MI355X dense FP32 matrix
 PEAK_MFMA_16 = 2500.0    # TFLOP/s, MI355X dense FP16 / BF16 matrix
 PEAK_HBM = 8000.0        # GB/s
-# Kernel kinds of the timing probe: 0 generic SIMT, 1 FP32/16-bit MFMA, 2 rows.
-KIND_NAMES = {0: "k_simt", 1: "k_mfma32", 2: "k_rows"}
-KIND_SOURCES = {0: "k_simt.hip", 1: "k_mfma32.hip", 2: "k_rows.hip"}
+# Kernel kinds of the timing probe: 0 generic SIMT, 1 FP32 MFMA, 2 rows,
+# 3 16-bit MFMA (probe kind 1 also brackets kind 3; kind 4 brackets all).
+KIND_NAMES = {0: "k_simt", 1: "k_mfma32", 2: "k_rows", 3: "k_mfma16"}
+KIND_SOURCES = {0: "k_simt.hip", 1: "k_mfma32.hip", 2: "k_rows.hip", 3: "k_mfma16.hip"}
 KIND_LABELS = {
     0: "k_simt (generic table-driven contraction, split-K)",
     1: "k_mfma32 (fused permute + complex GEMM, FP32 MFMA 32x32x2)",
     2: "k_rows (row-streaming stem step, FP32 MFMA 16x16x4, LDS-staged stores)",
+    3: "k_mfma16 (fused permute + complex GEMM, FP16/BF16 MFMA 32x32x16)",
 }
+TIME_ALL = 4
+GOLDEN_CONFIG2 = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.txt")
 # Counter summaries (FETCH_SIZE / WRITE_SIZE) of the dominant kernel of the
 # default amplitude workload, per kernel kind.
 TRAFFIC_PROFILES = {1: "k_mfma32_config2_6x6x14_fp32_traffic.md",
@@ -108,38 +112,63 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(circ, openq, bits, n_fixed, budget_s, plan_seed, base_wires):
-    """The oracle timed on a bounded sample of the same amplitude sum: with
-    n_fixed wires fixed, the batch is the sum of 2^n_fixed sub-slices; time
-    as many sub-slices as fit the budget and extrapolate to the full sum."""
-    import numpy as np
-    import oracle
-    import paper_2110_14502_amd as R
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(circ, openq, bits, plan, budget_s):
+    """The oracle timed on whole slices of the benchmarked plan: each slice
+    contracted in complex128 along the plan's tree (oracle.contract_ordered,
+    the order given as data); as many slices as fit ~70% of the budget on all
+    host threads, then one slice on one thread; both extrapolated to every
+    slice of the step."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from plan_order import oracle_order, oracle_wires_and_ids
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
+        threadpool_limits = None
         threads = os.cpu_count() or 1
-    P = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), openq), n_sliced=n_fixed,
-               path_trials=64, seed=plan_seed, forced_wires=base_wires)
-    wires = P.sliced_wires()
-    rng = np.random.default_rng(0)
-    ids = rng.choice(1 << n_fixed, size=64, replace=False)
+    e = plan.export()
+    groups, pairs = oracle_order(circ, openq, e)
+    n_sl = int(plan.info()["n_slices"])
+
+    def one(sid):
+        ow, oids = oracle_wires_and_ids(e, [sid])
+        return oracle.slice_values_ordered(circ, openq, bits, ow, oids, groups, pairs)
+
     t0 = time.perf_counter()
     done = 0
-    for sid in ids:
-        oracle.slice_values_tn(circ, openq, bits, wires, [int(sid)])
+    for sid in range(n_sl):
+        one(sid)
         done += 1
-        if time.perf_counter() - t0 > budget_s:
+        if time.perf_counter() - t0 > 0.7 * budget_s:
             break
     dt = time.perf_counter() - t0
-    per_sub = dt / done
-    full = per_sub * (1 << n_fixed)
+    full = dt / done * n_sl
     n_amp = 1 << len(openq)
-    return {"value": n_amp / full, "unit": "amplitudes/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} of the 2^{n_fixed} sub-slices (wires fixed: the 8-wire slicing refined "
-                      f"to {n_fixed}) of the same 64-amplitude sum, complex128 numpy, "
-                      f"{dt:.1f} s, extrapolated to the full sum ({full:.3g} s)"}
+    res = {"value": n_amp / full, "unit": "amplitudes/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{done} of the {n_sl} slices of the benchmarked plan, each contracted in "
+                     f"complex128 along the plan's tree (oracle.contract_ordered), {dt:.1f} s on "
+                     f"{threads} threads, extrapolated to all {n_sl} slices ({full:.1f} s)",
+           "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    if threadpool_limits is not None:
+        with threadpool_limits(1):
+            t1 = time.perf_counter()
+            one(done % n_sl)
+            d1 = time.perf_counter() - t1
+        res["one_thread"] = {"value": n_amp / (d1 * n_sl), "unit": "amplitudes/s",
+                             "sample": f"1 slice on 1 thread, {d1:.1f} s, extrapolated to "
+                                       f"{n_sl} slices ({d1 * n_sl:.0f} s)"}
+    return res
 
 
 def _norm_err(a, ref, n_qubits):
@@ -296,6 +325,69 @@ def roofline(kind, tim, a, flops_total, kind_ms):
         "share_of_step_flops": tim["flops"] / flops_total,
         "probe_ms_per_step_by_kernel": kind_ms,
     }
+
+
+def launch_table(launches, n_reps=1):
+    """Per-launch roofline: t_min = max(F / P, B / 8 TB/s) with P the matrix
+    peak of the launch's arithmetic (FP32 157.3 TFLOP/s; 16-bit matrix cores
+    2.5 PFLOP/s), F and B the algorithmic flops and bytes; and per kernel
+    kind the summed time, rates and roofline fraction (sum of t_min over
+    sum of measured time)."""
+    rows, kinds = [], {}
+    for L in launches:
+        # 16-bit matrix cores: the 16-bit GEMM kernel, and the row kernel on
+        # a 16-bit stored A with sums of 16 or more.
+        lp_mma = L["kernel"] == 3 or (L["kernel"] == 2 and L["store_a"] != 0 and L["k"] >= 4)
+        peak = PEAK_MFMA_16 if lp_mma else PEAK_MFMA_FP32
+        t_f = L["flops"] / (peak * 1e12) * 1e3
+        t_b = L["bytes"] / (PEAK_HBM * 1e9) * 1e3
+        t_min = max(t_f, t_b)
+        ms = L["ms"] / n_reps
+        rows.append({"step": L["step"], "kernel": KIND_NAMES.get(L["kernel"], str(L["kernel"])),
+                     "mnk": [L["m"], L["n"], L["k"]], "copies": L["copies"],
+                     "store": [L["store_a"], L["store_b"], L["store_c"]],
+                     "flops": L["flops"], "bytes": L["bytes"], "ms": round(ms, 5),
+                     "t_min_ms": round(t_min, 5), "bound": "mfma" if t_f >= t_b else "hbm",
+                     "frac": round(t_min / ms, 4) if ms > 0 else None})
+        k = kinds.setdefault(L["kernel"], {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0,
+                                           "t_min_ms": 0.0, "t_min_mfma_ms": 0.0})
+        k["launches"] += 1
+        k["ms"] += ms
+        k["flops"] += L["flops"]
+        k["bytes"] += L["bytes"]
+        k["t_min_ms"] += t_min
+        k["t_min_mfma_ms"] += t_min if t_f >= t_b else 0.0
+    out = {}
+    for kind, k in kinds.items():
+        secs = k["ms"] / 1e3
+        mfma = k["t_min_mfma_ms"] >= 0.5 * k["t_min_ms"]
+        peak = PEAK_MFMA_16 if kind == 3 else PEAK_MFMA_FP32
+        out[KIND_NAMES.get(kind, str(kind))] = {
+            "kernel": KIND_LABELS.get(kind, str(kind)),
+            "bound": "mfma" if mfma else "hbm",
+            "achieved": (k["flops"] / secs / 1e12) if mfma else (k["bytes"] / secs / 1e9),
+            "peak": peak if mfma else PEAK_HBM,
+            "unit": "TFLOP/s" if mfma else "GB/s",
+            "frac": ((k["flops"] / secs / 1e12) / peak) if mfma else ((k["bytes"] / secs / 1e9) / PEAK_HBM),
+            "roofline_frac": k["t_min_ms"] / k["ms"] if k["ms"] > 0 else None,
+            "ms_per_step": k["ms"], "t_min_ms_per_step": k["t_min_ms"],
+            "achieved_tflops": k["flops"] / secs / 1e12, "achieved_gbs": k["bytes"] / secs / 1e9,
+            "launches": k["launches"]}
+    return rows, out
+
+
+def read_golden(path):
+    """(indices, complex128 values) of a stored oracle file."""
+    import numpy as np
+    idx, val = [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            i, re_, im_ = line.split()
+            idx.append(int(i))
+            val.append(complex(float(re_), float(im_)))
+    return np.array(idx), np.array(val, dtype=np.complex128)
 
 
 def log(*msg):
@@ -718,15 +810,17 @@ def main():
         log(f"{tag}: {time.perf_counter() - ts:.2f}s (groups of {r['slices_per_group']} slices)")
         return r
 
-    # Which kernel kind dominates the step: one probe step per kind (these
-    # also warm up), then the timed region brackets that kind's launches
-    # with HIP events (direct launches on the caller's stream).
-    kind_ms = {}
-    for kind in (1, 2, 0):
-        plan.set_timing(kind)
-        step(prec, f"probe {KIND_NAMES[kind]}")
-        kind_ms[KIND_NAMES[kind]] = plan.timing()["total_ms"] / frac
-    dom = max((1, 2, 0), key=lambda k: kind_ms[KIND_NAMES[k]])
+    # One probe step with every launch bracketed by events (direct launches
+    # on the caller's stream; it also warms up): the per-launch table, each
+    # kernel kind's time and roofline.  The timed region then brackets the
+    # launches of the kind that takes longest.
+    step(prec, "warm")
+    plan.set_timing(TIME_ALL)
+    step(prec, "probe all kernels")
+    table, by_kind = launch_table(plan.launch_timings())
+    kind_ms = {k: v["ms_per_step"] / frac for k, v in by_kind.items()}
+    names = {v: k for k, v in KIND_NAMES.items()}
+    dom = names[max(by_kind, key=lambda k: by_kind[k]["ms_per_step"])]
     if a.roofline_kernel >= 0:
         dom = a.roofline_kernel
     plan.set_timing(dom)
@@ -780,7 +874,17 @@ def main():
         "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),
                        "p99": 1000 * float(np.percentile(lat, 99))},
         "roofline": roofline(dom, tim, a, step_flops * frac * a.steps, kind_ms),
+        "roofline_by_kernel": by_kind,
+        "launch_table": table,
     }
+    golden = None
+    if (a.rows, a.cols, a.depth, a.seed, a.open, ids) == (6, 6, 14, 2, 6, None) and \
+            os.path.exists(GOLDEN_CONFIG2):
+        golden = read_golden(GOLDEN_CONFIG2)[1]
+        got = R.to_complex(ref_amps.view(-1, 2))
+        res["error_vs_oracle"] = _norm_err(got, golden, n)
+        res["fidelity_vs_oracle"] = _fidelity(got, golden)
+        res["oracle_reference"] = "tests/golden/config2_amplitudes.txt (complex128 oracle)"
     # The same call replayed as one captured graph launch (probe off).
     if a.graph_steps > 0:
         plan.set_timing(-1)
@@ -812,6 +916,11 @@ def main():
             return r
 
         step16("f16 warmup")
+        lp_plan.set_timing(TIME_ALL)
+        step16("f16 probe all kernels")
+        table16, by_kind16 = launch_table(lp_plan.launch_timings())
+        lp_plan.set_timing(-1)
+        step16("f16 graph capture")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(a.lp_steps):
@@ -826,11 +935,14 @@ def main():
             "plan_seed": probe.get("f16_chosen_seed", chosen),
             "fp32_reruns": rep16["fp32_reruns"],
             "normalized_error_vs_f32": _norm_err(lp_amps, f32_amps, n),
-            "fidelity_vs_f32": _fidelity(lp_amps, f32_amps)}
+            "fidelity_vs_f32": _fidelity(lp_amps, f32_amps),
+            "roofline_by_kernel": by_kind16, "launch_table": table16}
+        if golden is not None:
+            res["reduced_precision"]["error_vs_oracle"] = _norm_err(lp_amps, golden, n)
+            res["reduced_precision"]["fidelity_vs_oracle"] = _fidelity(lp_amps, golden)
     if a.cpu_seconds > 0:
         log("cpu baseline")
-        res["cpu_baseline"] = cpu_baseline(circ, openq, bits, a.sliced + 16, a.cpu_seconds,
-                                           a.plan_seed, plan.sliced_wires())
+        res["cpu_baseline"] = cpu_baseline(circ, openq, bits, plan, a.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

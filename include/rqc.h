@@ -32,7 +32,7 @@
  *     exception crosses this boundary.  rqc_last_error() gives a message for
  *     the last failure on the calling thread.  Errors of asynchronous device
  *     work surface at the next call that synchronises (for example
- *     rqc_contract_report).
+ *     rqc_contract_status).
  */
 #ifndef RQC_H
 #define RQC_H
@@ -138,7 +138,23 @@ typedef struct rqc_plan_opts {
   int32_t restarts;       /* independent searches with seeds derived from
                              `seed`; the plan with the lowest estimated time
                              is kept; 0 = 1 */
+  int32_t precision_policy; /* which intermediates use 16-bit storage and
+                               arithmetic in RQC_F16 / RQC_BF16 calls, see
+                               RQC_POLICY_*; 0 = RQC_POLICY_SIZE */
+  uint64_t hbm_budget_bytes; /* 0: unbounded.  Otherwise the plan's resident
+                                bytes plus the workspace of one slice and one
+                                bitstring in FP32 must fit, else EHBM */
 } rqc_plan_opts;
+
+/* Precision policies (Section 5.5: the parts of the network near the slice
+ * cuts are the most sensitive to reduced precision).
+ *   SIZE: an intermediate is stored (and multiplied) in 16 bits when it has
+ *         at least 2^lp_min_log2 (FP16) / 2^bf16_min_log2 (BF16) elements
+ *         per slice;
+ *   CALIBRATED: as SIZE, then rqc_plan_calibrate measures each step's
+ *         sensitivity on one slice and keeps the most sensitive steps in
+ *         complex64 until the estimated error meets the requested bound. */
+enum { RQC_POLICY_SIZE = 0, RQC_POLICY_CALIBRATED = 1 };
 
 void rqc_plan_opts_default(rqc_plan_opts* o);
 
@@ -147,7 +163,7 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts,
                            rqc_plan** out);
 void rqc_plan_destroy(rqc_plan* p);
 
-typedef struct rqc_plan_info {
+typedef struct rqc_plan_info_s {
   int32_t n_qubits, n_open, n_closed, n_sliced;
   uint64_t n_slices;
   int32_t n_leaves, n_steps;       /* steps = pairwise contractions */
@@ -162,18 +178,20 @@ typedef struct rqc_plan_info {
   double flops_per_bitstring;      /* steps that depend on the closed bits but on
                                       no sliced wire: once per bitstring, shared
                                       by all slices */
-} rqc_plan_info;
+} rqc_plan_info_t;
 
-rqc_status rqc_plan_get_info(const rqc_plan* p, rqc_plan_info* out);
+rqc_status rqc_plan_info(const rqc_plan* p, rqc_plan_info_t* out);
 
 /* Per-step shape: m, n, k are the numbers of row, column and summed index
- * bits of C[m,n] = A[m,k] B[k,n]; kernel 0 = generic SIMT, 1 = MFMA,
- * 2 = row streaming. */
+ * bits of C[m,n] = A[m,k] B[k,n]; kernel 0 = generic SIMT, 1 = FP32 MFMA,
+ * 2 = row streaming, 3 = 16-bit MFMA. */
 typedef struct rqc_step_info {
   int32_t m, n, k;
-  int32_t kernel;
+  int32_t kernel;         /* kernel of the step in RQC_F32 calls */
+  int32_t kernel_lp;      /* kernel of the step in RQC_F16 / RQC_BF16 calls */
   int32_t depends_on_slice, depends_on_bits;
-  int32_t lp_output;      /* output stored in 16 bits in reduced precision */
+  int32_t lp_output;      /* output stored in 16 bits in RQC_F16 calls */
+  int32_t lp_output_bf16; /* output stored in 16 bits in RQC_BF16 calls */
   int32_t reserved;
   double flops;           /* 8 * 2^(m+n+k) */
   double bytes_c64;       /* 8 * (|A| + |B| + |C|) */
@@ -196,10 +214,10 @@ rqc_status rqc_plan_resident_bytes(const rqc_plan* p, size_t* bytes);
 
 /* Upload leaves into caller memory (dev_ptr, 256-byte aligned, at least
  * rqc_plan_resident_bytes) and compute the slice-invariant subtrees on
- * `stream`.  The memory must stay valid until the plan is destroyed or
- * re-bound. */
-rqc_status rqc_plan_bind(rqc_plan* p, void* dev_ptr, size_t bytes,
-                         rqc_stream stream);
+ * `stream` (the call waits for them).  The memory must stay valid until the
+ * plan is destroyed or re-bound. */
+rqc_status rqc_plan_bind_memory(rqc_plan* p, void* dev_ptr, size_t bytes,
+                                rqc_stream stream);
 
 /* Workspace for a contraction of n_ids slices and n_batch bitstrings:
  * *min_bytes runs one slice and one bitstring at a time, *pref_bytes runs
@@ -208,7 +226,9 @@ rqc_status rqc_contract_workspace(const rqc_plan* p, uint64_t n_ids,
                                   uint64_t n_batch, int32_t prec,
                                   size_t* min_bytes, size_t* pref_bytes);
 
-/* Amplitudes of n_batch bitstrings, summed over the given slices.
+/* Amplitudes of n_batch bitstrings, summed over the given slices
+ * (Section 5.1: slices are independent sub-tasks; Section 6.4: the final
+ * reduction, here in FP64 in a fixed order).
  *   slice_ids   host array of n_ids slice ids (NULL with n_ids = 0: all);
  *   closed_bits host array n_batch x n_closed (0/1 bytes);
  *   workspace   device memory, 256-byte aligned, ws_bytes >= min_bytes;
@@ -217,7 +237,7 @@ rqc_status rqc_contract_workspace(const rqc_plan* p, uint64_t n_ids,
  *               holding each slice's own contribution.
  * All work is enqueued on `stream` as one graph launch (cached per shape);
  * the call returns before it finishes.  Slices whose reduced-precision run
- * produced a non-finite value are re-run in FP32 when rqc_contract_report
+ * produced a non-finite value are re-run in FP32 when rqc_contract_status
  * is called. */
 rqc_status rqc_contract(rqc_plan* p, const uint64_t* slice_ids, uint64_t n_ids,
                         const uint8_t* closed_bits, uint64_t n_batch,
@@ -234,8 +254,10 @@ typedef struct rqc_run_report {
 } rqc_run_report;
 
 /* Synchronise `stream`, re-run flagged slices in FP32 (synchronously) and
- * report.  ENUMERIC if non-finite values remain. */
-rqc_status rqc_contract_report(rqc_plan* p, rqc_stream stream,
+ * report.  A slice is flagged per group of bitstrings; its FP32 result is
+ * added for exactly the bitstrings whose sum skipped it.  ENUMERIC if
+ * non-finite values remain after the re-run (or appear in an FP32 call). */
+rqc_status rqc_contract_status(rqc_plan* p, rqc_stream stream,
                                rqc_run_report* out);
 
 /* ---- one pairwise contraction (Section 5.4) ----------------------------- */
@@ -271,6 +293,26 @@ rqc_status rqc_permute(const int32_t* labels_in, const int32_t* labels_out,
  * rqc_permute as the unfused baseline. */
 rqc_status rqc_cgemm(int64_t M, int64_t N, int64_t K, const void* A,
                      const void* B, void* C, rqc_stream stream);
+
+/* ---- large correlated batches: linear cross-entropy ------------------- */
+
+/* Statistics of an amplitude batch of an n_qubits circuit, in FP64 on the
+ * device (Appendix A: a bunch of 2^21 correlated amplitudes, fixing some
+ * qubits and exhausting the others, scored by the linear cross-entropy
+ * benchmark).  amps: device, n_amps x {re, im} doubles (the output of
+ * rqc_contract); samples: device array of n_samples entry indices or NULL.
+ * Writes 5 doubles to the device array out:
+ *   out[0] = sum |a|^2 over the batch; out[1] = sum |a|^4;
+ *   out[2] = 2^n_qubits * mean |a|^2 - 1  (every entry taken as a sample);
+ *   out[3] = 2^n_qubits * sum |a|^4 / sum |a|^2 - 1  (the expected linear
+ *            cross-entropy of entries drawn with probability |a|^2 / sum,
+ *            i.e. ideal sampling within the batch);
+ *   out[4] = 2^n_qubits * mean over samples of |a|^2 - 1 (0 without
+ *            samples; NaN if a sample index is >= n_amps).
+ * Enqueued on `stream`; one workgroup, fixed summation order. */
+rqc_status rqc_batch_xeb(const double* amps, uint64_t n_amps, int32_t n_qubits,
+                         const uint64_t* samples, uint64_t n_samples,
+                         double* out, rqc_stream stream);
 
 /* ---- serving: continuous batching of amplitude requests ---------------- */
 
@@ -339,13 +381,23 @@ void rqc_server_destroy(rqc_server* s);
  * effect at the next rqc_contract; results do not depend on it. */
 rqc_status rqc_plan_set_group_limit(rqc_plan* p, int32_t max_slices, int32_t max_bits);
 
-/* ---- measurement ---------------------------------------------------------- */
+/* ---- misc --------------------------------------------------------------- */
 
-/* Timing probe.  With kernel 0 (SIMT), 1 (MFMA) or 2 (rows), later rqc_contract calls
- * of this plan launch their kernels directly on the caller's stream instead
- * of replaying a graph, and every launch of that kernel is bracketed by a
- * pair of HIP events recorded on that stream; -1 turns the probe off and
- * restores graph launches. */
+const char* rqc_last_error(void);
+const char* rqc_version(void);
+
+/* ======================================================================
+ * Test and measurement hooks.  Not part of the amplitude path: they exist
+ * so that tests can force rare conditions from the host and so that the
+ * benchmark can time kernels on their own stream.
+ * ====================================================================== */
+
+/* Timing probe.  kernel 0 (SIMT), 1 (FP32 or 16-bit MFMA), 2 (rows),
+ * 3 (16-bit MFMA only) or 4 (every step launch): later rqc_contract calls of
+ * this plan launch their kernels directly on the caller's stream instead of
+ * replaying a graph, and every probed launch is bracketed by a pair of HIP
+ * events recorded on that stream; -1 turns the probe off and restores graph
+ * launches. */
 rqc_status rqc_plan_set_timing(rqc_plan* p, int32_t kernel);
 
 typedef struct rqc_timing {
@@ -356,18 +408,50 @@ typedef struct rqc_timing {
                            once and the output written once, per copy */
 } rqc_timing;
 
-/* Valid after rqc_contract_report of the call. */
+/* Valid after rqc_contract_status of the call. */
 rqc_status rqc_plan_get_timing(const rqc_plan* p, rqc_timing* out);
 
-/* ---- misc --------------------------------------------------------------- */
+/* One probed launch of the last reported call (i < launches). */
+typedef struct rqc_launch_timing {
+  int32_t step;         /* plan step index (rqc_plan_get_step) */
+  int32_t kernel;       /* 0 SIMT, 1 FP32 MFMA, 2 rows, 3 16-bit MFMA */
+  int32_t m, n, k;      /* bits of C[m,n] = A[m,k] B[k,n] */
+  int32_t copies;       /* independent problems of the launch */
+  int32_t store_a, store_b, store_c; /* 0 complex64, 1 FP16, 2 BF16 pairs */
+  int32_t reserved;
+  double ms, flops, bytes;
+} rqc_launch_timing;
 
-const char* rqc_last_error(void);
-const char* rqc_version(void);
+rqc_status rqc_plan_get_launch_timing(const rqc_plan* p, uint64_t i,
+                                      rqc_launch_timing* out);
 
-/* Test hook for the failure path of Section 5.5: adds `bias` to every
- * reduced-precision storage exponent shift of the plan (positive values
- * force overflow to inf, which flags the slice for an FP32 re-run). */
-rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias);
+/* Failure path of Section 5.5: adds `bias` to every reduced-precision
+ * storage exponent shift of the launches for bitstring groups that start at
+ * bitstring index first_bitstring or later (positive values force overflow
+ * to inf, which flags those (slice, bitstring group) pairs for an FP32
+ * re-run).  The kernels themselves run normally. */
+rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias,
+                                   uint64_t first_bitstring);
+
+/* One pairwise contraction with explicit operand storage (0 complex64,
+ * 1 FP16, 2 BF16: packed (re, im) 16-bit pairs, 4 bytes per element) and
+ * explicit kernel: 0 generic SIMT, 1 FP32 MFMA, 2 row streaming, 3 16-bit
+ * MFMA (mma_prec RQC_F16 or RQC_BF16).  With kernels 0 and 1 the arithmetic
+ * is FP32 on the converted operands (16-bit storage, FP32 compute); kernel 2
+ * uses the 16-bit matrix cores when A is stored in 16 bits and the summed
+ * labels fill chunks of 16 or more complex values, FP32 otherwise.  Labels,
+ * batching and strides as in rqc_pair_contract; no scaling is applied (the
+ * caller keeps values inside the 16-bit range).  EINVAL when the kernel's
+ * shape or layout conditions are not met (no fallback). */
+rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
+                                    const int32_t* labels_b, int32_t rank_b,
+                                    const int32_t* labels_c, int32_t rank_c,
+                                    const void* A, const void* B, void* C,
+                                    int32_t store_a, int32_t store_b,
+                                    int32_t store_c, int32_t batch_count,
+                                    int64_t stride_a, int64_t stride_b,
+                                    int64_t stride_c, int32_t kernel,
+                                    int32_t mma_prec, rqc_stream stream);
 
 #ifdef __cplusplus
 }

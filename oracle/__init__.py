@@ -18,7 +18,7 @@ Everything is plain numpy in complex128:
   data (``contract_ordered``: the order changes cost, never the value);
 * ``step``        -- a single pairwise contraction (Section 5.4) by
   ``numpy.einsum``, and by direct summation at sampled output coordinates;
-* ``metrics``     -- normalised error and linear fidelity.
+* ``metrics``     -- normalised error, linear fidelity, per-slice errors.
 
 Pins (see ``tests/test_oracle_pins.py``) tie each function to something
 other than itself: state vector vs tensor network, unitarity, the slice sum
@@ -31,7 +31,9 @@ from .statevector import statevector, amplitudes_sv, bit_index
 from .tn import (build_network, contract_network, amplitudes_tn,
                  slice_values_tn, wire_labels, contract_ordered, slice_values_ordered)
 from .step import einsum_step, sampled_step
-from .metrics import normalized_error, linear_fidelity, per_slice_error
+from .metrics import (normalized_error, linear_fidelity, per_slice_error,
+                      natural_slice_scale, slice_error_natural, xeb_of_samples,
+                      xeb_ideal_sampling)
 
 __all__ = [
     "gate_matrix", "H_M", "SQRT_X_M", "SQRT_Y_M", "SQRT_W_M", "fsim",
@@ -40,4 +42,5 @@ __all__ = [
     "contract_ordered", "slice_values_ordered",
     "wire_labels", "einsum_step", "sampled_step",
     "normalized_error", "linear_fidelity", "per_slice_error",
+    "natural_slice_scale", "slice_error_natural", "xeb_of_samples", "xeb_ideal_sampling",
 ]

@@ -48,7 +48,8 @@ class rqc_plan_opts(C.Structure):
                 ("forced_wires", C.POINTER(C.c_int32)), ("lp_min_log2", C.c_int32),
                 ("bf16_min_log2", C.c_int32), ("n_local_sliced", C.c_int32),
                 ("n_share_bits", C.c_int32), ("share_bits", C.POINTER(C.c_uint8)),
-                ("restarts", C.c_int32)]
+                ("restarts", C.c_int32), ("precision_policy", C.c_int32),
+                ("hbm_budget_bytes", C.c_uint64)]
 
 
 class rqc_plan_info(C.Structure):
@@ -62,8 +63,9 @@ class rqc_plan_info(C.Structure):
 
 class rqc_step_info(C.Structure):
     _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("k", C.c_int32), ("kernel", C.c_int32),
-                ("depends_on_slice", C.c_int32), ("depends_on_bits", C.c_int32),
-                ("lp_output", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double),
+                ("kernel_lp", C.c_int32), ("depends_on_slice", C.c_int32),
+                ("depends_on_bits", C.c_int32), ("lp_output", C.c_int32),
+                ("lp_output_bf16", C.c_int32), ("reserved", C.c_int32), ("flops", C.c_double),
                 ("bytes_c64", C.c_double)]
 
 
@@ -76,6 +78,13 @@ class rqc_run_report(C.Structure):
 class rqc_timing(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("total_ms", C.c_double), ("flops", C.c_double),
                 ("bytes", C.c_double)]
+
+
+class rqc_launch_timing(C.Structure):
+    _fields_ = [("step", C.c_int32), ("kernel", C.c_int32), ("m", C.c_int32), ("n", C.c_int32),
+                ("k", C.c_int32), ("copies", C.c_int32), ("store_a", C.c_int32),
+                ("store_b", C.c_int32), ("store_c", C.c_int32), ("reserved", C.c_int32),
+                ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
 
 
 class rqc_server_opts(C.Structure):
@@ -115,20 +124,21 @@ _PROTOS = {
     "rqc_plan_opts_default": (None, [C.POINTER(rqc_plan_opts)]),
     "rqc_plan_create": (_S, [_P, C.POINTER(rqc_plan_opts), C.POINTER(_P)]),
     "rqc_plan_destroy": (None, [_P]),
-    "rqc_plan_get_info": (_S, [_P, C.POINTER(rqc_plan_info)]),
+    "rqc_plan_info": (_S, [_P, C.POINTER(rqc_plan_info)]),
     "rqc_plan_get_step": (_S, [_P, C.c_int32, C.POINTER(rqc_step_info)]),
     "rqc_plan_export_json": (_S, [_P, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
     "rqc_plan_resident_bytes": (_S, [_P, C.POINTER(C.c_size_t)]),
-    "rqc_plan_bind": (_S, [_P, _P, C.c_size_t, _P]),
+    "rqc_plan_bind_memory": (_S, [_P, _P, C.c_size_t, _P]),
     "rqc_contract_workspace": (_S, [_P, C.c_uint64, C.c_uint64, C.c_int32,
                                     C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "rqc_contract": (_S, [_P, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint8),
                           C.c_uint64, C.c_int32, _P, C.c_size_t, _P, _P, _P]),
-    "rqc_contract_report": (_S, [_P, _P, C.POINTER(rqc_run_report)]),
+    "rqc_contract_status": (_S, [_P, _P, C.POINTER(rqc_run_report)]),
     "rqc_pair_contract": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                C.POINTER(C.c_int32), C.c_int32, _P, _P, _P, C.c_int32,
                                C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P]),
     "rqc_permute": (_S, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, _P, _P, _P]),
+    "rqc_batch_xeb": (_S, [_P, C.c_uint64, C.c_int32, _P, C.c_uint64, _P, _P]),
     "rqc_cgemm": (_S, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P]),
     "rqc_server_create": (_S, [C.POINTER(rqc_server_opts), C.POINTER(_P)]),
     "rqc_server_submit": (_S, [_P, C.POINTER(rqc_request), C.POINTER(C.c_uint64)]),
@@ -139,7 +149,12 @@ _PROTOS = {
     "rqc_server_destroy": (None, [_P]),
     "rqc_last_error": (C.c_char_p, []),
     "rqc_version": (C.c_char_p, []),
-    "rqc_plan_set_scale_bias": (_S, [_P, C.c_int32]),
+    "rqc_plan_set_scale_bias": (_S, [_P, C.c_int32, C.c_uint64]),
+    "rqc_plan_get_launch_timing": (_S, [_P, C.c_uint64, C.POINTER(rqc_launch_timing)]),
+    "rqc_pair_contract_stored": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
+                                      C.c_int32, C.POINTER(C.c_int32), C.c_int32, _P, _P, _P,
+                                      C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
+                                      C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P]),
     "rqc_plan_set_timing": (_S, [_P, C.c_int32]),
     "rqc_plan_set_group_limit": (_S, [_P, C.c_int32, C.c_int32]),
     "rqc_plan_get_timing": (_S, [_P, C.POINTER(rqc_timing)]),
@@ -233,7 +248,8 @@ class Plan:
 
     def __init__(self, network: Network, max_log2_elems=0, n_sliced=-1, path_trials=256,
                  reconf_rounds=-1, seed=0, forced_wires=(), lp_min_log2=0, bf16_min_log2=0,
-                 n_local_sliced=0, share_bits=(), restarts=1):
+                 n_local_sliced=0, share_bits=(), restarts=1, precision_policy=0,
+                 hbm_budget_bytes=0):
         o = rqc_plan_opts()
         _lib.rqc_plan_opts_default(C.byref(o))
         o.max_log2_elems = int(max_log2_elems)
@@ -252,6 +268,8 @@ class Plan:
         o.n_share_bits = len(share_bits)
         o.restarts = int(restarts)
         o.share_bits = C.cast(self._share, C.POINTER(C.c_uint8))
+        o.precision_policy = int(precision_policy)
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
         h = C.c_void_p()
         _check(_lib.rqc_plan_create(network.h, C.byref(o), C.byref(h)))
         self.h = h
@@ -268,7 +286,7 @@ class Plan:
     # ---- host-side description
     def info(self) -> dict:
         i = rqc_plan_info()
-        _check(_lib.rqc_plan_get_info(self.h, C.byref(i)))
+        _check(_lib.rqc_plan_info(self.h, C.byref(i)))
         return {f: getattr(i, f) for f, _ in rqc_plan_info._fields_}
 
     def steps(self):
@@ -316,11 +334,14 @@ class Plan:
         import torch
         nbytes = max(256, self.resident_bytes())
         self._resident = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        _check(_lib.rqc_plan_bind(self.h, _ptr(self._resident), nbytes, _stream_handle(stream)))
+        _check(_lib.rqc_plan_bind_memory(self.h, _ptr(self._resident), nbytes,
+                                         _stream_handle(stream)))
         return self
 
-    def set_scale_bias(self, bias: int):
-        _check(_lib.rqc_plan_set_scale_bias(self.h, int(bias)))
+    def set_scale_bias(self, bias: int, first_bitstring: int = 0):
+        """Test hook: bias the 16-bit storage shifts of bitstring groups from
+        first_bitstring on (forces the FP32 re-run path)."""
+        _check(_lib.rqc_plan_set_scale_bias(self.h, int(bias), int(first_bitstring)))
 
     def contract(self, closed_bits, slice_ids=None, prec=F32, workspace=None,
                  per_slice=False, stream=None, sync=True, out=None):
@@ -379,9 +400,19 @@ class Plan:
         _check(_lib.rqc_plan_get_timing(self.h, C.byref(t)))
         return {f: getattr(t, f) for f, _ in rqc_timing._fields_}
 
+    def launch_timings(self):
+        """Per probed launch of the last reported call: step, kernel, shape,
+        storage, event-measured ms, algorithmic flops and bytes."""
+        out = []
+        for i in range(int(self.timing()["launches"])):
+            t = rqc_launch_timing()
+            _check(_lib.rqc_plan_get_launch_timing(self.h, i, C.byref(t)))
+            out.append({f: getattr(t, f) for f, _ in rqc_launch_timing._fields_})
+        return out
+
     def report(self, stream=None) -> dict:
         r = rqc_run_report()
-        _check(_lib.rqc_contract_report(self.h, _stream_handle(stream), C.byref(r)))
+        _check(_lib.rqc_contract_status(self.h, _stream_handle(stream), C.byref(r)))
         return {f: getattr(r, f) for f, _ in rqc_run_report._fields_}
 
 
@@ -404,6 +435,41 @@ def pair_contract(A, B, labels_a, labels_b, labels_c, C_out=None, kernel=-1, bat
                                   int(batch), int(stride_a), int(stride_b), int(stride_c),
                                   int(kernel), int(prec), _stream_handle(stream)))
     return C_out
+
+
+ST_C64, ST_F16, ST_BF16 = 0, 1, 2
+KERN_SIMT, KERN_MFMA, KERN_ROWS, KERN_MFMA16 = 0, 1, 2, 3
+
+
+def pair_contract_stored(A, B, C_out, labels_a, labels_b, labels_c, store_a, store_b, store_c,
+                         kernel, mma_prec=F32, batch=1, stride_a=0, stride_b=0, stride_c=0,
+                         stream=None):
+    """One contraction with explicit operand storage (ST_*) and kernel
+    (KERN_*); A, B, C_out are device tensors holding complex64 or packed
+    16-bit (re, im) pairs as their storage code says."""
+    _check(_lib.rqc_pair_contract_stored(_i32(labels_a), len(labels_a), _i32(labels_b),
+                                         len(labels_b), _i32(labels_c), len(labels_c), _ptr(A),
+                                         _ptr(B), _ptr(C_out), int(store_a), int(store_b),
+                                         int(store_c), int(batch), int(stride_a), int(stride_b),
+                                         int(stride_c), int(kernel), int(mma_prec),
+                                         _stream_handle(stream)))
+    return C_out
+
+
+def batch_xeb(amps, n_qubits, samples=None, stream=None):
+    """FP64 statistics of an amplitude batch on the device (rqc_batch_xeb):
+    amps is the float64 device tensor of (re, im) pairs that contract()
+    returns; samples an int64 device tensor of entry indices or None."""
+    import torch
+    n = amps.numel() // 2
+    out = torch.empty(5, dtype=torch.float64, device=amps.device)
+    ns = 0 if samples is None else samples.numel()
+    _check(_lib.rqc_batch_xeb(_ptr(amps), n, int(n_qubits),
+                              _ptr(samples) if samples is not None else None, ns, _ptr(out),
+                              _stream_handle(stream)))
+    v = out.cpu().numpy()
+    return {"sum_p": float(v[0]), "sum_p2": float(v[1]), "xeb_all": float(v[2]),
+            "xeb_ideal_sampling": float(v[3]), "xeb_samples": float(v[4])}
 
 
 def permute(X, labels_in, labels_out, out=None, stream=None):

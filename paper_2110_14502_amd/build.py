@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librqc.so")
 
-SOURCES = ["k_mfma32.hip", "k_mfma16.hip", "k_rows.hip", "k_simt.hip", "kernels.hip", "network.cpp", "planner.cpp", "executor.cpp", "capi.cpp", "server.cpp"]
+# Every HIP and C++ source of csrc/ (host C++ is compiled as HIP too).
+SOURCES = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-I" + INCLUDE, "-I" + CSRC]
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

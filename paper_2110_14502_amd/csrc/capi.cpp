@@ -144,8 +144,18 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_
     po.share_bits.assign(o.share_bits, o.share_bits + o.n_share_bits);
     for (auto& b : po.share_bits)
       if (b > 1) throw rqc::Error{RQC_EINVAL, "share bits must be 0 or 1"};
+    if (o.precision_policy != RQC_POLICY_SIZE && o.precision_policy != RQC_POLICY_CALIBRATED)
+      throw rqc::Error{RQC_EINVAL, "unknown precision policy"};
+    po.precision_policy = o.precision_policy;
     rqc::make_plan(p->pd);
-    rqc::resident_bytes(p);
+    const size_t res = rqc::resident_bytes(p);
+    if (o.hbm_budget_bytes) {
+      const rqc::GroupLayout& L1 = rqc::group_layout(p, RQC_F32, 1, 1);
+      const size_t need = res + (size_t)rqc::ws_layout(p, L1, 1, 1).total;
+      if (need > o.hbm_budget_bytes)
+        throw rqc::Error{RQC_EHBM, "plan needs " + std::to_string(need) +
+                                       " device bytes for one slice, above the budget"};
+    }
   } catch (...) {
     delete p;
     throw;
@@ -157,7 +167,7 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_
 
 void rqc_plan_destroy(rqc_plan* p) { delete p; }
 
-rqc_status rqc_plan_get_info(const rqc_plan* p, rqc_plan_info* out) {
+rqc_status rqc_plan_info(const rqc_plan* p, rqc_plan_info_t* out) {
   RQC_TRY
   if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
   const rqc::PlanData& pd = p->pd;
@@ -191,9 +201,11 @@ rqc_status rqc_plan_get_step(const rqc_plan* p, int32_t i, rqc_step_info* out) {
   out->n = st.n;
   out->k = st.k;
   out->kernel = i < (int)p->kern.size() ? p->kern[i] : -1;
+  out->kernel_lp = i < (int)p->kern_lp.size() ? p->kern_lp[i] : -1;
   out->depends_on_slice = st.dep_s;
   out->depends_on_bits = st.dep_b;
   out->lp_output = st.lp;
+  out->lp_output_bf16 = st.lp_bf16;
   out->flops = 8.0 * std::ldexp(1.0, st.m + st.n + st.k);
   out->bytes_c64 = 8.0 * (std::ldexp(1.0, st.m + st.k) + std::ldexp(1.0, st.n + st.k) + std::ldexp(1.0, st.m + st.n));
   return RQC_OK;
@@ -223,7 +235,7 @@ rqc_status rqc_plan_resident_bytes(const rqc_plan* p, size_t* bytes) {
   RQC_CATCH
 }
 
-rqc_status rqc_plan_bind(rqc_plan* p, void* dev_ptr, size_t bytes, rqc_stream stream) {
+rqc_status rqc_plan_bind_memory(rqc_plan* p, void* dev_ptr, size_t bytes, rqc_stream stream) {
   RQC_TRY
   if (!p || !dev_ptr) throw rqc::Error{RQC_EINVAL, "NULL argument"};
   rqc::bind_plan(p, dev_ptr, bytes, static_cast<hipStream_t>(stream));
@@ -261,7 +273,7 @@ rqc_status rqc_contract(rqc_plan* p, const uint64_t* slice_ids, uint64_t n_ids,
   RQC_CATCH
 }
 
-rqc_status rqc_contract_report(rqc_plan* p, rqc_stream stream, rqc_run_report* out) {
+rqc_status rqc_contract_status(rqc_plan* p, rqc_stream stream, rqc_run_report* out) {
   RQC_TRY
   if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
   rqc::report(p, p->pending, static_cast<hipStream_t>(stream), out);
@@ -269,13 +281,13 @@ rqc_status rqc_contract_report(rqc_plan* p, rqc_stream stream, rqc_run_report* o
   RQC_CATCH
 }
 
-rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias) {
+rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias, uint64_t first_bitstring) {
   RQC_TRY
   if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
   if (bias < -64 || bias > 64) throw rqc::Error{RQC_EINVAL, "bias out of range"};
   p->scale_bias = bias;
-  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
-  p->graphs.clear();
+  p->scale_bias_from = first_bitstring;
+  rqc::clear_graphs(p);
   return RQC_OK;
   RQC_CATCH
 }
@@ -293,10 +305,10 @@ rqc_status rqc_plan_set_group_limit(rqc_plan* p, int32_t max_slices, int32_t max
 rqc_status rqc_plan_set_timing(rqc_plan* p, int32_t kernel) {
   RQC_TRY
   if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
-  if (kernel < -1 || kernel > 2) throw rqc::Error{RQC_EINVAL, "kernel must be -1, 0, 1 or 2"};
+  if (kernel < -1 || kernel > rqc::kTimeAll)
+    throw rqc::Error{RQC_EINVAL, "kernel must be -1, 0, 1, 2, 3 or 4"};
   p->timing_kernel = kernel;
-  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
-  p->graphs.clear();
+  rqc::clear_graphs(p);
   return RQC_OK;
   RQC_CATCH
 }
@@ -305,6 +317,28 @@ rqc_status rqc_plan_get_timing(const rqc_plan* p, rqc_timing* out) {
   RQC_TRY
   if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
   *out = p->last_timing;
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_get_launch_timing(const rqc_plan* p, uint64_t i, rqc_launch_timing* out) {
+  RQC_TRY
+  if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  if (i >= p->tms.size() || i >= p->trec.size()) throw rqc::Error{RQC_EINVAL, "launch index out of range"};
+  const rqc::LaunchRecord& r = p->trec[i];
+  std::memset(out, 0, sizeof *out);
+  out->step = r.step;
+  out->kernel = r.kernel;
+  out->m = r.m;
+  out->n = r.n;
+  out->k = r.k;
+  out->copies = r.copies;
+  out->store_a = r.sa;
+  out->store_b = r.sb;
+  out->store_c = r.sc;
+  out->ms = p->tms[i];
+  out->flops = r.flops;
+  out->bytes = r.bytes;
   return RQC_OK;
   RQC_CATCH
 }
@@ -347,6 +381,75 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
   rqc::hip_check(rqc::launch_step(d, kern, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, lp_kind,
                                   static_cast<hipStream_t>(stream)),
                  "pair contract");
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
+                                    const int32_t* labels_b, int32_t rank_b,
+                                    const int32_t* labels_c, int32_t rank_c, const void* A,
+                                    const void* B, void* C, int32_t store_a, int32_t store_b,
+                                    int32_t store_c, int32_t batch_count, int64_t stride_a,
+                                    int64_t stride_b, int64_t stride_c, int32_t kernel,
+                                    int32_t mma_prec, rqc_stream stream) {
+  RQC_TRY
+  if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
+  if (rank_a < 0 || rank_b < 0 || rank_c < 0 || rank_a > 40 || rank_b > 40 || rank_c > 40)
+    throw rqc::Error{RQC_EINVAL, "rank out of range"};
+  if ((rank_a && !labels_a) || (rank_b && !labels_b) || (rank_c && !labels_c))
+    throw rqc::Error{RQC_EINVAL, "NULL labels"};
+  if (batch_count < 1 || batch_count > 65535) throw rqc::Error{RQC_EINVAL, "batch_count out of range"};
+  for (int32_t st : {store_a, store_b, store_c})
+    if (st < rqc::ST_C64 || st > rqc::ST_BF16) throw rqc::Error{RQC_EINVAL, "storage code out of range"};
+  if (kernel < rqc::KERN_SIMT || kernel > rqc::KERN_MFMA16) throw rqc::Error{RQC_EINVAL, "kernel must be 0..3"};
+  if (kernel == rqc::KERN_MFMA16 && mma_prec != RQC_F16 && mma_prec != RQC_BF16)
+    throw rqc::Error{RQC_EINVAL, "the 16-bit MFMA kernel needs mma_prec RQC_F16 or RQC_BF16"};
+  // One 16-bit type per call (the kernels are built for one LP type mixed
+  // with complex64).
+  int lp = 0;
+  for (int32_t st : {store_a, store_b, store_c})
+    if (st != rqc::ST_C64) {
+      if (lp && st != lp) throw rqc::Error{RQC_EINVAL, "FP16 and BF16 storage in one call"};
+      lp = st;
+    }
+  if (kernel == rqc::KERN_MFMA16 && lp && lp != (mma_prec == RQC_F16 ? rqc::ST_F16 : rqc::ST_BF16))
+    throw rqc::Error{RQC_EINVAL, "16-bit storage type differs from mma_prec"};
+  std::vector<int> la(labels_a, labels_a + rank_a), lb(labels_b, labels_b + rank_b),
+      lc(labels_c, labels_c + rank_c);
+  for (auto* l : {&la, &lb}) {
+    std::vector<int> v(*l);
+    std::sort(v.begin(), v.end());
+    if (std::adjacent_find(v.begin(), v.end()) != v.end()) throw rqc::Error{RQC_EINVAL, "repeated label"};
+  }
+  int kern = kernel;
+  rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, kern);
+  if (kern != kernel) throw rqc::Error{RQC_EINVAL, "shape or layout not supported by the requested kernel"};
+  d.A = A;
+  d.B = B;
+  d.C = C;
+  d.sA_s = stride_a;
+  d.sB_s = stride_b;
+  d.sC_s = stride_c;
+  d.gs_c = batch_count;
+  d.copies = batch_count;
+  const int lp_kind = kernel == rqc::KERN_MFMA16 ? (mma_prec == RQC_F16 ? rqc::ST_F16 : rqc::ST_BF16) : 0;
+  rqc::hip_check(rqc::launch_step(d, kern, store_a, store_b, store_c, lp_kind,
+                                  static_cast<hipStream_t>(stream)),
+                 "pair contract (stored)");
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_batch_xeb(const double* amps, uint64_t n_amps, int32_t n_qubits,
+                         const uint64_t* samples, uint64_t n_samples, double* out,
+                         rqc_stream stream) {
+  RQC_TRY
+  if (!amps || !out) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
+  if (n_samples && !samples) throw rqc::Error{RQC_EINVAL, "samples is NULL"};
+  if (n_qubits < 1 || n_qubits > 1000) throw rqc::Error{RQC_EINVAL, "n_qubits out of range"};
+  rqc::hip_check(rqc::launch_batch_stats(amps, n_amps, n_qubits, samples, n_samples, out,
+                                         static_cast<hipStream_t>(stream)),
+                 "batch statistics");
   return RQC_OK;
   RQC_CATCH
 }

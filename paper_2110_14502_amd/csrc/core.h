@@ -91,6 +91,7 @@ struct PlanOpts {
   int n_local = 0;            // 0: all sliced wires enumerated by slice ids
   std::vector<uint8_t> share_bits;  // values of the fixed sliced wires
   int restarts = 1;                 // independent searches, best kept
+  int precision_policy = 0;         // RQC_POLICY_*
 };
 
 struct Tree {

@@ -331,7 +331,17 @@ void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
   p->res = base;
   p->res_bytes = bytes;
   p->bound = true;
-  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  clear_graphs(p);
+}
+
+void clear_graphs(rqc_plan* p) {
+  for (auto& kv : p->graphs) {
+    if (kv.second.done) {
+      (void)hipEventSynchronize(kv.second.done);
+      (void)hipEventDestroy(kv.second.done);
+    }
+    (void)hipGraphExecDestroy(kv.second.exec);
+  }
   p->graphs.clear();
 }
 
@@ -489,8 +499,9 @@ WsLayout ws_layout(rqc_plan* p, const GroupLayout& L, uint64_t n_ids, uint64_t n
   o = align256(o + 8 * (int64_t)n_ids);
   w.bits_off = o;
   o = align256(o + (int64_t)n_batch * (int64_t)std::max<size_t>(1, pd.net.closed.size()));
+  w.n_bgroups = ((int64_t)n_batch + L.gb - 1) / L.gb;
   w.flags_off = o;
-  o = align256(o + 4 * (int64_t)n_ids);
+  o = align256(o + 4 * (int64_t)n_ids * w.n_bgroups);
   w.jobs_off = o;
   o = align256(o + (int64_t)sizeof(LeafJob) * (int64_t)std::max<size_t>(1, L.jobs.size()));
   w.tmp_off = o;
@@ -529,12 +540,14 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
     if (P.m_off < 0) return nullptr;
     return reinterpret_cast<float*>(P.resident ? p->res + P.m_off : scale + P.m_off);
   };
-  hip_check(launch_fill_i32(flags, 0, (int64_t)n_ids, s), "clear flags");
+  hip_check(launch_fill_i32(flags, 0, (int64_t)n_ids * W.n_bgroups, s), "clear flags");
   size_t probe = 0;
-  p->tflops.clear();
-  p->tbytes.clear();
+  p->trec.clear();
   for (uint64_t b0 = 0; b0 < n_batch; b0 += L.gb) {
     const int gbc = (int)std::min<uint64_t>(L.gb, n_batch - b0);
+    // This bitstring group's row of flags: one per slice.
+    int32_t* gflags = flags + (int64_t)(b0 / L.gb) * (int64_t)n_ids;
+    const int bias = b0 >= p->scale_bias_from ? p->scale_bias : 0;
     for (uint64_t g0 = 0; g0 < n_ids; g0 += L.gs) {
       const int gsc = (int)std::min<uint64_t>(L.gs, n_ids - g0);
       if (track && L.scale_bytes > 0)
@@ -565,8 +578,8 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
           d.maxA_const = A.max_const, d.maxB_const = B.max_const;
           d.eA_s = A.es, d.eA_b = A.eb, d.eB_s = B.es, d.eB_b = B.eb, d.eC_s = C.es, d.eC_b = C.eb;
           d.lp_out = C.store != ST_C64;
-          d.bias = p->scale_bias;
-          d.flag = flags + g0;
+          d.bias = bias;
+          d.flag = gflags + g0;
           d.dep_s_c = C.dep_s;
           d.flag_n = gsc;
         }
@@ -577,7 +590,8 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
           d.p_stride = (int64_t(1) << pd.node_labels[st.node].size()) * (C.dep_s ? L.gs : 1) *
                        (C.dep_b ? L.gb : 1);
         }
-        const bool timed = kern == p->timing_kernel || (kern == KERN_MFMA16 && p->timing_kernel == KERN_MFMA);
+        const bool timed = p->timing_kernel == kTimeAll || kern == p->timing_kernel ||
+                           (kern == KERN_MFMA16 && p->timing_kernel == KERN_MFMA);
         if (timed) {
           if (p->tev.size() < 2 * (probe + 1)) {
             // Timing only: no system-scope fence, so that the recorded
@@ -598,16 +612,23 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
           const double cp = (double)d.copies;
           const int ca = (A.dep_s ? (C.dep_s ? gsc : 1) : 1) * (A.dep_b ? (C.dep_b ? gbc : 1) : 1);
           const int cb = (B.dep_s ? (C.dep_s ? gsc : 1) : 1) * (B.dep_b ? (C.dep_b ? gbc : 1) : 1);
-          p->tflops.push_back(8.0 * std::ldexp(1.0, st.m + st.n + st.k) * cp);
-          p->tbytes.push_back(elsize(A.store) * std::ldexp(1.0, st.m + st.k) * ca +
-                              elsize(B.store) * std::ldexp(1.0, st.n + st.k) * cb +
-                              elsize(C.store) * std::ldexp(1.0, st.m + st.n) * cp);
+          LaunchRecord lr;
+          lr.step = (int)i;
+          lr.kernel = kern;
+          lr.m = st.m, lr.n = st.n, lr.k = st.k;
+          lr.copies = d.copies;
+          lr.sa = A.store, lr.sb = B.store, lr.sc = C.store;
+          lr.flops = 8.0 * std::ldexp(1.0, st.m + st.n + st.k) * cp;
+          lr.bytes = elsize(A.store) * std::ldexp(1.0, st.m + st.k) * ca +
+                     elsize(B.store) * std::ldexp(1.0, st.n + st.k) * cb +
+                     elsize(C.store) * std::ldexp(1.0, st.m + st.n) * cp;
+          p->trec.push_back(lr);
         }
       }
       const int root = pd.tree.root;
       const Placement& R = L.place[root];
       hip_check(launch_slice_sum(ptr(R), R.store, eptr(R), R.s_stride, R.b_stride, R.es, R.eb,
-                                 R.dep_s, R.dep_b, n_elems, gsc, gbc, lp_mode ? flags + g0 : nullptr,
+                                 R.dep_s, R.dep_b, n_elems, gsc, gbc, lp_mode ? gflags + g0 : nullptr,
                                  out, per_slice, ps_row0 + (int64_t)g0, (int64_t)n_batch,
                                  (int64_t)b0, g0 == 0 ? 1 : 0, s),
                 "slice sum");
@@ -646,7 +667,7 @@ static void choose_group(rqc_plan* p, int prec, uint64_t n_ids, uint64_t n_batch
 
 void contract(rqc_plan* p, const uint64_t* ids_in, uint64_t n_ids, const uint8_t* bits,
               uint64_t n_batch, int prec, void* ws_v, size_t ws_bytes, double* out,
-              double* per_slice, hipStream_t s, PendingRun& r) {
+              double* per_slice, hipStream_t s, PendingRun& r, bool direct) {
   PlanData& pd = p->pd;
   if (!p->bound) throw Error{RQC_EINVAL, "plan is not bound to device memory"};
   if (prec != RQC_F32 && prec != RQC_F16 && prec != RQC_BF16) throw Error{RQC_EINVAL, "bad precision"};
@@ -689,12 +710,14 @@ void contract(rqc_plan* p, const uint64_t* ids_in, uint64_t n_ids, const uint8_t
   GraphKey key{prec, gs, gb, n_ids, n_batch, ws_v, out, per_slice};
   auto it = p->graphs.find(key);
   int reused = 0;
-  if (p->timing_kernel >= 0) {
-    // Timing probe: direct launches so that each probed launch is bracketed
-    // by events recorded on `s` itself.
+  if (p->timing_kernel >= 0 || direct) {
+    // Timing probe, or a caller that wants no graph objects: direct launches
+    // on `s` (each probed launch bracketed by events recorded on `s`).
     record_call(p, L, W, n_ids, n_batch, ws, out, per_slice, 0, s);
   } else if (it != p->graphs.end()) {
-    hip_check(hipGraphLaunch(it->second, s), "graph launch");
+    hip_check(hipGraphLaunch(it->second.exec, s), "graph launch");
+    hip_check(hipEventRecord(it->second.done, s), "graph event");
+    it->second.last_use = ++p->graph_clock;
     reused = 1;
   } else {
     if (!p->capture_stream)
@@ -709,16 +732,31 @@ void contract(rqc_plan* p, const uint64_t* ids_in, uint64_t n_ids, const uint8_t
     }
     hipGraph_t g;
     hip_check(hipStreamEndCapture(p->capture_stream, &g), "end capture");
-    hipGraphExec_t ex;
-    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    GraphEntry ge;
+    hipError_t e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     hip_check(e, "graph instantiate");
-    if (p->graphs.size() > 32) {
-      for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
-      p->graphs.clear();
+    e = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipGraphExecDestroy(ge.exec);
+      hip_check(e, "graph event");
     }
-    p->graphs[key] = ex;
-    hip_check(hipGraphLaunch(ex, s), "graph launch");
+    // Bounded cache: the least recently launched exec goes, once its last
+    // launch (possibly still running on another stream) has completed.
+    while (p->graphs.size() >= kMaxGraphs) {
+      auto victim = p->graphs.begin();
+      for (auto jt = p->graphs.begin(); jt != p->graphs.end(); ++jt)
+        if (jt->second.last_use < victim->second.last_use) victim = jt;
+      (void)hipEventSynchronize(victim->second.done);
+      (void)hipEventDestroy(victim->second.done);
+      (void)hipGraphExecDestroy(victim->second.exec);
+      p->graphs.erase(victim);
+    }
+    ge.last_use = ++p->graph_clock;
+    GraphEntry& slot = p->graphs[key];
+    slot = ge;
+    hip_check(hipGraphLaunch(slot.exec, s), "graph launch");
+    hip_check(hipEventRecord(slot.done, s), "graph event");
   }
   r.active = true;
   r.prec = prec;
@@ -741,13 +779,15 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
   hip_check(hipStreamSynchronize(s), "synchronize");
   if (!r.active) return;
   p->last_timing = rqc_timing{};
-  for (size_t i = 0; i < p->tflops.size() && p->timing_kernel >= 0; ++i) {
+  p->tms.clear();
+  for (size_t i = 0; i < p->trec.size() && p->timing_kernel >= 0; ++i) {
     float ms = 0.f;
     hip_check(hipEventElapsedTime(&ms, p->tev[2 * i], p->tev[2 * i + 1]), "event time");
+    p->tms.push_back(ms);
     p->last_timing.launches++;
     p->last_timing.total_ms += ms;
-    p->last_timing.flops += p->tflops[i];
-    p->last_timing.bytes += p->tbytes[i];
+    p->last_timing.flops += p->trec[i].flops;
+    p->last_timing.bytes += p->trec[i].bytes;
   }
   rep->n_slices = r.n_ids;
   rep->slices_per_group = r.gs;
@@ -756,11 +796,19 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
   rep->flops = r.flops;
   const GroupLayout& L0 = group_layout(p, r.prec, r.gs, r.gb);
   const WsLayout W0 = ws_layout(p, L0, r.n_ids, r.n_batch);
-  std::vector<int32_t> flags(r.n_ids);
-  hip_check(hipMemcpy(flags.data(), r.ws + W0.flags_off, 4 * r.n_ids, hipMemcpyDeviceToHost), "flags");
+  const int64_t nbg = W0.n_bgroups;
+  std::vector<int32_t> flags((size_t)(r.n_ids * nbg));
+  hip_check(hipMemcpy(flags.data(), r.ws + W0.flags_off, 4 * flags.size(), hipMemcpyDeviceToHost),
+            "flags");
+  // A slice is re-run when any of its bitstring groups was flagged; its FP32
+  // result is then added for exactly those groups, whose slice sums skipped it.
   std::vector<uint64_t> redo;
   for (uint64_t i = 0; i < r.n_ids; ++i)
-    if (flags[i]) redo.push_back(i);
+    for (int64_t g = 0; g < nbg; ++g)
+      if (flags[(size_t)(g * (int64_t)r.n_ids + (int64_t)i)]) {
+        redo.push_back(i);
+        break;
+      }
   r.active = false;
   if (redo.empty()) return;
   // With normalised complex64 storage a non-finite FP32 value can only come
@@ -774,7 +822,10 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
     throw Error{RQC_EHBM, "workspace too small for the FP32 re-run"};
   const GroupLayout& L = group_layout(p, RQC_F32, 1, gb);
   const WsLayout W = ws_layout(p, L, 1, r.n_batch);
-  const int64_t n_out = 2 * (int64_t)r.n_batch << p->pd.net.open.size();
+  const int64_t ne2 = int64_t(2) << p->pd.net.open.size();  // doubles per bitstring
+  const std::vector<LaunchRecord> keep_rec = p->trec;  // the probed call's records
+  double* tmp = reinterpret_cast<double*>(r.ws + W.tmp_off);
+  std::vector<int32_t> f32_flags((size_t)W.n_bgroups);
   for (uint64_t idx : redo) {
     const uint64_t id = r.ids[idx];
     hip_check(hipMemcpyAsync(r.ws + W.ids_off, &id, 8, hipMemcpyHostToDevice, s), "ids");
@@ -783,18 +834,36 @@ void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
       hip_check(hipMemcpyAsync(r.ws + W.jobs_off, L.jobs.data(), sizeof(LeafJob) * L.jobs.size(),
                                hipMemcpyHostToDevice, s),
                 "jobs");
-    double* tmp = reinterpret_cast<double*>(r.ws + W.tmp_off);
-    record_call(p, L, W, 1, r.n_batch, r.ws, tmp, r.per_slice, (int64_t)idx, s);
-    hip_check(launch_add_f64(r.out, tmp, n_out, s), "add re-run");
+    record_call(p, L, W, 1, r.n_batch, r.ws, tmp, nullptr, 0, s);
+    for (int64_t g = 0; g < nbg; ++g) {
+      if (!flags[(size_t)(g * (int64_t)r.n_ids + (int64_t)idx)]) continue;
+      const int64_t b0 = g * r.gb;
+      const int64_t nb = std::min<int64_t>(r.gb, (int64_t)r.n_batch - b0);
+      hip_check(launch_add_f64(r.out + b0 * ne2, tmp + b0 * ne2, nb * ne2, s), "add re-run");
+      if (r.per_slice)
+        hip_check(hipMemcpyAsync(r.per_slice + ((int64_t)idx * (int64_t)r.n_batch + b0) * ne2,
+                                 tmp + b0 * ne2, 8 * nb * ne2, hipMemcpyDeviceToDevice, s),
+                  "per-slice re-run");
+    }
     hip_check(hipStreamSynchronize(s), "re-run");
+    hip_check(hipMemcpy(f32_flags.data(), r.ws + W.flags_off, 4 * f32_flags.size(),
+                        hipMemcpyDeviceToHost),
+              "re-run flags");
+    for (int32_t f : f32_flags)
+      if (f) {
+        p->trec = keep_rec;
+        throw Error{RQC_ENUMERIC, "non-finite values persisted after the FP32 re-run of slice " +
+                                      std::to_string(id)};
+      }
     rep->fp32_reruns++;
   }
+  p->trec = keep_rec;
 }
 
 }  // namespace rqc
 
 rqc_plan::~rqc_plan() {
-  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  rqc::clear_graphs(this);
   for (auto e : tev) (void)hipEventDestroy(e);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }

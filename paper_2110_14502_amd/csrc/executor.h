@@ -64,8 +64,26 @@ struct PendingRun {
   double flops = 0;
 };
 
+// Workspace of one call.  Flags: one int32 per (bitstring group, slice), set
+// when a reduced-precision copy of that slice in that group of bitstrings
+// held a non-finite value (the slice sum then skipped it).
 struct WsLayout {
   int64_t ids_off, bits_off, flags_off, jobs_off, tmp_off, scale_off, arena_off, total;
+  int64_t n_bgroups;
+};
+
+// A captured call and the event recorded after its last launch (an exec is
+// destroyed only once that event has completed).
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  uint64_t last_use = 0;
+};
+
+// One probed launch of the timing hook.
+struct LaunchRecord {
+  int step, kernel, m, n, k, copies, sa, sb, sc;
+  double flops, bytes;
 };
 
 }  // namespace rqc
@@ -84,18 +102,21 @@ struct rqc_plan {
   int64_t inv_exp_off = 0;              // bytes: int32 exponent per node
   int64_t inv_bytes = 0;
   int scale_bias = 0;
+  uint64_t scale_bias_from = 0;         // first bitstring whose groups get the bias
   // Per-step descriptor templates (layout only) and chosen kernels.
   std::vector<rqc::StepDesc> tmpl, tmpl_lp;  // FP32 and reduced precision
   std::vector<int> kern, kern_lp;
-  // Timing probe: events around launches of one kernel kind.
+  // Timing probe: events around launches of one kernel kind (or of all).
   int timing_kernel = -1;
   int group_limit_s = 0, group_limit_b = 0;  // 0: bounded by the workspace only
   std::vector<hipEvent_t> tev;          // pairs (start, stop)
-  std::vector<double> tflops, tbytes;   // per probed launch
+  std::vector<rqc::LaunchRecord> trec;  // per probed launch
+  std::vector<double> tms;              // per probed launch, after the report
   rqc_timing last_timing{};
   // Caches.
   std::map<std::tuple<int, int, int>, rqc::GroupLayout> layouts;
-  std::map<rqc::GraphKey, hipGraphExec_t> graphs;
+  std::map<rqc::GraphKey, rqc::GraphEntry> graphs;
+  uint64_t graph_clock = 0;
   hipStream_t capture_stream = nullptr;
   rqc::PendingRun pending;
   ~rqc_plan();
@@ -109,9 +130,10 @@ const GroupLayout& group_layout(rqc_plan* p, int prec, int gs, int gb);
 WsLayout ws_layout(rqc_plan* p, const GroupLayout& L, uint64_t n_ids, uint64_t n_batch);
 // Enqueue a contraction call on `s` (one graph launch); `run` keeps what the
 // report needs.
+// direct: launch on `s` without capturing or caching a graph.
 void contract(rqc_plan* p, const uint64_t* ids, uint64_t n_ids, const uint8_t* bits,
               uint64_t n_batch, int prec, void* ws, size_t ws_bytes, double* out,
-              double* per_slice, hipStream_t s, PendingRun& run);
+              double* per_slice, hipStream_t s, PendingRun& run, bool direct = false);
 // Synchronise `s`, re-run flagged slices in FP32, fill the report.
 void report(rqc_plan* p, PendingRun& run, hipStream_t s, rqc_run_report* r);
 
@@ -122,5 +144,14 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
                         const std::vector<int>& lc, int& kernel);
 
 void hip_check(hipError_t e, const char* what);
+
+// Destroy every cached graph exec of the plan, each after its last launch
+// has completed.
+void clear_graphs(rqc_plan* p);
+
+// Timing probe kinds: a kernel kind, or every step launch.
+constexpr int kTimeAll = 4;
+// Cached graph execs per plan.
+constexpr size_t kMaxGraphs = 32;
 
 }  // namespace rqc

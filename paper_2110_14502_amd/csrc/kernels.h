@@ -111,6 +111,10 @@ hipError_t launch_slice_sum(const void* root, int root_store, const int32_t* roo
                             const int32_t* flags, double* out, double* per_slice,
                             int64_t ps_row0, int64_t n_batch_total, int64_t b0, int first,
                             hipStream_t s);
+// FP64 statistics of an amplitude batch: out[0] = sum |a|^2, out[1] = sum
+// |a|^4, out[2..4] the linear cross-entropy values (see rqc_batch_xeb).
+hipError_t launch_batch_stats(const double* amps, uint64_t n, int n_qubits, const uint64_t* samples,
+                              uint64_t n_samples, double* out, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 hipError_t launch_add_f64(double* dst, const double* src, int64_t n, hipStream_t s);

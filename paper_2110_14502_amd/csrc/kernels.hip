@@ -269,3 +269,71 @@ hipError_t launch_permute(const void* in, void* out, int rank, const int8_t* src
 }
 
 }  // namespace rqc
+
+namespace rqc {
+
+// ---------------------------------------------------------------------------
+// Statistics of an amplitude batch in FP64 (one workgroup, fixed summation
+// order, so the result does not depend on timing): sum |a|^2, sum |a|^4, and
+// the linear cross-entropy values derived from them; optionally the mean
+// |a|^2 over sampled entries of the batch (bounds-checked: an index outside
+// the batch makes that result NaN).
+// ---------------------------------------------------------------------------
+constexpr int kStatThreads = 1024;
+
+__global__ __launch_bounds__(kStatThreads) void k_batch_stats(const double* amps, uint64_t n,
+                                                               double dim, const uint64_t* samples,
+                                                               uint64_t n_samples, double* out) {
+  __shared__ double r1[kStatThreads], r2[kStatThreads], r3[kStatThreads];
+  __shared__ int bad_any[kStatThreads];
+  const int t = threadIdx.x;
+  double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int bad = 0;
+  for (uint64_t i = t; i < n; i += kStatThreads) {
+    const double re = amps[2 * i], im = amps[2 * i + 1];
+    const double p = re * re + im * im;
+    s1 += p;
+    s2 += p * p;
+  }
+  for (uint64_t j = t; j < n_samples; j += kStatThreads) {
+    const uint64_t i = samples[j];
+    if (i >= n) {
+      bad = 1;
+      continue;
+    }
+    const double re = amps[2 * i], im = amps[2 * i + 1];
+    s3 += re * re + im * im;
+  }
+  r1[t] = s1;
+  r2[t] = s2;
+  r3[t] = s3;
+  bad_any[t] = bad;
+  __syncthreads();
+  for (int w = kStatThreads / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      r1[t] += r1[t + w];
+      r2[t] += r2[t + w];
+      r3[t] += r3[t + w];
+      bad_any[t] |= bad_any[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double sum_p = r1[0], sum_p2 = r2[0];
+    out[0] = sum_p;
+    out[1] = sum_p2;
+    out[2] = n ? dim * sum_p / (double)n - 1.0 : 0.0;  // all entries taken as samples
+    out[3] = sum_p > 0.0 ? dim * sum_p2 / sum_p - 1.0 : 0.0;  // entries drawn with p = |a|^2
+    out[4] = n_samples == 0 ? 0.0
+             : (bad_any[0] ? __builtin_nan("") : dim * r3[0] / (double)n_samples - 1.0);
+  }
+}
+
+hipError_t launch_batch_stats(const double* amps, uint64_t n, int n_qubits, const uint64_t* samples,
+                              uint64_t n_samples, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_stats, dim3(1), dim3(kStatThreads), 0, s, amps, n,
+                     ldexp(1.0, n_qubits), samples, n_samples, out);
+  return hipGetLastError();
+}
+
+}  // namespace rqc

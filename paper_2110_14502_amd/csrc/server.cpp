@@ -224,7 +224,7 @@ bool rqc_server::admit_one() {
       requeue();
       return false;
     }
-    if (rqc_plan_bind(p, res, rb, streams[0]) != RQC_OK) {
+    if (rqc_plan_bind_memory(p, res, rb, streams[0]) != RQC_OK) {
       pool.free(res);
       rqc_plan_destroy(p);
       for (auto& r : batch) fail(r, RQC_EDEVICE);

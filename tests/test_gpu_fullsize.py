@@ -1,8 +1,10 @@
 """Full-size checks of the benchmark workload: the 6x6 (1+14+1) circuit with
 64 open-qubit amplitudes and 8 sliced wires (256 slices).
 
-The oracle cannot contract one of its 256 slices in seconds (about 2^37
-complex multiply-adds each), so the full size is covered by:
+* The benchmarked plan's amplitudes in FP32, FP16 and BF16 against the
+  stored oracle values (tests/golden/config2_amplitudes.txt: the oracle's
+  complex128 sum over the 256 slices of the same slicing, cross-checked
+  against a second order and slicing);
 * element-by-element parity on sub-slices of the same circuit: the slicing
   refined to 24 fixed wires makes each sub-slice cheap for the oracle;
 * the plan's densest step at its real shape and layouts, checked on sampled
@@ -19,13 +21,16 @@ import pytest
 
 import rqcgen
 import oracle
+from golden_io import read_golden
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 R = pytest.importorskip("paper_2110_14502_amd")
 
-ROWS, COLS, DEPTH, SEED, N_OPEN, N_SLICED, TRIALS, PLAN_SEED = 6, 6, 14, 2, 6, 8, 4096, 2
+# The benchmarked plan: planner seed 42, 1024 path trials (the cheapest by
+# the planner's cost among seeds 2..257, and the one the benchmark picks).
+ROWS, COLS, DEPTH, SEED, N_OPEN, N_SLICED, TRIALS, PLAN_SEED = 6, 6, 14, 2, 6, 8, 1024, 42
 N = ROWS * COLS
 OPEN = list(range(N - N_OPEN, N))
 
@@ -107,14 +112,30 @@ def test_fullsize_closed_entry_matches_open_batch(workload):
     assert abs(a - amps[j]) * 2 ** (N / 2) < 1e-4
 
 
+def test_fullsize_fp32_vs_oracle_golden(workload):
+    _, _, _, plan, amps = workload
+    _say("fullsize fp32 vs oracle")
+    idx, ref = read_golden("config2_amplitudes.txt")
+    assert list(idx) == list(range(1 << N_OPEN))
+    assert oracle.normalized_error(amps, ref, N) < 1e-4
+    assert oracle.linear_fidelity(amps, ref) > 0.999999
+
+
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
-def test_fullsize_reduced_precision_vs_fp32(workload, prec):
+def test_fullsize_reduced_precision_vs_oracle_golden(workload, prec):
+    """The benchmarked plan in FP16 / BF16 against the oracle: normalised
+    error <= 2e-2 and linear fidelity >= 0.99; the 16-bit matrix cores run
+    (dense steps) and the error is above the FP32 level."""
     circ, bits, net, plan, amps = workload
-    _say("fullsize", prec)
+    _say("fullsize", prec, "vs oracle")
+    steps = [s for s in plan.steps() if s["depends_on_slice"]]
+    assert sum(s["kernel_lp"] == R.KERN_MFMA16 for s in steps) >= 4
+    _, ref = read_golden("config2_amplitudes.txt")
     lp = R.to_complex(plan.contract(bits, prec=R.PRECISIONS[prec]))[0]
     assert plan.last_report["fp32_reruns"] == 0
-    assert oracle.normalized_error(lp, amps, N) < 2e-2
-    assert oracle.linear_fidelity(lp, amps) > 0.99
+    err = oracle.normalized_error(lp, ref, N)
+    assert 1e-6 < err < 2e-2, err
+    assert oracle.linear_fidelity(lp, ref) > 0.99
 
 
 def test_fullsize_porter_thomas_mean(workload):

@@ -13,6 +13,7 @@ import pytest
 
 import rqcgen
 import oracle
+from plan_order import oracle_order, oracle_wires_and_ids
 
 pytestmark = pytest.mark.gpu
 
@@ -152,13 +153,61 @@ def test_sliced_per_slice_and_sum_fp32():
     assert oracle.normalized_error(amps, full, 25) < 1e-4
 
 
+def _lp_case():
+    """5x5 (1+12+1), four open qubits, four sliced wires, FP16 storage from
+    2^6 and BF16 storage from 2^10 elements per slice (BF16 keeps 8
+    significand bits and rounds more per stored stage; the library default
+    is 2^24): the plan has 16-bit matrix-core steps and 16-bit stored
+    intermediates on the slice-dependent path."""
+    c = rqcgen.grid_rqc(5, 5, 12, 3)
+    openq = [21, 22, 23, 24]
+    P = R.Plan(R.Network(R.Circuit.from_rqcgen(c), openq), n_sliced=4, seed=5, path_trials=64,
+               lp_min_log2=6, bf16_min_log2=10).bind()
+    bits = rqcgen.random_bits(21, 9)
+    e = P.export()
+    groups, pairs = oracle_order(c, openq, e)
+    ow, oids = oracle_wires_and_ids(e, range(16))
+    ref = oracle.slice_values_ordered(c, openq, bits, ow, oids, groups, pairs)
+    return c, P, bits, ref
+
+
+@pytest.fixture(scope="module")
+def lp_case():
+    return _lp_case()
+
+
+def test_lp_case_plan_runs_16_bit_work(lp_case):
+    _, P, _, _ = lp_case
+    st = [s for s in P.steps() if s["depends_on_slice"]]
+    assert sum(s["kernel_lp"] == R.KERN_MFMA16 for s in st) >= 4
+    assert sum(s["lp_output"] for s in st) >= 10
+    assert sum(s["lp_output_bf16"] for s in st) >= 10
+
+
+def test_lp_case_fp32_vs_oracle(lp_case):
+    _say("lp case fp32")
+    _, P, bits, ref = lp_case
+    amps, per = P.contract(bits, per_slice=True)
+    assert oracle.slice_error_natural(R.to_complex(per)[:, 0], ref, 25, 4) < 1e-4
+    assert oracle.normalized_error(R.to_complex(amps)[0], ref.sum(0), 25) < 1e-4
+
+
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
-def test_sliced_reduced_precision(prec):
-    _say("sliced", prec)
-    c, P, bits, amps, per, ref = _sliced_case(R.PRECISIONS[prec])
+def test_lp_case_reduced_precision_vs_oracle(lp_case, prec):
+    """Amplitudes and slices of a plan whose 16-bit paths run, against the
+    oracle: normalised error <= 2e-2, linear fidelity >= 0.99, and above the
+    FP32 level (the 16-bit path ran)."""
+    _say("lp case", prec)
+    _, P, bits, ref = lp_case
+    amps, per = P.contract(bits, prec=R.PRECISIONS[prec], per_slice=True)
+    amps = R.to_complex(amps)[0]
+    per = R.to_complex(per)[:, 0]
     full = ref.sum(0)
-    assert oracle.normalized_error(amps, full, 25) < 2e-2
+    err = oracle.normalized_error(amps, full, 25)
+    assert 1e-6 < err < 2e-2, err
     assert oracle.linear_fidelity(amps, full) > 0.99
+    assert oracle.slice_error_natural(per, ref, 25, 4) < 2e-2
+    assert oracle.linear_fidelity(per, ref) > 0.99
     assert P.last_report["fp32_reruns"] == 0
 
 
@@ -175,6 +224,34 @@ def test_overflow_filter_reruns_in_fp32():
     full = oracle.amplitudes_tn(c, openq, bits)
     assert oracle.normalized_error(amps, full, 25) < 1e-4
     P.set_scale_bias(0)
+
+
+def test_overflow_in_later_bitstring_groups_is_rerun_once():
+    """The filter with one bitstring per group and the overflow forced only
+    from the second bitstring on: the first bitstring keeps its FP16 sum,
+    the others get exactly one FP32 copy of every slice (none is counted
+    twice), and the per-slice rows of the re-run groups are the FP32 ones."""
+    _say("rerun later groups")
+    c, openq, P = _setup(5, 5, 8, 3, 4, n_sliced=3, seed=5, path_trials=32, lp_min_log2=4)
+    bits = np.stack([rqcgen.random_bits(21, s) for s in (9, 10, 11)])
+    P.set_group_limit(0, 1)
+    P.set_scale_bias(40, first_bitstring=1)
+    amps, per = P.contract(bits, prec=R.F16, per_slice=True)
+    assert P.last_report["bits_per_group"] == 1
+    assert P.last_report["fp32_reruns"] == 8
+    amps, per = R.to_complex(amps), R.to_complex(per)
+    wires = P.sliced_wires()
+    for i in range(3):
+        ref = oracle.slice_values_tn(c, openq, bits[i], wires, range(8))
+        full = ref.sum(0)
+        err = oracle.normalized_error(amps[i], full, 25)
+        if i == 0:
+            assert 1e-6 < err < 2e-2, err  # FP16, not re-run
+        else:
+            assert err < 1e-4, (i, err)   # FP32 re-run, added once
+            assert oracle.per_slice_error(per[:, i], ref) < 1e-4
+    P.set_scale_bias(0)
+    P.set_group_limit(0, 0)
 
 
 def test_graph_replay_is_bitwise_identical():

@@ -1,0 +1,176 @@
+"""Kernel-level parity of the 16-bit storage paths (Section 5.5: reduced
+precision; half storage with FP32 arithmetic for memory-bound steps).
+
+Operands are stored as packed (re, im) FP16 or BF16 pairs.  The reference
+is numpy.einsum in complex128 on the operands' stored values (the 16-bit
+values converted exactly), so:
+
+* when every multiplied value is already 16-bit (both operands stored in
+  16 bits), the products are exact in FP32 and only the FP32 accumulation
+  rounds: error <= 2e-5 x RMS, on the 16-bit matrix cores as well as with
+  FP32 arithmetic;
+* when a complex64 operand meets the 16-bit matrix cores it is rounded to
+  16 bits inside the kernel: error at the 16-bit level (FP16 u = 2^-11,
+  BF16 u = 2^-8), bounded by 6e-3 / 4e-2 x RMS and above 1e-6 (the 16-bit
+  products ran);
+* a 16-bit output adds one rounding of the result at the same level.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import rqcgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2110_14502_amd")
+
+LP_TOL = {R.ST_F16: 6e-3, R.ST_BF16: 4e-2}
+TORCH16 = {R.ST_F16: torch.float16, R.ST_BF16: torch.bfloat16}
+MMA = {R.ST_F16: R.F16, R.ST_BF16: R.BF16}
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _store(x, st):
+    """Device tensor of x in storage `st` and the complex128 values it holds."""
+    t = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(x.astype(np.complex64))))
+    if st != R.ST_C64:
+        t = t.to(TORCH16[st])
+    held = t.float().numpy()
+    return t.contiguous().cuda(), held[..., 0].astype(np.float64) + 1j * held[..., 1]
+
+
+def _empty(n, st):
+    dt = torch.float32 if st == R.ST_C64 else TORCH16[st]
+    return torch.empty((n, 2), dtype=dt, device="cuda")
+
+
+def _values(t):
+    h = t.float().cpu().numpy()
+    return h[..., 0].astype(np.float64) + 1j * h[..., 1]
+
+
+def _rel_rms(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.sqrt(np.mean(np.abs(ref) ** 2)))
+
+
+def _plan_layout(m, n, k, seed):
+    """Summed labels lowest in both operands, same order (the planner's
+    layouts); random orders elsewhere."""
+    rng = np.random.default_rng(seed)
+    M, N, K = list(range(m)), list(range(100, 100 + n)), list(range(200, 200 + k))
+    la = [M[i] for i in rng.permutation(m)] + K
+    lb = [N[i] for i in rng.permutation(n)] + K
+    lc = M + N
+    lc = [lc[i] for i in rng.permutation(len(lc))]
+    return la, lb, lc
+
+
+def _run(m, n, k, seed, sa, sb, sc, kernel, batch=1, mma=None):
+    la, lb, lc = _plan_layout(m, n, k, seed)
+    a = rqcgen.random_complex((batch, 1 << (m + k)), seed)
+    b = rqcgen.random_complex(1 << (n + k), seed + 1)
+    A, a_held = _store(a.reshape(-1), sa)
+    B, b_held = _store(b, sb)
+    C = _empty(batch << (m + n), sc)
+    if mma is None:
+        mma = R.F32
+    R.pair_contract_stored(A, B, C, la, lb, lc, sa, sb, sc, kernel, mma_prec=mma, batch=batch,
+                           stride_a=1 << (m + k), stride_b=0, stride_c=1 << (m + n))
+    torch.cuda.synchronize()
+    got = _values(C).reshape(batch, -1)
+    a_held = a_held.reshape(batch, -1)
+    errs = []
+    for i in range(batch):
+        ref = oracle.einsum_step(a_held[i], b_held, la, lb, lc)
+        errs.append(_rel_rms(got[i], ref))
+    return max(errs)
+
+
+LP = [R.ST_F16, R.ST_BF16]
+
+
+@pytest.mark.parametrize("lp", LP)
+def test_rows_kernel_16bit_matrix_cores(lp):
+    """Row-streaming kernel with A stored in 16 bits and sums of 16..64
+    complex values: the 16-bit matrix-core path (16x16x32)."""
+    for (m, n, k, seed) in ((13, 3, 4, 51), (12, 5, 5, 52), (11, 2, 6, 53)):
+        _say("rows 16-bit mma", lp, m, n, k)
+        # both operands 16-bit: exact products, FP32 accumulation
+        err = _run(m, n, k, seed, lp, lp, R.ST_C64, R.KERN_ROWS, batch=2)
+        assert err < 2e-5, (m, n, k, err)
+        # complex64 B rounded to 16 bits in the kernel
+        err = _run(m, n, k, seed, lp, R.ST_C64, R.ST_C64, R.KERN_ROWS)
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+        # 16-bit output
+        err = _run(m, n, k, seed, lp, lp, lp, R.KERN_ROWS)
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+
+
+@pytest.mark.parametrize("lp", LP)
+def test_rows_kernel_half_storage_fp32_arithmetic(lp):
+    """Row-streaming kernel with short sums (k <= 3) on a 16-bit stored A:
+    the values are converted and multiplied in FP32."""
+    for (m, n, k, seed) in ((14, 3, 3, 61), (12, 2, 1, 62), (13, 4, 2, 63), (10, 0, 3, 64)):
+        _say("rows half storage", lp, m, n, k)
+        err = _run(m, n, k, seed, lp, R.ST_C64, R.ST_C64, R.KERN_ROWS, batch=2)
+        assert err < 2e-5, (m, n, k, err)
+
+
+@pytest.mark.parametrize("lp", LP)
+def test_simt_kernel_half_storage_fp32_arithmetic(lp):
+    """Generic kernel on 16-bit stored operands (FP32 arithmetic)."""
+    cases = ((9, 4, 3, 71), (12, 6, 5, 72), (6, 6, 8, 73))
+    for (m, n, k, seed) in cases:
+        _say("simt half storage", lp, m, n, k)
+        for sa, sb in ((lp, R.ST_C64), (R.ST_C64, lp), (lp, lp)):
+            err = _run(m, n, k, seed, sa, sb, R.ST_C64, R.KERN_SIMT)
+            assert err < 2e-5, (m, n, k, sa, sb, err)
+        err = _run(m, n, k, seed, lp, lp, lp, R.KERN_SIMT)
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+
+
+@pytest.mark.parametrize("lp", LP)
+def test_fp32_mfma_kernel_half_storage(lp):
+    """FP32 matrix cores on 16-bit stored operands."""
+    for (m, n, k, seed) in ((9, 7, 4, 81), (10, 6, 6, 82), (8, 8, 8, 83)):
+        _say("mfma32 half storage", lp, m, n, k)
+        err = _run(m, n, k, seed, lp, lp, R.ST_C64, R.KERN_MFMA, batch=2)
+        assert err < 2e-5, (m, n, k, err)
+        err = _run(m, n, k, seed, lp, R.ST_C64, lp, R.KERN_MFMA)
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+
+
+@pytest.mark.parametrize("lp", LP)
+def test_16bit_mfma_kernel_stored_operands(lp):
+    """16-bit matrix cores (32x32x16) on 16-bit stored operands: exact
+    products, FP32 accumulation; and with complex64 operands rounded in
+    the kernel."""
+    for (m, n, k, seed) in ((9, 7, 4, 91), (10, 6, 5, 92), (8, 7, 8, 93)):
+        _say("mfma16 stored", lp, m, n, k)
+        err = _run(m, n, k, seed, lp, lp, R.ST_C64, R.KERN_MFMA16, batch=2, mma=MMA[lp])
+        assert err < 2e-5, (m, n, k, err)
+        err = _run(m, n, k, seed, R.ST_C64, R.ST_C64, R.ST_C64, R.KERN_MFMA16, mma=MMA[lp])
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+        err = _run(m, n, k, seed, lp, lp, lp, R.KERN_MFMA16, mma=MMA[lp])
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+
+
+def test_stored_entry_rejects_unsupported_requests():
+    la, lb, lc = _plan_layout(6, 2, 2, 1)
+    A, _ = _store(rqcgen.random_complex(1 << 8, 1), R.ST_C64)
+    B, _ = _store(rqcgen.random_complex(1 << 4, 2), R.ST_C64)
+    C = _empty(1 << 8, R.ST_C64)
+    with pytest.raises(R.RqcError):   # too small for the FP32 matrix cores
+        R.pair_contract_stored(A, B, C, la, lb, lc, 0, 0, 0, R.KERN_MFMA)
+    with pytest.raises(R.RqcError):   # FP16 and BF16 in one call
+        R.pair_contract_stored(A, B, C, la, lb, lc, R.ST_F16, R.ST_BF16, 0, R.KERN_SIMT)
+    with pytest.raises(R.RqcError):   # 16-bit matrix cores need an MMA type
+        R.pair_contract_stored(A, B, C, la, lb, lc, 0, 0, 0, R.KERN_MFMA16, mma_prec=R.F32)

@@ -250,8 +250,41 @@ def test_metrics():
     assert abs(oracle.normalized_error(ref + 1 / 8, ref, 6) - 1.0) < 1e-15
     assert abs(oracle.linear_fidelity(3j * ref, ref) - 1.0) < 1e-15
     assert oracle.linear_fidelity(np.array([1, 0]), np.array([0, 1])) == 0.0
-    assert abs(oracle.per_slice_error(ref * 1.01, ref) -
-               0.01 * np.max(np.abs(ref)) / np.sqrt(np.mean(np.abs(ref) ** 2))) < 1e-15
+    # Hand-computed values.  ref = (1, 2, 0), got = (1+1j, 2, 0.5):
+    # |got - ref| = (1, 0, 0.5), max 1; RMS(ref) = sqrt(5/3).
+    r3 = np.array([1, 2, 0], dtype=complex)
+    g3 = np.array([1 + 1j, 2, 0.5])
+    assert abs(oracle.per_slice_error(g3, r3) - 0.7745966692414834) < 1e-15  # sqrt(3/5)
+    # Natural scale of a 4-qubit amplitude cut on 2 wires: 2^-3.  A tiny
+    # reference (RMS 1e-30) is measured against it: 0.01 / 0.125.
+    assert oracle.natural_slice_scale(4, 2) == 0.125
+    tiny = np.array([1e-30, -1e-30j])
+    assert abs(oracle.slice_error_natural(tiny + 0.01, tiny, 4, 2) - 0.08) < 1e-15
+    # Above the natural scale it is the error relative to the RMS.
+    assert abs(oracle.slice_error_natural(g3, r3, 4, 2) - 0.7745966692414834) < 1e-15
+    assert abs(oracle.slice_error_natural(g3 * 0.5, r3 * 0.5, 2, 0) - 0.7745966692414834) < 1e-15
+    # With the 2^-(n+S)/2 scale above the RMS: n = 0, S = 0 gives 1.
+    assert abs(oracle.slice_error_natural(r3 * 1e-3 + 1e-3, r3 * 1e-3, 0, 0) - 1e-3) < 1e-15
+
+
+def test_linear_xeb():
+    # Hand-computed: amplitudes (0.6, 0.8) of one qubit, p = (0.36, 0.64).
+    a = np.array([0.6, 0.8j])
+    assert abs(oracle.xeb_ideal_sampling(a, 1) - 0.0784) < 1e-15   # 2 * 0.5392 - 1
+    assert abs(oracle.xeb_of_samples(a, 1, [1, 1, 0]) - 0.09333333333333327) < 1e-15
+    assert abs(oracle.xeb_of_samples(a, 1, [0, 1])) < 1e-15       # every entry once
+    # Uniform amplitudes: 0; a basis state: 2^n - 1.
+    u = np.full(16, 0.25)
+    assert abs(oracle.xeb_ideal_sampling(u, 4)) < 1e-15
+    d = np.zeros(8)
+    d[5] = 1.0
+    assert oracle.xeb_ideal_sampling(d, 3) == 7.0
+    assert oracle.xeb_of_samples(d, 3, [5]) == 7.0
+    # Porter-Thomas (Section 6.2): for a random circuit 2^n sum p^2 is close
+    # to 2, so ideal sampling scores about 1.
+    c = rqcgen.grid_rqc(4, 4, 12, 3)
+    psi = oracle.statevector(c)
+    assert abs(oracle.xeb_ideal_sampling(psi, 16) - 1.0) < 0.1
 
 
 def _random_order(tensors, rng):
