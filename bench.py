@@ -49,7 +49,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", default="amplitudes",
-                    choices=["amplitudes", "steps", "kernel", "serve", "copy", "share"],
+                    choices=["amplitudes", "steps", "kernel", "serve", "copy", "share", "batch"],
                     help="amplitudes: the sliced circuit contraction (default); steps: "
                          "synthetic rank-24..32 pairwise contractions, fused vs permute+GEMM; "
                          "kernel: one plan-shaped contraction repeated; share: one GPU's "
@@ -735,6 +735,61 @@ def share_mode(a):
     print(json.dumps(res), flush=True)
 
 
+def batch_mode(a):
+    """A large correlated batch (Appendix A: fix some qubits, exhaust the
+    rest): the 6x6 (1+12+1) circuit with qubits 15..35 open, 2^21 amplitudes
+    from one sliced contraction, in FP32 and FP16; the linear cross-entropy
+    statistics computed on the device; 64 entries checked against the stored
+    oracle values."""
+    import numpy as np
+    import torch
+    import rqcgen
+    import paper_2110_14502_amd as R
+    torch.cuda.set_device(0)
+    circ = rqcgen.grid_rqc(6, 6, 12, 2)
+    n, n_open = 36, 21
+    openq = list(range(n - n_open, n))
+    bits = rqcgen.random_bits(n - n_open, 3)
+    t = time.perf_counter()
+    plan = R.Plan(R.Network(R.Circuit.from_rqcgen(circ), openq), max_log2_elems=28,
+                  path_trials=128, seed=1).bind("cuda:0")
+    info = plan.info()
+    t_plan = time.perf_counter() - t
+    flops = info["flops_per_slice"] * info["n_slices"] + info["flops_per_bitstring"]
+    pattern = rqcgen.random_bits(15, 4)
+    entries = sum(int(b) << i for i, b in enumerate(pattern)) + (np.arange(64) << 15)
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batch6_amplitudes.txt")
+    if os.path.exists(gpath):
+        golden = read_golden(gpath)[1]
+    res = {"mode": "batch", "n_gpus": 1, "data": "synthetic", "unit": "amplitudes/s",
+           "config": {"workload": "6x6 grid RQC depth 1+12+1, circuit seed 2, qubits 15..35 open "
+                                  "(2^21 amplitudes), qubits 0..14 closed at random_bits(15, 3)",
+                      "n_slices": info["n_slices"], "plan_max_log2_elems": info["max_log2_elems"],
+                      "plan_log2_flops": math.log2(flops), "plan_seconds": round(t_plan, 2)}}
+    for prec in ("f32", "f16"):
+        out = plan.contract(bits, prec=R.PRECISIONS[prec])  # warm (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.reps):
+            out = plan.contract(bits, prec=R.PRECISIONS[prec])
+        torch.cuda.synchronize()
+        secs = (time.perf_counter() - t0) / a.reps
+        st = R.batch_xeb(out, n, samples=torch.from_numpy(entries.astype(np.int64)).cuda())
+        row = {"seconds": secs, "amplitudes_per_s": (1 << n_open) / secs,
+               "tflops": flops / secs / 1e12, "xeb": st,
+               "fp32_reruns": plan.last_report["fp32_reruns"]}
+        if golden is not None:
+            got = R.to_complex(out)[0][entries]
+            row["error_vs_oracle_64"] = _norm_err(got, golden, n)
+            row["fidelity_vs_oracle_64"] = _fidelity(got, golden)
+        res[prec] = row
+        log(f"batch {prec}: {secs:.3f} s, xeb ideal-sampling {st['xeb_ideal_sampling']:.4f}")
+    res["speedup_f16"] = res["f32"]["seconds"] / res["f16"]["seconds"]
+    res["value"] = res["f16"]["amplitudes_per_s"]
+    print(json.dumps(res), flush=True)
+
+
 def copy_mode(a):
     """Plain device copies, reads and writes (calibration of the traffic
     counters and of the achievable HBM rate)."""
@@ -773,6 +828,8 @@ def main():
         return copy_mode(a)
     if a.mode == "share":
         return share_mode(a)
+    if a.mode == "batch":
+        return batch_mode(a)
     import numpy as np
     import torch
     import rqcgen

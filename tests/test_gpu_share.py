@@ -6,12 +6,25 @@ oracle's work to seconds per slice.)
 
 The oracle's own greedy order does not fit in memory on this network, so it
 contracts its own gate tensors in the plan's order given as data (the order
-changes cost, never the value).  Checked:
-* 4 of the slices against the oracle;
-* 32 checked slices, FP16 and BF16 against FP32 within the reduced-precision
-  tolerance;
+changes cost, never the value).  Its values for all 256 slices are stored
+(tests/golden/share4_slices.txt, written by an oracle-only script along the
+committed order fixture share4_order.json, which is this test's plan).
+Checked:
+* all 256 slices in FP32, and 32 checked slices in FP16 and BF16, against
+  the stored oracle values;
 * sub-slices of the 32 checked slices (up to 40 more wires fixed, half of
   them drawn at random) against the oracle.
+
+The error unit is the natural size of one slice, 2^-(n+S)/2 for S sliced
+wires in all (oracle.slice_error_natural).  The slices of this share cancel
+far below that size: the oracle's values are about 1e-57 against a natural
+6.5e-41, and a complex64 contraction with power-of-two normalisation of
+every intermediate (the GPU's FP32 path, emulated on the CPU) returns them
+to about 1e-50, i.e. with relative errors of 1e7-1e8.  Relative errors and
+linear fidelity on these slices therefore measure rounding noise of any
+finite precision, FP32 included; fidelity >= 0.99 is asserted where the
+values are well-conditioned (the 6x6 amplitude batches, the 2^21 batch and
+the 16-bit plan of the parity tests).
 """
 import sys
 
@@ -20,6 +33,7 @@ import pytest
 
 import rqcgen
 import oracle
+from golden_io import GOLDEN, read_golden
 from plan_order import oracle_order, oracle_wires_and_ids
 
 pytestmark = pytest.mark.gpu
@@ -58,16 +72,20 @@ def _wires(plan):
 
 
 def _err(got, ref, plan):
-    """Per-slice error over the checked slices, in units of the larger of
-    their RMS and the natural scale of one slice, 2^-(n+S)/2 (S sliced wires
-    in all: 2^S slices of random phase summing to an amplitude of RMS size
-    2^-n/2).  Some slices cancel to values many orders below that scale,
-    where FP32 returns its rounding noise; that noise is negligible at the
-    natural scale, and measured against it."""
+    """Per-slice error in units of the larger of the slices' RMS and the
+    natural size of one slice (oracle.slice_error_natural)."""
     n_sliced = len(plan.sliced_wires()) + len(plan.fixed_wires())
-    natural = 2.0 ** (-(N + n_sliced) / 2)
-    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
-    return np.max(np.abs(got - ref)) / max(rms, natural)
+    return oracle.slice_error_natural(got, ref, N, n_sliced)
+
+
+def _golden_matches(plan):
+    """The stored values are for this plan's slicing: same enumerated,
+    fixed and pruned wires as the order fixture."""
+    import json
+    with open(f"{GOLDEN}/share4_order.json") as f:
+        fx = json.load(f)
+    e = plan.export()
+    return all(e[k] == fx[k] for k in ("sliced_wires", "fixed_wires", "pruned_wires"))
 
 
 def test_share_values_are_finite_and_not_all_zero(share):
@@ -78,30 +96,25 @@ def test_share_values_are_finite_and_not_all_zero(share):
 
 
 def test_share_slices_vs_oracle(share):
-    circ, bits, _, plan, _, per32, checked = share
+    _, _, _, plan, _, per32, _ = share
     _say("share slices vs oracle")
-    e = plan.export()
-    groups, pairs = oracle_order(circ, [], e)
-    ids = checked[:4]
-    ow, oids = oracle_wires_and_ids(e, ids)
-    ref = oracle.slice_values_ordered(circ, [], bits, ow, oids, groups, pairs)[:, 0]
-    assert _err(per32[ids], ref, plan) < 1e-4
+    assert _golden_matches(plan)
+    idx, ref = read_golden("share4_slices.txt")
+    assert list(idx) == list(range(256))
+    assert _err(per32, ref, plan) < 1e-4
 
 
-# FP16 meets the reduced-precision bound per slice.  BF16 keeps 8
-# significand bits: on these slices, whose values are far smaller than the
-# terms that cancel to form them, its per-slice error measured 0.02-0.05;
-# the bound states that, and the fidelity bound is the same for both.
-@pytest.mark.parametrize("prec,tol", [("f16", 2e-2), ("bf16", 6e-2)])
-def test_share_reduced_precision_vs_fp32(share, prec, tol):
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_share_reduced_precision_vs_oracle(share, prec):
     _, bits, _, plan, ws, per32, checked = share
-    _say("share", prec)
+    _say("share", prec, "vs oracle")
+    assert _golden_matches(plan)
+    _, ref = read_golden("share4_slices.txt")
     _, per = plan.contract(bits, per_slice=True, prec=R.PRECISIONS[prec], workspace=ws)
     lp = R.to_complex(per)[:, 0, 0]
     assert np.all(np.isfinite(lp))
-    assert _err(lp[checked], per32[checked], plan) < tol
-    if np.sqrt(np.mean(np.abs(per32[checked]) ** 2)) > 2.0 ** (-(N + len(plan.sliced_wires()) + len(plan.fixed_wires())) / 2):
-        assert oracle.linear_fidelity(lp[checked], per32[checked]) > 0.99
+    assert plan.last_report["fp32_reruns"] == 0
+    assert _err(lp[checked], ref[checked], plan) < 2e-2
 
 
 def test_share_subslices_vs_oracle(share):
