@@ -294,6 +294,25 @@ rqc_status rqc_permute(const int32_t* labels_in, const int32_t* labels_out,
 rqc_status rqc_cgemm(int64_t M, int64_t N, int64_t K, const void* A,
                      const void* B, void* C, rqc_stream stream);
 
+/* rqc_contract for callers that cannot allocate device memory (code under a
+ * HIP graph capture of their own, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments and results as rqc_contract without the
+ * workspace: the call's workspace lives in a static device array of
+ * rqc_contract_noalloc_scratch_bytes() bytes (256 MiB) that each GPU the
+ * library runs on holds until the process ends; its address is looked up
+ * once per device.  The kernels are launched directly on `stream` (no graph
+ * is captured or cached).  EHBM, before anything is launched, when even one
+ * slice and one bitstring at a time do not fit the scratch.  Every call on a
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (other streams or threads, including the FP32
+ * re-run inside rqc_contract_status) race and must be serialised by the
+ * caller.  Complete each call with rqc_contract_status before the next. */
+rqc_status rqc_contract_noalloc(rqc_plan* p, const uint64_t* slice_ids,
+                                uint64_t n_ids, const uint8_t* closed_bits,
+                                uint64_t n_batch, int32_t prec, double* out,
+                                double* per_slice, rqc_stream stream);
+uint64_t rqc_contract_noalloc_scratch_bytes(void);
+
 /* ---- large correlated batches: linear cross-entropy ------------------- */
 
 /* Statistics of an amplitude batch of an n_qubits circuit, in FP64 on the

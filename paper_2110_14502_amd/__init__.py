@@ -139,6 +139,9 @@ _PROTOS = {
                                C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P]),
     "rqc_permute": (_S, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, _P, _P, _P]),
     "rqc_batch_xeb": (_S, [_P, C.c_uint64, C.c_int32, _P, C.c_uint64, _P, _P]),
+    "rqc_contract_noalloc": (_S, [_P, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint8),
+                                  C.c_uint64, C.c_int32, _P, _P, _P]),
+    "rqc_contract_noalloc_scratch_bytes": (C.c_uint64, []),
     "rqc_cgemm": (_S, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P]),
     "rqc_server_create": (_S, [C.POINTER(rqc_server_opts), C.POINTER(_P)]),
     "rqc_server_submit": (_S, [_P, C.POINTER(rqc_request), C.POINTER(C.c_uint64)]),
@@ -379,6 +382,41 @@ class Plan:
         _check(_lib.rqc_contract(self.h, idp, n_ids, bits.ctypes.data_as(C.POINTER(C.c_uint8)),
                                  n_batch, prec, _ptr(workspace), workspace.numel(), _ptr(out),
                                  _ptr(ps) if ps is not None else None, _stream_handle(stream)))
+        self.last_report = None
+        if sync:
+            self.last_report = self.report(stream)
+        amps = out.view(n_batch, -1, 2)
+        if per_slice:
+            return amps, ps.view(-1, n_batch, 1 << len(self.open), 2)
+        return amps
+
+    def contract_noalloc(self, closed_bits, slice_ids=None, prec=F32, per_slice=False,
+                         stream=None, sync=True, out=None):
+        """contract() through rqc_contract_noalloc: the workspace is the
+        library's static per-device scratch (no workspace argument).  Calls
+        on one GPU must not overlap."""
+        import torch
+        bits = np.ascontiguousarray(np.asarray(closed_bits, dtype=np.uint8))
+        if bits.ndim == 1:
+            bits = bits.reshape(1, -1)
+        n_batch = bits.shape[0]
+        prec = PRECISIONS.get(prec, prec) if isinstance(prec, str) else int(prec)
+        ids = None if slice_ids is None else np.ascontiguousarray(np.asarray(slice_ids, dtype=np.uint64))
+        n_ids = 0 if ids is None else ids.size
+        n_out = n_batch * (1 << len(self.open))
+        dev = self._resident.device if self._resident is not None else \
+            torch.device("cuda", torch.cuda.current_device())
+        if out is None:
+            out = torch.empty(2 * n_out, dtype=torch.float64, device=dev)
+        ps = None
+        if per_slice:
+            cnt = n_ids if ids is not None else self.info()["n_slices"]
+            ps = torch.zeros(2 * n_out * cnt, dtype=torch.float64, device=dev)
+        idp = ids.ctypes.data_as(C.POINTER(C.c_uint64)) if ids is not None else None
+        _check(_lib.rqc_contract_noalloc(self.h, idp, n_ids,
+                                         bits.ctypes.data_as(C.POINTER(C.c_uint8)), n_batch, prec,
+                                         _ptr(out), _ptr(ps) if ps is not None else None,
+                                         _stream_handle(stream)))
         self.last_report = None
         if sync:
             self.last_report = self.report(stream)

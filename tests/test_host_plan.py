@@ -24,7 +24,8 @@ def _plan(rows, cols, depth, cseed, n_open, **kw):
 
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "rqc.h")).read()
-    declared = set(re.findall(r"^\s*(?:rqc_status|void|const char\*)\s+(rqc_\w+)\s*\(", header, re.M))
+    declared = set(re.findall(r"^\s*(?:rqc_status|void|uint64_t|const char\*)\s+(rqc_\w+)\s*\(",
+                              header, re.M))
     assert declared, "no declarations parsed"
     for name in declared:
         assert hasattr(R._lib, name), name
