@@ -44,47 +44,6 @@ __device__ __forceinline__ uint32_t pack_lp<ST_BF16>(float2 v) {
   return __builtin_bit_cast(uint32_t, o);
 }
 
-// Load one operand element as a packed low-precision complex word.
-template <int LP, int S>
-__device__ __forceinline__ uint32_t load_lp(const void* p, int64_t i, int pre) {
-  if (S == LP) return reinterpret_cast<const uint32_t*>(p)[i];
-  float2 v = load_c<S>(p, i);
-  if (pre) {
-    v.x = ldexpf(v.x, pre);
-    v.y = ldexpf(v.y, pre);
-  }
-  return pack_lp<LP>(v);
-}
-
-// Four consecutive operand elements (16 bytes of packed words in 16-bit
-// storage, 32 bytes of complex64) as packed low-precision words.
-template <int LP, int S>
-__device__ __forceinline__ uint4 load_lp4(const void* p, int64_t i, int pre) {
-  if (S == LP) return *reinterpret_cast<const uint4*>(reinterpret_cast<const uint32_t*>(p) + i);
-  float2 v[4];
-  if (S == ST_C64) {
-    const float4* q = reinterpret_cast<const float4*>(reinterpret_cast<const float2*>(p) + i);
-    const float4 x = q[0], y = q[1];
-    v[0] = make_float2(x.x, x.y);
-    v[1] = make_float2(x.z, x.w);
-    v[2] = make_float2(y.x, y.y);
-    v[3] = make_float2(y.z, y.w);
-  } else {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = load_c<S>(p, i + t);
-  }
-  uint32_t w[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (pre) {
-      v[t].x = ldexpf(v[t].x, pre);
-      v[t].y = ldexpf(v[t].y, pre);
-    }
-    w[t] = pack_lp<LP>(v[t]);
-  }
-  return make_uint4(w[0], w[1], w[2], w[3]);
-}
-
 template <int LP>
 __device__ __forceinline__ floatx16 mfma16(u32x4 a, u32x4 b, floatx16 c);
 template <>
@@ -210,43 +169,87 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
     return r;
   };
 
-  uint32_t ra[16], rb[8];
+  // A chunk in flight is kept raw in registers: 16-bit stored operands as
+  // their packed words, complex64 operands as their float pairs.  The
+  // conversion to packed 16-bit words (with the copy's power-of-two
+  // pre-scale) happens only when the chunk is written to LDS, so issuing the
+  // next chunk's loads never waits for their data.  (The scalar-load path of
+  // other layouts converts at load time: its raw chunk would not fit the
+  // register budget.)
+  constexpr int EA = (VEC && SA != LP) ? 2 : 1, EB = (VEC && SB != LP) ? 2 : 1;  // words per element
+  constexpr int WA = (VEC ? 4 * NA : NA) * EA, WB = (VEC ? 4 * NB : NB) * EB;
+  uint32_t ra[WA], rb[WB];
   auto load_chunk = [&](int64_t oA, int64_t oB, int kc, int pA, int pB) {
     int64_t kA, kB;
     k_offsets(d, ot, kc, kA, kB);
+    const uint32_t* pa = reinterpret_cast<const uint32_t*>(d.A);
+    const uint32_t* pb = reinterpret_cast<const uint32_t*>(d.B);
     if (VEC) {
 #pragma unroll
-      for (int j = 0; j < NA; ++j) {
-        const uint4 v = load_lp4<LP, SA>(d.A, oA + kA + gA[j], pA);
-        ra[4 * j] = v.x, ra[4 * j + 1] = v.y, ra[4 * j + 2] = v.z, ra[4 * j + 3] = v.w;
-      }
+      for (int j = 0; j < NA; ++j)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const uint4 v = load_lp4<LP, SB>(d.B, oB + kB + gB[j], pB);
-        rb[4 * j] = v.x, rb[4 * j + 1] = v.y, rb[4 * j + 2] = v.z, rb[4 * j + 3] = v.w;
-      }
+        for (int h = 0; h < EA; ++h) {
+          const uint4 v = *reinterpret_cast<const uint4*>(pa + EA * (oA + kA + gA[j]) + 4 * h);
+          ra[(4 * j + 0) * EA + 4 * h + 0] = v.x;
+          ra[(4 * j + 0) * EA + 4 * h + 1] = v.y;
+          ra[(4 * j + 0) * EA + 4 * h + 2] = v.z;
+          ra[(4 * j + 0) * EA + 4 * h + 3] = v.w;
+        }
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int h = 0; h < EB; ++h) {
+          const uint4 v = *reinterpret_cast<const uint4*>(pb + EB * (oB + kB + gB[j]) + 4 * h);
+          rb[(4 * j + 0) * EB + 4 * h + 0] = v.x;
+          rb[(4 * j + 0) * EB + 4 * h + 1] = v.y;
+          rb[(4 * j + 0) * EB + 4 * h + 2] = v.z;
+          rb[(4 * j + 0) * EB + 4 * h + 3] = v.w;
+        }
     } else {
+      auto one = [&](const void* p, int64_t i, bool lp, int pre) -> uint32_t {
+        if (lp) return reinterpret_cast<const uint32_t*>(p)[i];
+        float2 v = reinterpret_cast<const float2*>(p)[i];
+        if (pre) {
+          v.x = ldexpf(v.x, pre);
+          v.y = ldexpf(v.y, pre);
+        }
+        return pack_lp<LP>(v);
+      };
 #pragma unroll
-      for (int j = 0; j < NA; ++j) ra[j] = load_lp<LP, SA>(d.A, oA + kA + gA[j], pA);
+      for (int j = 0; j < NA; ++j) ra[j] = one(d.A, oA + kA + gA[j], SA == LP, pA);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) rb[j] = load_lp<LP, SB>(d.B, oB + kB + gB[j], pB);
+      for (int j = 0; j < NB; ++j) rb[j] = one(d.B, oB + kB + gB[j], SB == LP, pB);
     }
   };
-  auto store_chunk = [&](int buf) {
+  // Packed word of raw element i of a register array (E words per element).
+  auto word = [&](const uint32_t* r, int E, int i, int pre) -> uint32_t {
+    if (E == 1) return r[i];
+    float2 v = make_float2(__uint_as_float(r[2 * i]), __uint_as_float(r[2 * i + 1]));
+    if (pre) {
+      v.x = ldexpf(v.x, pre);
+      v.y = ldexpf(v.y, pre);
+    }
+    return pack_lp<LP>(v);
+  };
+  auto store_chunk = [&](int buf, int pA, int pB) {
     uint32_t* An = Abuf + buf * kLABuf;
     uint32_t* Bn = Bbuf + buf * kLBBuf;
     if (VEC) {
 #pragma unroll
       for (int j = 0; j < NA; ++j)
-        *reinterpret_cast<uint4*>(An + lA[j]) = make_uint4(ra[4 * j], ra[4 * j + 1], ra[4 * j + 2], ra[4 * j + 3]);
+        *reinterpret_cast<uint4*>(An + lA[j]) =
+            make_uint4(word(ra, EA, 4 * j, pA), word(ra, EA, 4 * j + 1, pA),
+                       word(ra, EA, 4 * j + 2, pA), word(ra, EA, 4 * j + 3, pA));
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        *reinterpret_cast<uint4*>(Bn + lB[j]) = make_uint4(rb[4 * j], rb[4 * j + 1], rb[4 * j + 2], rb[4 * j + 3]);
+        *reinterpret_cast<uint4*>(Bn + lB[j]) =
+            make_uint4(word(rb, EB, 4 * j, pB), word(rb, EB, 4 * j + 1, pB),
+                       word(rb, EB, 4 * j + 2, pB), word(rb, EB, 4 * j + 3, pB));
     } else {
 #pragma unroll
-      for (int j = 0; j < NA; ++j) An[lA[j]] = ra[j];
+      for (int j = 0; j < NA; ++j) An[lA[j]] = word(ra, EA, j, pA);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) Bn[lB[j]] = rb[j];
+      for (int j = 0; j < NB; ++j) Bn[lB[j]] = word(rb, EB, j, pB);
     }
   };
 
@@ -276,7 +279,7 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
     outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
     ncs = copy_scale(js, jb);
     load_chunk(oA, oB, 0, ncs.pA, ncs.pB);
-    store_chunk(0);
+    store_chunk(0, ncs.pA, ncs.pB);
   }
   __syncthreads();
   for (; t < n_items; t += G) {
@@ -335,7 +338,7 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
         acc[1][0] = mfma16<LP>(a1, b0, acc[1][0]);
         acc[1][1] = mfma16<LP>(a1, b1, acc[1][1]);
       }
-      if (more) store_chunk(cb ^ 1);
+      if (more) store_chunk(cb ^ 1, cs.pA, cs.pB);
       __syncthreads();
     }
 
@@ -362,7 +365,7 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
       __syncthreads();
     }
     if (next_tile) {
-      store_chunk(0);
+      store_chunk(0, ncs.pA, ncs.pB);
       __syncthreads();
     }
   }
