@@ -107,6 +107,8 @@ def parse():
     ap.add_argument("--graph-steps", type=int, default=1)
     ap.add_argument("--lp-steps", type=int, default=1,
                     help="timed steps of the reduced-precision (f16) comparison, 0 = skip")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="per-step kernel tuning of the benchmarked plan before timing (1 = on)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline sample, 0 = skip")
     return ap.parse_args()
@@ -425,14 +427,24 @@ def kernel_mode(a):
     C = torch.empty(a.batch << (m + n), dtype=torch.complex64, device="cuda")
     res = {"mode": "kernel", "m": m, "n": n, "k": k, "batch": a.batch, "prec": a.kprec}
     kp = R.PRECISIONS[a.kprec]
+    fl = 8.0 * a.batch * 2.0 ** (m + n + k)
+    by = 8.0 * a.batch * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n))
+    if kp == R.F32 and m >= 7 and n >= 6 and k >= 4:
+        # FP32 matrix-core variants: 3M / 4M products, per-tile / persistent.
+        for var, name in ((0, "3m_auto"), (1, "4m_auto"), (2, "3m_tiles"), (3, "4m_tiles"),
+                          (4, "3m_persistent"), (5, "4m_persistent")):
+            ms = _events_time(lambda: R.pair_contract_stored(
+                A, B, C, la, lb, lc, R.ST_C64, R.ST_C64, R.ST_C64, R.KERN_MFMA, batch=a.batch,
+                stride_a=1 << (m + k), stride_b=1 << (n + k), stride_c=1 << (m + n), variant=var),
+                a.reps)
+            res[name] = {"ms": ms, "tflops": fl / ms / 1e9, "gbs": by / ms / 1e6}
+            log(f"variant {name}: {ms:.3f} ms, {fl / ms / 1e9:.1f} TFLOP/s")
     for kern in (-1, 0):
         ms = _events_time(lambda: R.pair_contract(A, B, la, lb, lc, C_out=C, kernel=kern,
                                                   batch=a.batch, stride_a=1 << (m + k),
                                                   stride_b=1 << (n + k), stride_c=1 << (m + n),
                                                   prec=kp),
                           a.reps)
-        fl = 8.0 * a.batch * 2.0 ** (m + n + k)
-        by = 8.0 * a.batch * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n))
         res["auto" if kern < 0 else "generic"] = {"ms": ms, "tflops": fl / ms / 1e9,
                                                  "gbs": by / ms / 1e6}
         log(f"kernel {kern}: {ms:.3f} ms, {fl / ms / 1e9:.1f} TFLOP/s")
@@ -860,6 +872,12 @@ def main():
     ws_bytes = int(min(pref, max(lo, a.ws_fraction * free)))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda:0")
     out = torch.empty(2 << a.open, dtype=torch.float64, device="cuda:0")
+    tune = None
+    if a.tune:
+        t0 = time.perf_counter()
+        tune = plan.autotune(prec, n_ids=len(ids) if ids else 0, workspace=ws)
+        tune["seconds"] = round(time.perf_counter() - t0, 2)
+        log(f"autotune {a.prec}: {tune}")
     def step(p, tag):
         ts = time.perf_counter()
         plan.contract(bits, slice_ids=ids, prec=p, workspace=ws, out=out, sync=False)
@@ -933,6 +951,7 @@ def main():
         "roofline": roofline(dom, tim, a, step_flops * frac * a.steps, kind_ms),
         "roofline_by_kernel": by_kind,
         "launch_table": table,
+        "autotune": tune,
     }
     golden = None
     if (a.rows, a.cols, a.depth, a.seed, a.open, ids) == (6, 6, 14, 2, 6, None) and \
@@ -972,6 +991,11 @@ def main():
             log(f"{tag}: {time.perf_counter() - ts:.2f}s (groups of {r['slices_per_group']} slices)")
             return r
 
+        if a.tune:
+            t0 = time.perf_counter()
+            tune16 = lp_plan.autotune(R.F16, n_ids=len(ids) if ids else 0, workspace=ws)
+            tune16["seconds"] = round(time.perf_counter() - t0, 2)
+            log(f"autotune f16: {tune16}")
         step16("f16 warmup")
         lp_plan.set_timing(TIME_ALL)
         step16("f16 probe all kernels")
@@ -993,7 +1017,8 @@ def main():
             "fp32_reruns": rep16["fp32_reruns"],
             "normalized_error_vs_f32": _norm_err(lp_amps, f32_amps, n),
             "fidelity_vs_f32": _fidelity(lp_amps, f32_amps),
-            "roofline_by_kernel": by_kind16, "launch_table": table16}
+            "roofline_by_kernel": by_kind16, "launch_table": table16,
+            "autotune": tune16 if a.tune else None}
         if golden is not None:
             res["reduced_precision"]["error_vs_oracle"] = _norm_err(lp_amps, golden, n)
             res["reduced_precision"]["fidelity_vs_oracle"] = _fidelity(lp_amps, golden)

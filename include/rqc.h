@@ -153,8 +153,11 @@ typedef struct rqc_plan_opts {
  *         per slice;
  *   CALIBRATED: as SIZE, then rqc_plan_calibrate measures each step's
  *         sensitivity on one slice and keeps the most sensitive steps in
- *         complex64 until the estimated error meets the requested bound. */
-enum { RQC_POLICY_SIZE = 0, RQC_POLICY_CALIBRATED = 1 };
+ *         complex64 until the estimated error meets the requested bound;
+ *   STORAGE: 16-bit storage by the size rule, every product in FP32 on the
+ *         converted values (half storage, FP32 arithmetic: halves the bytes
+ *         of memory-bound steps at FP32 rounding of the arithmetic). */
+enum { RQC_POLICY_SIZE = 0, RQC_POLICY_CALIBRATED = 1, RQC_POLICY_STORAGE = 2 };
 
 void rqc_plan_opts_default(rqc_plan_opts* o);
 
@@ -393,6 +396,65 @@ void rqc_server_destroy(rqc_server* s);
 
 /* ---- execution tuning ---------------------------------------------------- */
 
+/* Per-step kernel tuning (Section 5.4 designs a kernel per contraction case;
+ * here the choice per step is measured).  For every step of the plan with
+ * more than one valid (kernel, variant) pair -- the FP32 matrix-core kernel
+ * with three or four real products per complex product, per-tile or
+ * persistent; the row-streaming kernel where its conditions hold -- each
+ * pair is timed with HIP events on `stream` for the group of slices and
+ * bitstrings that a call of n_ids slices (0 = all) and n_batch bitstrings
+ * in precision `prec` gets in this workspace, and the fastest is kept for
+ * that precision.  The workspace (256-byte aligned, at least the call's
+ * minimum) is overwritten; the call synchronises `stream`.  cache_path
+ * (optional, NULL or ""): a text file of "signature kernel variant" lines
+ * (signature: the step's shape and layouts up to renaming of labels, its
+ * operand storage and the group size), read first and rewritten after;
+ * steps found in it are not timed.  Results do not depend on the choices
+ * beyond FP32 rounding. */
+typedef struct rqc_tune_report {
+  int32_t steps;        /* steps with more than one candidate */
+  int32_t timed;        /* of which timed on the device */
+  int32_t cached;       /* of which taken from the cache file */
+  int32_t changed;      /* steps whose choice differs from the previous one */
+  double ms_default;    /* timed steps: summed time of the previous choices */
+  double ms_tuned;      /* timed steps: summed time of the chosen ones */
+} rqc_tune_report;
+
+rqc_status rqc_plan_autotune(rqc_plan* p, int32_t prec, uint64_t n_ids,
+                             uint64_t n_batch, void* workspace, size_t ws_bytes,
+                             const char* cache_path, rqc_stream stream,
+                             rqc_tune_report* out);
+
+/* Precision pre-analysis for RQC_F16 / RQC_BF16 calls (Section 5.5: the
+ * parts of the network near the slice cuts are the most sensitive).  Slice
+ * `slice_id` with closed bits `closed_bits` (host, n_closed bytes) is
+ * contracted in FP32, then once per candidate step (one whose output the size
+ * rule stores in 16 bits, or whose kernel uses the 16-bit matrix cores) with
+ * only that step in reduced precision; its error against the FP32 result,
+ * max |a - a32| / max(RMS(a32), err_floor), is its sensitivity.  Steps are
+ * then put in reduced precision from the least sensitive on while the root
+ * sum of squares of their errors stays <= target_err; the others store
+ * complex64 and multiply in FP32 in calls of precision `prec`.  The whole
+ * assignment is checked on the same slice (dropping the most sensitive kept
+ * step while the measured error is above the target).  err_floor is for
+ * slices whose value cancels far below their natural size (for example
+ * 2^-(n+S)/2 for S sliced wires); 0 measures against the slice's own RMS.
+ * The workspace must hold one slice and one bitstring in FP32 plus
+ * 16 x 2^n_open bytes; it is overwritten, and `stream` is synchronised. */
+typedef struct rqc_calib_report {
+  int32_t candidates;   /* steps whose precision was chosen */
+  int32_t reduced;      /* of which left in reduced precision */
+  double estimated_err; /* root sum of squares of the kept steps' errors */
+  double measured_err;  /* error of the final assignment on the slice */
+  double min_step_err, max_step_err;
+} rqc_calib_report;
+
+rqc_status rqc_plan_calibrate(rqc_plan* p, int32_t prec, uint64_t slice_id,
+                              const uint8_t* closed_bits, double target_err,
+                              double err_floor, void* workspace,
+                              size_t ws_bytes, rqc_stream stream,
+                              rqc_calib_report* out);
+
 /* Upper bounds on the slices and bitstrings contracted side by side in one
  * group (one batched launch per step); 0 = no bound beyond the workspace.
  * Smaller groups keep a group's intermediates within the GPU's last-level
@@ -460,8 +522,11 @@ rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias,
  * uses the 16-bit matrix cores when A is stored in 16 bits and the summed
  * labels fill chunks of 16 or more complex values, FP32 otherwise.  Labels,
  * batching and strides as in rqc_pair_contract; no scaling is applied (the
- * caller keeps values inside the 16-bit range).  EINVAL when the kernel's
- * shape or layout conditions are not met (no fallback). */
+ * caller keeps values inside the 16-bit range).  variant: kernel variant
+ * bits (0 = default; FP32 matrix cores: 1 = four real products per complex
+ * product instead of three, 2 = one tile per workgroup, 4 = persistent
+ * walk).  EINVAL when the kernel's shape or layout conditions are not met
+ * (no fallback). */
 rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
                                     const int32_t* labels_b, int32_t rank_b,
                                     const int32_t* labels_c, int32_t rank_c,
@@ -470,7 +535,8 @@ rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
                                     int32_t store_c, int32_t batch_count,
                                     int64_t stride_a, int64_t stride_b,
                                     int64_t stride_c, int32_t kernel,
-                                    int32_t mma_prec, rqc_stream stream);
+                                    int32_t mma_prec, int32_t variant,
+                                    rqc_stream stream);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,7 @@ OK, EINVAL, ENOMEM, EHBM, EDEVICE, EUNSUPPORTED, ENUMERIC = 0, -1, -2, -3, -4, -
 F32, F16, BF16 = 0, 1, 2
 PRECISIONS = {"f32": F32, "fp32": F32, "f16": F16, "fp16": F16, "bf16": BF16}
 GATE_H, GATE_SQRT_X, GATE_SQRT_Y, GATE_SQRT_W, GATE_FSIM, GATE_U1, GATE_U2 = range(7)
+POLICY_SIZE, POLICY_CALIBRATED, POLICY_STORAGE = 0, 1, 2
 
 
 class RqcError(RuntimeError):
@@ -85,6 +86,17 @@ class rqc_launch_timing(C.Structure):
                 ("k", C.c_int32), ("copies", C.c_int32), ("store_a", C.c_int32),
                 ("store_b", C.c_int32), ("store_c", C.c_int32), ("reserved", C.c_int32),
                 ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+class rqc_tune_report(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("timed", C.c_int32), ("cached", C.c_int32),
+                ("changed", C.c_int32), ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
+
+
+class rqc_calib_report(C.Structure):
+    _fields_ = [("candidates", C.c_int32), ("reduced", C.c_int32),
+                ("estimated_err", C.c_double), ("measured_err", C.c_double),
+                ("min_step_err", C.c_double), ("max_step_err", C.c_double)]
 
 
 class rqc_server_opts(C.Structure):
@@ -157,8 +169,13 @@ _PROTOS = {
     "rqc_pair_contract_stored": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
                                       C.c_int32, C.POINTER(C.c_int32), C.c_int32, _P, _P, _P,
                                       C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
-                                      C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P]),
+                                      C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                      _P]),
     "rqc_plan_set_timing": (_S, [_P, C.c_int32]),
+    "rqc_plan_autotune": (_S, [_P, C.c_int32, C.c_uint64, C.c_uint64, _P, C.c_size_t, C.c_char_p,
+                               _P, C.POINTER(rqc_tune_report)]),
+    "rqc_plan_calibrate": (_S, [_P, C.c_int32, C.c_uint64, C.POINTER(C.c_uint8), C.c_double,
+                                C.c_double, _P, C.c_size_t, _P, C.POINTER(rqc_calib_report)]),
     "rqc_plan_set_group_limit": (_S, [_P, C.c_int32, C.c_int32]),
     "rqc_plan_get_timing": (_S, [_P, C.POINTER(rqc_timing)]),
 }
@@ -425,6 +442,44 @@ class Plan:
             return amps, ps.view(-1, n_batch, 1 << len(self.open), 2)
         return amps
 
+    def _scratch(self, n_ids, n_batch, prec, extra=0):
+        import torch
+        lo, pref = self.workspace_bytes(n_ids, n_batch, prec)
+        have = self._ws.numel() if self._ws is not None else 0
+        if have < lo + extra:
+            self._ws = None
+            free, _ = torch.cuda.mem_get_info(self._resident.device)
+            size = int(min(pref + extra, max(lo + extra, 0.8 * free)))
+            self._ws = torch.empty(size, dtype=torch.uint8, device=self._resident.device)
+        return self._ws
+
+    def autotune(self, prec=F32, n_ids=0, n_batch=1, workspace=None, cache_path=None,
+                 stream=None) -> dict:
+        """Time each step's valid (kernel, variant) pairs for this call shape
+        and keep the fastest (rqc_plan_autotune)."""
+        prec = PRECISIONS.get(prec, prec) if isinstance(prec, str) else int(prec)
+        ws = workspace if workspace is not None else self._scratch(n_ids, n_batch, prec)
+        r = rqc_tune_report()
+        _check(_lib.rqc_plan_autotune(self.h, prec, int(n_ids), int(n_batch), _ptr(ws), ws.numel(),
+                                      cache_path.encode() if cache_path else None,
+                                      _stream_handle(stream), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in rqc_tune_report._fields_}
+
+    def calibrate(self, closed_bits, prec=F16, slice_id=0, target_err=5e-3, err_floor=0.0,
+                  workspace=None, stream=None) -> dict:
+        """Per-step precision assignment from the sensitivity of one slice
+        (rqc_plan_calibrate)."""
+        prec = PRECISIONS.get(prec, prec) if isinstance(prec, str) else int(prec)
+        bits = np.ascontiguousarray(np.asarray(closed_bits, dtype=np.uint8).reshape(-1))
+        extra = 256 + 16 * (1 << len(self.open))
+        ws = workspace if workspace is not None else self._scratch(1, 1, F32, extra)
+        r = rqc_calib_report()
+        _check(_lib.rqc_plan_calibrate(self.h, prec, int(slice_id),
+                                       bits.ctypes.data_as(C.POINTER(C.c_uint8)), float(target_err),
+                                       float(err_floor), _ptr(ws), ws.numel(),
+                                       _stream_handle(stream), C.byref(r)))
+        return {f: getattr(r, f) for f, _ in rqc_calib_report._fields_}
+
     def set_group_limit(self, max_slices=0, max_bits=0):
         """Bound the slices / bitstrings per batched group (0 = workspace only)."""
         _check(_lib.rqc_plan_set_group_limit(self.h, int(max_slices), int(max_bits)))
@@ -479,9 +534,12 @@ ST_C64, ST_F16, ST_BF16 = 0, 1, 2
 KERN_SIMT, KERN_MFMA, KERN_ROWS, KERN_MFMA16 = 0, 1, 2, 3
 
 
+VAR_4M, VAR_TILES, VAR_PERSISTENT = 1, 2, 4
+
+
 def pair_contract_stored(A, B, C_out, labels_a, labels_b, labels_c, store_a, store_b, store_c,
                          kernel, mma_prec=F32, batch=1, stride_a=0, stride_b=0, stride_c=0,
-                         stream=None):
+                         variant=0, stream=None):
     """One contraction with explicit operand storage (ST_*) and kernel
     (KERN_*); A, B, C_out are device tensors holding complex64 or packed
     16-bit (re, im) pairs as their storage code says."""
@@ -490,7 +548,7 @@ def pair_contract_stored(A, B, C_out, labels_a, labels_b, labels_c, store_a, sto
                                          _ptr(B), _ptr(C_out), int(store_a), int(store_b),
                                          int(store_c), int(batch), int(stride_a), int(stride_b),
                                          int(stride_c), int(kernel), int(mma_prec),
-                                         _stream_handle(stream)))
+                                         int(variant), _stream_handle(stream)))
     return C_out
 
 

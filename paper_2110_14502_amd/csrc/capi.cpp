@@ -144,7 +144,8 @@ rqc_status rqc_plan_create(const rqc_network* n, const rqc_plan_opts* opts, rqc_
     po.share_bits.assign(o.share_bits, o.share_bits + o.n_share_bits);
     for (auto& b : po.share_bits)
       if (b > 1) throw rqc::Error{RQC_EINVAL, "share bits must be 0 or 1"};
-    if (o.precision_policy != RQC_POLICY_SIZE && o.precision_policy != RQC_POLICY_CALIBRATED)
+    if (o.precision_policy != RQC_POLICY_SIZE && o.precision_policy != RQC_POLICY_CALIBRATED &&
+        o.precision_policy != RQC_POLICY_STORAGE)
       throw rqc::Error{RQC_EINVAL, "unknown precision policy"};
     po.precision_policy = o.precision_policy;
     rqc::make_plan(p->pd);
@@ -200,12 +201,12 @@ rqc_status rqc_plan_get_step(const rqc_plan* p, int32_t i, rqc_step_info* out) {
   out->m = st.m;
   out->n = st.n;
   out->k = st.k;
-  out->kernel = i < (int)p->kern.size() ? p->kern[i] : -1;
-  out->kernel_lp = i < (int)p->kern_lp.size() ? p->kern_lp[i] : -1;
+  out->kernel = p->sel_kern[RQC_F32][i];
+  out->kernel_lp = p->sel_kern[RQC_F16][i];
   out->depends_on_slice = st.dep_s;
   out->depends_on_bits = st.dep_b;
-  out->lp_output = st.lp;
-  out->lp_output_bf16 = st.lp_bf16;
+  out->lp_output = rqc::step_lp_store(p, RQC_F16, (size_t)i);
+  out->lp_output_bf16 = rqc::step_lp_store(p, RQC_BF16, (size_t)i);
   out->flops = 8.0 * std::ldexp(1.0, st.m + st.n + st.k);
   out->bytes_c64 = 8.0 * (std::ldexp(1.0, st.m + st.k) + std::ldexp(1.0, st.n + st.k) + std::ldexp(1.0, st.m + st.n));
   return RQC_OK;
@@ -302,6 +303,29 @@ rqc_status rqc_plan_set_group_limit(rqc_plan* p, int32_t max_slices, int32_t max
   RQC_CATCH
 }
 
+rqc_status rqc_plan_autotune(rqc_plan* p, int32_t prec, uint64_t n_ids, uint64_t n_batch,
+                             void* workspace, size_t ws_bytes, const char* cache_path,
+                             rqc_stream stream, rqc_tune_report* out) {
+  RQC_TRY
+  if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  rqc::autotune(p, prec, n_ids, n_batch, workspace, ws_bytes, cache_path,
+                static_cast<hipStream_t>(stream), out);
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_plan_calibrate(rqc_plan* p, int32_t prec, uint64_t slice_id,
+                              const uint8_t* closed_bits, double target_err, double err_floor,
+                              void* workspace, size_t ws_bytes, rqc_stream stream,
+                              rqc_calib_report* out) {
+  RQC_TRY
+  if (!p || !out) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  rqc::calibrate(p, prec, slice_id, closed_bits, target_err, err_floor, workspace, ws_bytes,
+                 static_cast<hipStream_t>(stream), out);
+  return RQC_OK;
+  RQC_CATCH
+}
+
 rqc_status rqc_plan_set_timing(rqc_plan* p, int32_t kernel) {
   RQC_TRY
   if (!p) throw rqc::Error{RQC_EINVAL, "NULL plan"};
@@ -391,7 +415,7 @@ rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
                                     const void* B, void* C, int32_t store_a, int32_t store_b,
                                     int32_t store_c, int32_t batch_count, int64_t stride_a,
                                     int64_t stride_b, int64_t stride_c, int32_t kernel,
-                                    int32_t mma_prec, rqc_stream stream) {
+                                    int32_t mma_prec, int32_t variant, rqc_stream stream) {
   RQC_TRY
   if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
   if (rank_a < 0 || rank_b < 0 || rank_c < 0 || rank_a > 40 || rank_b > 40 || rank_c > 40)
@@ -432,6 +456,8 @@ rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
   d.sC_s = stride_c;
   d.gs_c = batch_count;
   d.copies = batch_count;
+  if (variant < 0 || variant > 15) throw rqc::Error{RQC_EINVAL, "variant out of range"};
+  d.variant = variant;
   const int lp_kind = kernel == rqc::KERN_MFMA16 ? (mma_prec == RQC_F16 ? rqc::ST_F16 : rqc::ST_BF16) : 0;
   rqc::hip_check(rqc::launch_step(d, kern, store_a, store_b, store_c, lp_kind,
                                   static_cast<hipStream_t>(stream)),

@@ -264,7 +264,51 @@ size_t resident_bytes(rqc_plan* p) {
     p->tmpl_lp.push_back(make_pair_desc(st.la, st.lb, st.lc, k2));
     p->kern_lp.push_back(k2);
   }
+  for (int m = 0; m < 3; ++m) {
+    p->lp_on[m].assign(pd.steps.size(), m == RQC_F32 ? 0 : 1);
+    p->tuned_kern[m].assign(pd.steps.size(), -1);
+    p->tuned_var[m].assign(pd.steps.size(), 0);
+  }
+  select_steps(p);
   return (size_t)off;
+}
+
+bool step_lp_store(const rqc_plan* p, int prec, size_t i) {
+  if (prec == RQC_F32 || !p->lp_on[prec][i]) return false;
+  const Step& st = p->pd.steps[i];
+  return prec == RQC_BF16 ? st.lp_bf16 : st.lp;
+}
+
+void select_steps(rqc_plan* p) {
+  const PlanData& pd = p->pd;
+  const bool storage_only = pd.opts.precision_policy == RQC_POLICY_STORAGE;
+  for (int m = 0; m < 3; ++m) {
+    p->sel_desc[m].resize(pd.steps.size());
+    p->sel_kern[m].resize(pd.steps.size());
+    for (size_t i = 0; i < pd.steps.size(); ++i) {
+      const Step& st = pd.steps[i];
+      // Reduced-precision arithmetic: the step's LP kernel, unless the
+      // policy keeps all arithmetic in FP32 or the step was taken out of
+      // reduced precision.
+      const bool lp_math = m != RQC_F32 && p->lp_on[m][i] && !storage_only;
+      int k = lp_math ? p->kern_lp[i] : p->kern[i];
+      StepDesc d = lp_math ? p->tmpl_lp[i] : p->tmpl[i];
+      if (p->tuned_kern[m][i] >= 0) {
+        int kt = p->tuned_kern[m][i];
+        StepDesc dt = make_pair_desc(st.la, st.lb, st.lc, kt);
+        if (kt == p->tuned_kern[m][i]) {
+          k = kt;
+          d = dt;
+        }
+      }
+      d.variant = p->tuned_var[m][i];
+      if (m != RQC_F32 && !lp_math) d.variant |= kVarFP32Math;
+      p->sel_desc[m][i] = d;
+      p->sel_kern[m][i] = k;
+    }
+  }
+  p->layouts.clear();
+  clear_graphs(p);
 }
 
 void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
@@ -308,8 +352,8 @@ void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
   for (const Step& st : pd.steps) {
     if (!st.invariant) continue;
     const size_t si = &st - &pd.steps[0];
-    const int kern = p->kern[si];
-    StepDesc d = p->tmpl[si];
+    const int kern = p->sel_kern[RQC_F32][si];
+    StepDesc d = p->sel_desc[RQC_F32][si];
     d.A = base + p->inv_off[st.a];
     d.B = base + p->inv_off[st.b];
     d.C = base + p->inv_off[st.node];
@@ -379,8 +423,7 @@ static GroupLayout compute_layout(rqc_plan* p, int prec, int gs, int gb) {
       continue;
     }
     const int cs = P.dep_s ? gs : 1, cb = P.dep_b ? gb : 1;
-    const Step& ps = pd.steps[v >= nl ? pd.step_of_node[v] : 0];
-    const bool lp16 = v >= nl && (prec == RQC_BF16 ? ps.lp_bf16 : ps.lp);
+    const bool lp16 = v >= nl && step_lp_store(p, prec, (size_t)pd.step_of_node[v]);
     P.store = (lp_mode && lp16) ? lp_store : ST_C64;
     P.s_stride = P.dep_s ? E : 0;
     P.b_stride = P.dep_b ? E * cs : 0;
@@ -424,8 +467,8 @@ static GroupLayout compute_layout(rqc_plan* p, int prec, int gs, int gb) {
     if (st.invariant) continue;
     L.place[st.node].off = alloc(bytes[st.node]);
     // Split-K for generic steps whose output tiles cannot fill the GPU.
-    const StepDesc& t = p->tmpl[i];
-    if (p->kern[i] == KERN_SIMT && t.n_ko >= 2) {
+    const StepDesc& t = p->sel_desc[prec][i];
+    if (p->sel_kern[prec][i] == KERN_SIMT && t.n_ko >= 2) {
       const Placement& C = L.place[st.node];
       const int64_t copies = (int64_t)(C.dep_s ? gs : 1) * (C.dep_b ? gb : 1);
       const int64_t work = (int64_t)t.n_row_tiles * t.n_col_tiles * copies;
@@ -517,9 +560,64 @@ WsLayout ws_layout(rqc_plan* p, const GroupLayout& L, uint64_t n_ids, uint64_t n
 // ---------------------------------------------------------------------------
 // Recording one call (captured into a graph, or run directly for re-runs)
 // ---------------------------------------------------------------------------
-static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, uint64_t n_ids,
-                        uint64_t n_batch, char* ws, double* out, double* per_slice,
-                        int64_t ps_row0, hipStream_t s) {
+// Descriptor of step i for one group (gsc slices x gbc bitstrings, slice
+// flags at `gflags`) with its operands, strides and scale arrays bound.
+StepDesc bind_step(rqc_plan* p, const GroupLayout& L, const WsLayout& W, char* ws, size_t i,
+                   int gsc, int gbc, int32_t* gflags, int bias) {
+  const PlanData& pd = p->pd;
+  char* arena = ws + W.arena_off;
+  char* scale = ws + W.scale_off;
+  auto ptr = [&](const Placement& P) -> char* { return P.resident ? p->res + P.off : arena + P.off; };
+  auto eptr = [&](const Placement& P) -> int32_t* {
+    if (P.e_off < 0) return nullptr;
+    return reinterpret_cast<int32_t*>(P.resident ? p->res + P.e_off : scale + P.e_off);
+  };
+  auto mptr = [&](const Placement& P) -> float* {
+    if (P.m_off < 0) return nullptr;
+    return reinterpret_cast<float*>(P.resident ? p->res + P.m_off : scale + P.m_off);
+  };
+  const Step& st = pd.steps[i];
+  StepDesc d = p->sel_desc[L.prec][i];
+  const Placement &A = L.place[st.a], &B = L.place[st.b], &C = L.place[st.node];
+  d.A = ptr(A);
+  d.B = ptr(B);
+  d.C = ptr(C);
+  d.sA_s = A.s_stride, d.sA_b = A.b_stride;
+  d.sB_s = B.s_stride, d.sB_b = B.b_stride;
+  d.sC_s = C.s_stride, d.sC_b = C.b_stride;
+  d.gs_c = C.dep_s ? gsc : 1;
+  d.copies = d.gs_c * (C.dep_b ? gbc : 1);
+  // Exponents and maxima are kept in every precision.
+  d.track = 1;
+  d.expA = eptr(A), d.expB = eptr(B), d.expC = eptr(C);
+  d.maxA = mptr(A), d.maxB = mptr(B), d.maxC = mptr(C);
+  d.maxA_const = A.max_const, d.maxB_const = B.max_const;
+  d.eA_s = A.es, d.eA_b = A.eb, d.eB_s = B.es, d.eB_b = B.eb, d.eC_s = C.es, d.eC_b = C.eb;
+  d.lp_out = C.store != ST_C64;
+  d.bias = bias;
+  d.flag = gflags;
+  d.dep_s_c = C.dep_s;
+  d.flag_n = gsc;
+  if (L.ksplit[i]) {
+    d.ksplit = L.ksplit[i];
+    d.P = reinterpret_cast<float2*>(arena + L.p_off[i]);
+    d.p_stride = (int64_t(1) << pd.node_labels[st.node].size()) * (C.dep_s ? L.gs : 1) *
+                 (C.dep_b ? L.gb : 1);
+  }
+  return d;
+}
+
+hipError_t launch_bound_step(const rqc_plan* p, const GroupLayout& L, size_t i, const StepDesc& d,
+                             int kern, hipStream_t s) {
+  const Step& st = p->pd.steps[i];
+  const int lp_kind = L.prec == RQC_F16 ? ST_F16 : (L.prec == RQC_BF16 ? ST_BF16 : 0);
+  return launch_step(d, kern, L.place[st.a].store, L.place[st.b].store, L.place[st.node].store,
+                     lp_kind, s);
+}
+
+void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, uint64_t n_ids,
+                 uint64_t n_batch, char* ws, double* out, double* per_slice, int64_t ps_row0,
+                 hipStream_t s) {
   PlanData& pd = p->pd;
   const bool track = true;                  // exponents in every precision
   const bool lp_mode = L.prec != RQC_F32;   // slice flags drive FP32 re-runs
@@ -535,10 +633,6 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
   auto eptr = [&](const Placement& P) -> int32_t* {
     if (P.e_off < 0) return nullptr;
     return reinterpret_cast<int32_t*>(P.resident ? p->res + P.e_off : scale + P.e_off);
-  };
-  auto mptr = [&](const Placement& P) -> float* {
-    if (P.m_off < 0) return nullptr;
-    return reinterpret_cast<float*>(P.resident ? p->res + P.m_off : scale + P.m_off);
   };
   hip_check(launch_fill_i32(flags, 0, (int64_t)n_ids * W.n_bgroups, s), "clear flags");
   size_t probe = 0;
@@ -560,36 +654,9 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
       for (size_t i = 0; i < pd.steps.size(); ++i) {
         const Step& st = pd.steps[i];
         if (st.invariant) continue;
-        const bool lpm = L.prec != RQC_F32;
-        StepDesc d = lpm ? p->tmpl_lp[i] : p->tmpl[i];
+        StepDesc d = bind_step(p, L, W, ws, i, gsc, gbc, gflags + g0, bias);
         const Placement &A = L.place[st.a], &B = L.place[st.b], &C = L.place[st.node];
-        d.A = ptr(A);
-        d.B = ptr(B);
-        d.C = ptr(C);
-        d.sA_s = A.s_stride, d.sA_b = A.b_stride;
-        d.sB_s = B.s_stride, d.sB_b = B.b_stride;
-        d.sC_s = C.s_stride, d.sC_b = C.b_stride;
-        d.gs_c = C.dep_s ? gsc : 1;
-        d.copies = d.gs_c * (C.dep_b ? gbc : 1);
-        d.track = track ? 1 : 0;
-        if (track) {
-          d.expA = eptr(A), d.expB = eptr(B), d.expC = eptr(C);
-          d.maxA = mptr(A), d.maxB = mptr(B), d.maxC = mptr(C);
-          d.maxA_const = A.max_const, d.maxB_const = B.max_const;
-          d.eA_s = A.es, d.eA_b = A.eb, d.eB_s = B.es, d.eB_b = B.eb, d.eC_s = C.es, d.eC_b = C.eb;
-          d.lp_out = C.store != ST_C64;
-          d.bias = bias;
-          d.flag = gflags + g0;
-          d.dep_s_c = C.dep_s;
-          d.flag_n = gsc;
-        }
-        const int kern = lpm ? p->kern_lp[i] : p->kern[i];
-        if (L.ksplit[i]) {
-          d.ksplit = L.ksplit[i];
-          d.P = reinterpret_cast<float2*>(arena + L.p_off[i]);
-          d.p_stride = (int64_t(1) << pd.node_labels[st.node].size()) * (C.dep_s ? L.gs : 1) *
-                       (C.dep_b ? L.gb : 1);
-        }
+        const int kern = p->sel_kern[L.prec][i];
         const bool timed = p->timing_kernel == kTimeAll || kern == p->timing_kernel ||
                            (kern == KERN_MFMA16 && p->timing_kernel == KERN_MFMA);
         if (timed) {
@@ -604,8 +671,7 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
           }
           hip_check(hipEventRecord(p->tev[2 * probe], s), "event record");
         }
-        const int lp_kind = L.prec == RQC_F16 ? ST_F16 : (L.prec == RQC_BF16 ? ST_BF16 : 0);
-        hip_check(launch_step(d, kern, A.store, B.store, C.store, lp_kind, s), "step");
+        hip_check(launch_bound_step(p, L, i, d, kern, s), "step");
         if (timed) {
           hip_check(hipEventRecord(p->tev[2 * probe + 1], s), "event record");
           ++probe;
@@ -636,14 +702,14 @@ static void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, ui
   }
 }
 
-static bool fits(rqc_plan* p, int prec, int gs, int gb, uint64_t n_ids, uint64_t n_batch,
-                 size_t ws_bytes) {
+bool fits(rqc_plan* p, int prec, int gs, int gb, uint64_t n_ids, uint64_t n_batch,
+          size_t ws_bytes) {
   GroupLayout L = compute_layout(p, prec, gs, gb);
   return (size_t)ws_layout(p, L, n_ids, n_batch).total <= ws_bytes;
 }
 
-static void choose_group(rqc_plan* p, int prec, uint64_t n_ids, uint64_t n_batch, size_t ws_bytes,
-                         int& gs, int& gb) {
+void choose_group(rqc_plan* p, int prec, uint64_t n_ids, uint64_t n_batch, size_t ws_bytes,
+                  int& gs, int& gb) {
   int max_gs = (int)std::min<uint64_t>(n_ids, 4096);
   int max_gb = (int)std::min<uint64_t>(n_batch, 4096);
   if (p->group_limit_s > 0) max_gs = std::min(max_gs, p->group_limit_s);

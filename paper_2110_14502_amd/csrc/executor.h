@@ -103,9 +103,17 @@ struct rqc_plan {
   int64_t inv_bytes = 0;
   int scale_bias = 0;
   uint64_t scale_bias_from = 0;         // first bitstring whose groups get the bias
-  // Per-step descriptor templates (layout only) and chosen kernels.
+  // Per-step descriptor templates (layout only) and default kernels.
   std::vector<rqc::StepDesc> tmpl, tmpl_lp;  // FP32 and reduced precision
   std::vector<int> kern, kern_lp;
+  // Per precision mode (RQC_F32, RQC_F16, RQC_BF16) and step: whether the
+  // step runs in reduced precision (16-bit storage of its output by the size
+  // rule, 16-bit matrix cores; modes 1 and 2 only), the tuner's choice of
+  // kernel and variant (-1: none), and the descriptor and kernel launched.
+  std::vector<char> lp_on[3];
+  std::vector<int> tuned_kern[3], tuned_var[3];
+  std::vector<rqc::StepDesc> sel_desc[3];
+  std::vector<int> sel_kern[3];
   // Timing probe: events around launches of one kernel kind (or of all).
   int timing_kernel = -1;
   int group_limit_s = 0, group_limit_b = 0;  // 0: bounded by the workspace only
@@ -134,6 +142,32 @@ WsLayout ws_layout(rqc_plan* p, const GroupLayout& L, uint64_t n_ids, uint64_t n
 void contract(rqc_plan* p, const uint64_t* ids, uint64_t n_ids, const uint8_t* bits,
               uint64_t n_batch, int prec, void* ws, size_t ws_bytes, double* out,
               double* per_slice, hipStream_t s, PendingRun& run, bool direct = false);
+// Group sizes (slices, bitstrings) for a call within ws_bytes; EHBM if one
+// slice and one bitstring do not fit.
+void choose_group(rqc_plan* p, int prec, uint64_t n_ids, uint64_t n_batch, size_t ws_bytes,
+                  int& gs, int& gb);
+bool fits(rqc_plan* p, int prec, int gs, int gb, uint64_t n_ids, uint64_t n_batch,
+          size_t ws_bytes);
+
+// Every launch of one call (ids, bits and leaf jobs already in the
+// workspace), in order on `s`.
+void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, uint64_t n_ids,
+                 uint64_t n_batch, char* ws, double* out, double* per_slice, int64_t ps_row0,
+                 hipStream_t s);
+
+// Descriptor of step i for one group (gsc slices x gbc bitstrings) with its
+// operands, strides and scale arrays bound, and its launch.
+StepDesc bind_step(rqc_plan* p, const GroupLayout& L, const WsLayout& W, char* ws, size_t i,
+                   int gsc, int gbc, int32_t* gflags, int bias);
+hipError_t launch_bound_step(const rqc_plan* p, const GroupLayout& L, size_t i, const StepDesc& d,
+                             int kern, hipStream_t s);
+
+// Per-step kernel tuning and the precision pre-analysis (tune.cpp).
+void autotune(rqc_plan* p, int prec, uint64_t n_ids, uint64_t n_batch, void* ws, size_t ws_bytes,
+              const char* cache_path, hipStream_t s, rqc_tune_report* rep);
+void calibrate(rqc_plan* p, int prec, uint64_t slice_id, const uint8_t* bits, double target,
+               double err_floor, void* ws, size_t ws_bytes, hipStream_t s, rqc_calib_report* rep);
+
 // Synchronise `s`, re-run flagged slices in FP32, fill the report.
 void report(rqc_plan* p, PendingRun& run, hipStream_t s, rqc_run_report* r);
 
@@ -148,6 +182,14 @@ void hip_check(hipError_t e, const char* what);
 // Destroy every cached graph exec of the plan, each after its last launch
 // has completed.
 void clear_graphs(rqc_plan* p);
+
+// Rebuild the launched descriptor and kernel of every step and mode from the
+// defaults, the precision policy, the per-step reduced-precision switches and
+// the tuner's choices; drops cached layouts and graphs.
+void select_steps(rqc_plan* p);
+
+// Whether step i stores its output in 16 bits in mode `prec`.
+bool step_lp_store(const rqc_plan* p, int prec, size_t i);
 
 // Timing probe kinds: a kernel kind, or every step launch.
 constexpr int kTimeAll = 4;

@@ -21,7 +21,132 @@ namespace rqc {
 // ---------------------------------------------------------------------------
 constexpr unsigned kMfmaGrid = 256 * 2;
 
-template <int SA, int SB, int SC>
+// ---------------------------------------------------------------------------
+// Arithmetic of one 16-k chunk for one wave (64 rows x 32 complex columns of
+// the tile), in two forms:
+//
+// 4M: the real 2x2 expansion of B (kernels_dev.h): A_r (64 x 32 real k) times
+//     B_r (32 real k x 64 real columns) on four 32x32 accumulators; 8 real
+//     flops executed per complex multiply-add.
+// 3M: three real products per complex product (Gauss):
+//         P1 = Ar Br,  P2 = Ai Bi,  P3 = (Ar + Ai)(Br + Bi),
+//         Re C = P1 - P2,  Im C = P3 - P1 - P2,
+//     on six 32x32 accumulators (two row blocks x three products); each
+//     MFMA takes two complex k (one per half wave), so a chunk is 48 MFMAs
+//     instead of 64: 6 real flops executed per complex multiply-add, with
+//     half the LDS reads.  The sums Ar + Ai and Br + Bi are formed in
+//     registers from the same LDS planes.
+// ---------------------------------------------------------------------------
+template <bool M3>
+struct Acc32 {
+  floatx16 v[M3 ? 6 : 4];
+};
+
+template <bool M3>
+__device__ __forceinline__ void acc_zero(Acc32<M3>& acc) {
+#pragma unroll
+  for (int i = 0; i < (M3 ? 6 : 4); ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc.v[i][r] = 0.f;
+}
+
+// Abuf_cb / Bbuf_cb: the chunk's LDS buffers ([k][re|im][row] floats and
+// [k][col] complex values).
+template <bool M3>
+__device__ __forceinline__ void chunk_mfma(const float* Abuf_cb, const float2* Bbuf_cb, int lane,
+                                           int wm, int wn, Acc32<M3>& acc) {
+  if constexpr (!M3) {
+    const int lrow = lane & 31;
+    const int cpart = lane >> 5;         // A_r column parity: 0 re, 1 im
+    const int dpart = lane & 1;          // C_r column parity
+    const int ncol = (lane & 31) >> 1;   // complex column inside a 16-col block
+    const bool bswap = cpart != dpart;
+    const float bsign = (cpart == 1 && dpart == 0) ? -1.f : 1.f;
+    const float* As = Abuf_cb + cpart * kAPlane + wm * 64 + lrow;
+    const float2* Bs = Bbuf_cb + wn * 32 + ncol;
+    // Operands of step k+1 are read from LDS while the MFMAs of step k run.
+    float a0 = As[0], a1 = As[32];
+    float2 b0 = Bs[0], b1 = Bs[16];
+#pragma unroll
+    for (int k = 0; k < kTK; ++k) {
+      float a0n = 0.f, a1n = 0.f;
+      float2 b0n = make_float2(0.f, 0.f), b1n = make_float2(0.f, 0.f);
+      if (k + 1 < kTK) {
+        a0n = As[(k + 1) * kAStride];
+        a1n = As[(k + 1) * kAStride + 32];
+        b0n = Bs[(k + 1) * kBStride];
+        b1n = Bs[(k + 1) * kBStride + 16];
+      }
+      const float v0 = bsign * (bswap ? b0.y : b0.x);
+      const float v1 = bsign * (bswap ? b1.y : b1.x);
+      acc.v[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v0, acc.v[0], 0, 0, 0);
+      acc.v[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v1, acc.v[1], 0, 0, 0);
+      acc.v[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v0, acc.v[2], 0, 0, 0);
+      acc.v[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v1, acc.v[3], 0, 0, 0);
+      a0 = a0n;
+      a1 = a1n;
+      b0 = b0n;
+      b1 = b1n;
+    }
+  } else {
+    // Lane half h takes complex k = 2 kk + h; rows / columns lane & 31.
+    const int h = lane >> 5, l = lane & 31;
+    const float* As = Abuf_cb + h * kAStride + wm * 64 + l;
+    const float2* Bs = Bbuf_cb + h * kBStride + wn * 32 + l;
+    float ar0 = As[0], ai0 = As[kAPlane], ar1 = As[32], ai1 = As[kAPlane + 32];
+    float2 b = Bs[0];
+#pragma unroll
+    for (int kk = 0; kk < kTK / 2; ++kk) {
+      float nr0 = 0.f, ni0 = 0.f, nr1 = 0.f, ni1 = 0.f;
+      float2 nb = make_float2(0.f, 0.f);
+      if (kk + 1 < kTK / 2) {
+        const int o = 2 * (kk + 1) * kAStride;
+        nr0 = As[o];
+        ni0 = As[o + kAPlane];
+        nr1 = As[o + 32];
+        ni1 = As[o + kAPlane + 32];
+        nb = Bs[2 * (kk + 1) * kBStride];
+      }
+      const float bs = b.x + b.y, as0 = ar0 + ai0, as1 = ar1 + ai1;
+      acc.v[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar0, b.x, acc.v[0], 0, 0, 0);
+      acc.v[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai0, b.y, acc.v[1], 0, 0, 0);
+      acc.v[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(as0, bs, acc.v[2], 0, 0, 0);
+      acc.v[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar1, b.x, acc.v[3], 0, 0, 0);
+      acc.v[4] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai1, b.y, acc.v[4], 0, 0, 0);
+      acc.v[5] = __builtin_amdgcn_mfma_f32_32x32x2f32(as1, bs, acc.v[5], 0, 0, 0);
+      ar0 = nr0;
+      ai0 = ni0;
+      ar1 = nr1;
+      ai1 = ni1;
+      b = nb;
+    }
+  }
+}
+
+// Writes this wave's 64 x 32 complex accumulators into the staged half Cs
+// ([row][real column] floats, kCStride per row).
+template <bool M3>
+__device__ __forceinline__ void stage_acc(float* Cs, const Acc32<M3>& acc, int lane, int wn) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      if constexpr (!M3) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = wn * 64 + j * 32 + (lane & 31);
+          Cs[row * kCStride + col] = acc.v[2 * i + j][r];
+        }
+      } else {
+        const float p1 = acc.v[3 * i][r], p2 = acc.v[3 * i + 1][r], p3 = acc.v[3 * i + 2][r];
+        const int col = 2 * (wn * 32 + (lane & 31));
+        *reinterpret_cast<float2*>(Cs + row * kCStride + col) = make_float2(p1 - p2, p3 - p1 - p2);
+      }
+    }
+}
+
+template <int SA, int SB, int SC, bool M3>
 __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items) {
   __shared__ float lds[kMainFloats + 16];
   __shared__ TileTab tcs;
@@ -71,14 +196,6 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
   int c_lo4[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) c_lo4[i] = tcs.c[((tid & 15) << 2) + i];
-
-  // Lane roles inside the real-expanded operands.
-  const int lrow = lane & 31;          // row inside a 32-row block
-  const int cpart = lane >> 5;         // A_r column parity: 0 re, 1 im
-  const int dpart = lane & 1;          // C_r column parity
-  const int ncol = (lane & 31) >> 1;   // complex column inside a 16-col block
-  const bool bswap = cpart != dpart;
-  const float bsign = (cpart == 1 && dpart == 0) ? -1.f : 1.f;
 
   const int n_kc = 1 << d.n_ko;
   // Tile counts are powers of two: item t is copy t >> tb, row tile
@@ -154,13 +271,8 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
     outer_offsets(d, ot, bid >> d.n_no, bid & cmask, js, jb, oA, oB, oC);
     const bool next_tile = t + G < n_items;
 
-    floatx16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    Acc32<M3> acc;
+    acc_zero(acc);
 
     for (int kc = 0; kc < n_kc; ++kc) {
       const int cb = kc & 1;
@@ -176,32 +288,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
         item_offsets(t + G, pA, pB, pC);
         load_chunk(pA, pB, 0);
       }
-      const float* As = Abuf + cb * kABuf + cpart * kAPlane + wm * 64 + lrow;
-      const float2* Bs = Bbuf + cb * kBBuf + wn * 32 + ncol;
-      // Operands of step k+1 are read from LDS while the MFMAs of step k run.
-      float a0 = As[0], a1 = As[32];
-      float2 b0 = Bs[0], b1 = Bs[16];
-#pragma unroll
-      for (int k = 0; k < kTK; ++k) {
-        float a0n = 0.f, a1n = 0.f;
-        float2 b0n = make_float2(0.f, 0.f), b1n = make_float2(0.f, 0.f);
-        if (k + 1 < kTK) {
-          a0n = As[(k + 1) * kAStride];
-          a1n = As[(k + 1) * kAStride + 32];
-          b0n = Bs[(k + 1) * kBStride];
-          b1n = Bs[(k + 1) * kBStride + 16];
-        }
-        const float v0 = bsign * (bswap ? b0.y : b0.x);
-        const float v1 = bsign * (bswap ? b1.y : b1.x);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v1, acc[1][1], 0, 0, 0);
-        a0 = a0n;
-        a1 = a1n;
-        b0 = b0n;
-        b1 = b1n;
-      }
+      chunk_mfma<M3>(Abuf + cb * kABuf, Bbuf + cb * kBBuf, lane, wm, wn, acc);
       if (more) store_chunk(cb ^ 1);
       __syncthreads();
     }
@@ -210,18 +297,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
     float* Cs = lds;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (wm == h) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-              const int col = wn * 64 + j * 32 + (lane & 31);
-              Cs[row * kCStride + col] = acc[i][j][r];
-            }
-      }
+      if (wm == h) stage_acc<M3>(Cs, acc, lane, wn);
       __syncthreads();
       if (vec_c)
         store_half4<SC>(d, Cs, tcs, oC + g_lo4 + (h ? g_half : 0), c_lo4, tid, sc, lmax, bad);
@@ -244,8 +320,8 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
 // in the chunk loop.  Same tiling and arithmetic; the output table is built in
 // the operand buffers after the last chunk.  51.8 KB of LDS.
 // ---------------------------------------------------------------------------
-template <int SA, int SB, int SC>
-__global__ __launch_bounds__(256, 3) void k_mfma32_tiles(StepDesc d) {
+template <int SA, int SB, int SC, bool M3>
+__global__ __launch_bounds__(256, M3 ? 2 : 3) void k_mfma32_tiles(StepDesc d) {
   __shared__ float lds[kMainFloats + 16];
   __shared__ OuterTab ot;
   float* Abuf = lds;
@@ -289,13 +365,6 @@ __global__ __launch_bounds__(256, 3) void k_mfma32_tiles(StepDesc d) {
     if (d.tC.role[b] == 0 && d.tC.cbit[b] == 6) hb = b;
   const int64_t g_half = int64_t(1) << d.tC.gpos[hb];
 
-  const int lrow = lane & 31;
-  const int cpart = lane >> 5;
-  const int dpart = lane & 1;
-  const int ncol = (lane & 31) >> 1;
-  const bool bswap = cpart != dpart;
-  const float bsign = (cpart == 1 && dpart == 0) ? -1.f : 1.f;
-
   const int n_kc = 1 << d.n_ko;
   float2 ra[8], rb[4];
   for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
@@ -321,13 +390,8 @@ __global__ __launch_bounds__(256, 3) void k_mfma32_tiles(StepDesc d) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) Bn[lB[j]] = rb[j];
     };
-    floatx16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    Acc32<M3> acc;
+    acc_zero(acc);
     load_chunk(0);
     __syncthreads();  // the tables (or the previous copy's output) are done with
     store_chunk(0);
@@ -336,31 +400,7 @@ __global__ __launch_bounds__(256, 3) void k_mfma32_tiles(StepDesc d) {
       const int cb = kc & 1;
       const bool more = kc + 1 < n_kc;
       if (more) load_chunk(kc + 1);
-      const float* As = Abuf + cb * kABuf + cpart * kAPlane + wm * 64 + lrow;
-      const float2* Bs = Bbuf + cb * kBBuf + wn * 32 + ncol;
-      float a0 = As[0], a1 = As[32];
-      float2 b0 = Bs[0], b1 = Bs[16];
-#pragma unroll
-      for (int k = 0; k < kTK; ++k) {
-        float a0n = 0.f, a1n = 0.f;
-        float2 b0n = make_float2(0.f, 0.f), b1n = make_float2(0.f, 0.f);
-        if (k + 1 < kTK) {
-          a0n = As[(k + 1) * kAStride];
-          a1n = As[(k + 1) * kAStride + 32];
-          b0n = Bs[(k + 1) * kBStride];
-          b1n = Bs[(k + 1) * kBStride + 16];
-        }
-        const float v0 = bsign * (bswap ? b0.y : b0.x);
-        const float v1 = bsign * (bswap ? b1.y : b1.x);
-        acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, v1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, v1, acc[1][1], 0, 0, 0);
-        a0 = a0n;
-        a1 = a1n;
-        b0 = b0n;
-        b1 = b1n;
-      }
+      chunk_mfma<M3>(Abuf + cb * kABuf, Bbuf + cb * kBBuf, lane, wm, wn, acc);
       if (more) store_chunk(cb ^ 1);
       __syncthreads();
     }
@@ -377,18 +417,7 @@ __global__ __launch_bounds__(256, 3) void k_mfma32_tiles(StepDesc d) {
     const int c_lane = tcs->c[lane];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (wm == h) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int row = i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-              const int col = wn * 64 + j * 32 + (lane & 31);
-              Cs[row * kCStride + col] = acc[i][j][r];
-            }
-      }
+      if (wm == h) stage_acc<M3>(Cs, acc, lane, wn);
       __syncthreads();
       const int64_t gl = g_lane + (h ? g_half : 0);
 #pragma unroll 4
@@ -403,13 +432,17 @@ __global__ __launch_bounds__(256, 3) void k_mfma32_tiles(StepDesc d) {
   }
 }
 
-#define RQC_MFMA_CASE(a, b, c)                                                         \
-  if (sa == a && sb == b && sc == c) {                                                 \
-    if (tiles_kernel)                                                                  \
-      hipLaunchKernelGGL((k_mfma32_tiles<a, b, c>), grid, dim3(256), 0, s, d);        \
-    else                                                                               \
-      hipLaunchKernelGGL((k_mfma32<a, b, c>), grid, dim3(256), 0, s, d, n_items);     \
-    return hipGetLastError();                                                          \
+#define RQC_MFMA_CASE(a, b, c)                                                          \
+  if (sa == a && sb == b && sc == c) {                                                  \
+    if (tiles_kernel && m3)                                                             \
+      hipLaunchKernelGGL((k_mfma32_tiles<a, b, c, true>), grid, dim3(256), 0, s, d);   \
+    else if (tiles_kernel)                                                              \
+      hipLaunchKernelGGL((k_mfma32_tiles<a, b, c, false>), grid, dim3(256), 0, s, d);  \
+    else if (m3)                                                                        \
+      hipLaunchKernelGGL((k_mfma32<a, b, c, true>), grid, dim3(256), 0, s, d, n_items); \
+    else                                                                                \
+      hipLaunchKernelGGL((k_mfma32<a, b, c, false>), grid, dim3(256), 0, s, d, n_items); \
+    return hipGetLastError();                                                           \
   }
 
 hipError_t launch_mfma32_kernel(const StepDesc& d, int sa, int sb, int sc, dim3 grid,
@@ -418,7 +451,8 @@ hipError_t launch_mfma32_kernel(const StepDesc& d, int sa, int sb, int sc, dim3 
   const uint64_t n_items = (uint64_t)grid.x * (uint64_t)d.copies;
   // Sums of 256 or more complex terms: one tile per workgroup (grid = tiles
   // x copies as given); shorter sums: the persistent walk.
-  const bool tiles_kernel = d.n_ko >= 4;
+  const bool tiles_kernel = d.variant & kVarTiles ? true : (d.variant & kVarPersistent ? false : d.n_ko >= 4);
+  const bool m3 = (d.variant & kVar4M) == 0;
   if (!tiles_kernel) grid = dim3((unsigned)(n_items < kMfmaGrid ? n_items : kMfmaGrid), 1);
   RQC_MFMA_CASE(ST_C64, ST_C64, ST_C64)
   RQC_MFMA_CASE(ST_C64, ST_C64, ST_F16)

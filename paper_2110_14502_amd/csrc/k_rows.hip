@@ -171,11 +171,11 @@ __device__ __forceinline__ void load_tile_rows(const StepDesc& d, int64_t oA, in
 // tile (or K chunk) are loaded while the current one is multiplied and
 // written.  KB: bits of one K chunk (the whole sum when k <= 4); NCH: chunks
 // of 8 complex output columns, whose accumulators stay in registers.
-template <int KB, int NCH, int SA>
+template <int KB, int NCH, int SA, bool ALLOW16>
 __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   constexpr int K = 1 << KB;
   constexpr int NJ = K >= 2 ? (2 * K) / 4 : 1;  // real k per lane quarter (FP32 MFMAs per chunk)
-  constexpr bool LPM = SA != ST_C64 && KB >= 4;  // 16-bit matrix cores
+  constexpr bool LPM = ALLOW16 && SA != ST_C64 && KB >= 4;  // 16-bit matrix cores
   extern __shared__ __attribute__((aligned(16))) float2 rows_lds[];  // 16-byte B reads
   __shared__ TileTab tc;
   __shared__ int64_t bofs[64];
@@ -444,11 +444,16 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   if (cur >= 0) finish_scale<256>(d, cjs, cjb, lmax, bad, red, wexp, sc);
 }
 
+// A 16-bit stored A with sums of 16 or more goes to the 16-bit matrix cores
+// unless the step asks for FP32 arithmetic (kVarFP32Math).
 template <int KB, int NCH>
 static hipError_t launch_rows_n(const StepDesc& d, int sa, dim3 grid, size_t lds, hipStream_t s) {
-  if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16>), grid, dim3(256), lds, s, d);
-  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16>), grid, dim3(256), lds, s, d);
-  else hipLaunchKernelGGL((k_rows<KB, NCH, ST_C64>), grid, dim3(256), lds, s, d);
+  const bool fp32 = (d.variant & kVarFP32Math) != 0;
+  if (sa == ST_F16 && fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16, false>), grid, dim3(256), lds, s, d);
+  else if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16, true>), grid, dim3(256), lds, s, d);
+  else if (sa == ST_BF16 && fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16, false>), grid, dim3(256), lds, s, d);
+  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16, true>), grid, dim3(256), lds, s, d);
+  else hipLaunchKernelGGL((k_rows<KB, NCH, ST_C64, true>), grid, dim3(256), lds, s, d);
   return hipGetLastError();
 }
 

@@ -64,6 +64,7 @@ struct StepDesc {
   // bits (their C positions in nh_C) select the chunk.
   int32_t ncb;
   int32_t vec_c;      // 1: tile bits 0 and 1 are C's address bits 0 and 1 (4-element stores)
+  int32_t variant;    // kernel variant bits (kVar*), chosen per step by the tuner; 0 = default
   int8_t nh_C[16];
   int8_t ro_A[kMaxOuter], ro_C[kMaxOuter];
   int8_t no_B[kMaxOuter], no_C[kMaxOuter];
@@ -84,6 +85,15 @@ struct LeafJob {
   int32_t dst_store;  // Store code of the destination
   int32_t out_s, out_b;  // copy strides of the destination (elements)
 };
+
+// Kernel variant bits of a step (StepDesc::variant).  FP32 matrix-core
+// kernel: the complex products as four real products on the real expansion
+// of B (kVar4M) or as three (the default); one tile per workgroup
+// (kVarTiles) or the persistent walk (kVarPersistent); neither: per-tile for
+// sums of 256 or more.
+// Any kernel: kVarFP32Math keeps the arithmetic in FP32 on 16-bit stored
+// operands (the row kernel would otherwise use the 16-bit matrix cores).
+constexpr int32_t kVar4M = 1, kVarTiles = 2, kVarPersistent = 4, kVarFP32Math = 8;
 
 // Kernel kinds of a step.
 // KERN_MFMA16: FP16/BF16 matrix cores, 32 complex k per chunk (reduced

@@ -1,9 +1,14 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
 Tolerances (FP32 path): amplitudes normalised by the RMS amplitude
-2^(-n/2) must agree to 1e-4; single contraction steps to 2e-5 relative to
-the RMS of the reference (FP32 unit roundoff 6e-8 times a K-term sum with
-K <= 2^16 and random signs gives ~1.5e-5 in the worst accumulation order).
+2^(-n/2) must agree to 1e-4; single contraction steps to max(2e-5, 6 u sqrt(K))
+relative to the RMS of the reference.  The rounding of a K-term FP32 sum of
+random-sign products grows like u sqrt(K) relative to the RMS output
+(u = 2^-24, partial sums growing as a random walk); the three-product form
+of the complex product (Im C = P3 - P1 - P2) roughly doubles it, and the
+factor 6 covers a 4-sigma tail over the checked outputs.  For the sums of
+up to 2^9 terms of most cases this is 2e-5; for the rank-24..32 steps with
+up to 2^16 summed terms it reaches 9e-5.
 Reduced precision: normalised error <= 2e-2 and linear fidelity >= 0.99.
 """
 import sys
@@ -28,6 +33,11 @@ def _say(*a):
 
 def _dev_c64(x):
     return torch.from_numpy(np.ascontiguousarray(x.astype(np.complex64))).cuda()
+
+
+def fp32_step_tol(k_bits):
+    """Single-step FP32 bound for sums of 2^k_bits terms (module docstring)."""
+    return max(2e-5, 6 * 2.0 ** -24 * 2.0 ** (k_bits / 2))
 
 
 def _rel_rms(got, ref):
@@ -381,5 +391,5 @@ def test_config3_full_rank_steps_sampled():
         ref = oracle.sampled_step(get(A), get(B), la, lb, lc, coords)
         got = C[torch.from_numpy(coords).cuda()].cpu().numpy()
         scale = np.sqrt(2.0 ** k)  # RMS of a sum of 2^k unit-variance products
-        assert np.max(np.abs(got - ref)) / scale < 2e-5
+        assert np.max(np.abs(got - ref)) / scale < fp32_step_tol(k)
         del A, B, C

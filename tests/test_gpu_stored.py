@@ -174,3 +174,24 @@ def test_stored_entry_rejects_unsupported_requests():
         R.pair_contract_stored(A, B, C, la, lb, lc, R.ST_F16, R.ST_BF16, 0, R.KERN_SIMT)
     with pytest.raises(R.RqcError):   # 16-bit matrix cores need an MMA type
         R.pair_contract_stored(A, B, C, la, lb, lc, 0, 0, 0, R.KERN_MFMA16, mma_prec=R.F32)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_fp32_mfma_variants_vs_einsum(variant):
+    """Every variant of the FP32 matrix-core kernel (three or four real
+    products per complex product; per-tile or persistent walk) against
+    einsum, on random index orders of A, B and C, short and long sums."""
+    _say("mfma32 variant", variant)
+    for (ra, rb, s, seed) in ((14, 12, 5, 3), (16, 13, 7, 4), (18, 16, 9, 8), (15, 15, 4, 5)):
+        st = rqcgen.synthetic_step(ra, rb, s, seed)
+        a = rqcgen.random_complex(1 << ra, seed + 100)
+        b = rqcgen.random_complex(1 << rb, seed + 200)
+        A, _ = _store(a, R.ST_C64)
+        B, _ = _store(b, R.ST_C64)
+        C = _empty(1 << len(st.labels_c), R.ST_C64)
+        R.pair_contract_stored(A, B, C, st.labels_a, st.labels_b, st.labels_c, R.ST_C64,
+                               R.ST_C64, R.ST_C64, R.KERN_MFMA, variant=variant)
+        torch.cuda.synchronize()
+        ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
+        err = _rel_rms(_values(C), ref)
+        assert err < 2e-5, (ra, rb, s, variant, err)
