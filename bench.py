@@ -429,6 +429,21 @@ def kernel_mode(a):
     kp = R.PRECISIONS[a.kprec]
     fl = 8.0 * a.batch * 2.0 ** (m + n + k)
     by = 8.0 * a.batch * (2.0 ** (m + k) + 2.0 ** (n + k) + 2.0 ** (m + n))
+    if kp != R.F32 and m >= 7 and n >= 6 and k >= 4:
+        # 16-bit matrix-core variants on the plan's storage (A and C in 16
+        # bits, B in complex64): the tile walk and the streaming form.
+        t16 = torch.float16 if kp == R.F16 else torch.bfloat16
+        A16 = torch.randn((a.batch << (m + k), 2), dtype=torch.float32, device="cuda").to(t16)
+        C16 = torch.empty((a.batch << (m + n), 2), dtype=t16, device="cuda")
+        lp = R.ST_F16 if kp == R.F16 else R.ST_BF16
+        for var, name in ((0, "lp_tiles"), (R.VAR_STREAM, "lp_stream")):
+            ms = _events_time(lambda: R.pair_contract_stored(
+                A16, B, C16, la, lb, lc, lp, R.ST_C64, lp, R.KERN_MFMA16, mma_prec=kp,
+                batch=a.batch, stride_a=1 << (m + k), stride_b=1 << (n + k),
+                stride_c=1 << (m + n), variant=var), a.reps)
+            by16 = a.batch * (4.0 * 2 ** (m + k) + 8.0 * 2 ** (n + k) + 4.0 * 2 ** (m + n))
+            res[name] = {"ms": ms, "tflops": fl / ms / 1e9, "gbs": by16 / ms / 1e6}
+            log(f"variant {name}: {ms:.3f} ms, {by16 / ms / 1e6:.0f} GB/s")
     if kp == R.F32 and m >= 7 and n >= 6 and k >= 4:
         # FP32 matrix-core variants: 3M / 4M products, per-tile / persistent.
         for var, name in ((0, "3m_auto"), (1, "4m_auto"), (2, "3m_tiles"), (3, "4m_tiles"),

@@ -525,8 +525,10 @@ rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias,
  * caller keeps values inside the 16-bit range).  variant: kernel variant
  * bits (0 = default; FP32 matrix cores: 1 = four real products per complex
  * product instead of three, 2 = one tile per workgroup, 4 = persistent
- * walk).  EINVAL when the kernel's shape or layout conditions are not met
- * (no fallback). */
+ * walk; any kernel: 8 = FP32 arithmetic on 16-bit stored operands; 16-bit
+ * matrix cores: 16 = stream A past a resident tile of B, for sums of 32 to
+ * 128 terms with A stored in 16 bits).  EINVAL when the kernel's shape or
+ * layout conditions are not met (no fallback). */
 rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
                                     const int32_t* labels_b, int32_t rank_b,
                                     const int32_t* labels_c, int32_t rank_c,

@@ -534,7 +534,7 @@ ST_C64, ST_F16, ST_BF16 = 0, 1, 2
 KERN_SIMT, KERN_MFMA, KERN_ROWS, KERN_MFMA16 = 0, 1, 2, 3
 
 
-VAR_4M, VAR_TILES, VAR_PERSISTENT = 1, 2, 4
+VAR_4M, VAR_TILES, VAR_PERSISTENT, VAR_FP32_MATH, VAR_STREAM = 1, 2, 4, 8, 16
 
 
 def pair_contract_stored(A, B, C_out, labels_a, labels_b, labels_c, store_a, store_b, store_c,

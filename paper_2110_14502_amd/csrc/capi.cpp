@@ -456,7 +456,7 @@ rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
   d.sC_s = stride_c;
   d.gs_c = batch_count;
   d.copies = batch_count;
-  if (variant < 0 || variant > 15) throw rqc::Error{RQC_EINVAL, "variant out of range"};
+  if (variant < 0 || variant > 31) throw rqc::Error{RQC_EINVAL, "variant out of range"};
   d.variant = variant;
   const int lp_kind = kernel == rqc::KERN_MFMA16 ? (mma_prec == RQC_F16 ? rqc::ST_F16 : rqc::ST_BF16) : 0;
   rqc::hip_check(rqc::launch_step(d, kern, store_a, store_b, store_c, lp_kind,

@@ -93,7 +93,10 @@ struct LeafJob {
 // sums of 256 or more.
 // Any kernel: kVarFP32Math keeps the arithmetic in FP32 on 16-bit stored
 // operands (the row kernel would otherwise use the 16-bit matrix cores).
-constexpr int32_t kVar4M = 1, kVarTiles = 2, kVarPersistent = 4, kVarFP32Math = 8;
+// 16-bit matrix-core kernel: kVarStream streams A past a resident B tile
+// (sums of 32..128 terms, A stored in 16 bits).
+constexpr int32_t kVar4M = 1, kVarTiles = 2, kVarPersistent = 4, kVarFP32Math = 8,
+                  kVarStream = 16;
 
 // Kernel kinds of a step.
 // KERN_MFMA16: FP16/BF16 matrix cores, 32 complex k per chunk (reduced

@@ -79,6 +79,7 @@ std::vector<std::pair<int, int>> candidates(rqc_plan* p, int m, size_t i) {
   if (fp32_mma && valid(KERN_MFMA))
     for (int v : {kVarTiles, kVarTiles | kVar4M, kVarPersistent, kVarPersistent | kVar4M})
       add(KERN_MFMA, v);
+  if (cur == KERN_MFMA16 && st.k >= 5 && st.k <= 7) add(KERN_MFMA16, kVarStream);
   if ((cur == KERN_MFMA || cur == KERN_MFMA16) && valid(KERN_ROWS)) add(KERN_ROWS, 0);
   if (c.size() == 1) c.clear();
   return c;

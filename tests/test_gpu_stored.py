@@ -73,7 +73,7 @@ def _plan_layout(m, n, k, seed):
     return la, lb, lc
 
 
-def _run(m, n, k, seed, sa, sb, sc, kernel, batch=1, mma=None):
+def _run(m, n, k, seed, sa, sb, sc, kernel, batch=1, mma=None, variant=0):
     la, lb, lc = _plan_layout(m, n, k, seed)
     a = rqcgen.random_complex((batch, 1 << (m + k)), seed)
     b = rqcgen.random_complex(1 << (n + k), seed + 1)
@@ -83,7 +83,8 @@ def _run(m, n, k, seed, sa, sb, sc, kernel, batch=1, mma=None):
     if mma is None:
         mma = R.F32
     R.pair_contract_stored(A, B, C, la, lb, lc, sa, sb, sc, kernel, mma_prec=mma, batch=batch,
-                           stride_a=1 << (m + k), stride_b=0, stride_c=1 << (m + n))
+                           stride_a=1 << (m + k), stride_b=0, stride_c=1 << (m + n),
+                           variant=variant)
     torch.cuda.synchronize()
     got = _values(C).reshape(batch, -1)
     a_held = a_held.reshape(batch, -1)
@@ -195,3 +196,19 @@ def test_fp32_mfma_variants_vs_einsum(variant):
         ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
         err = _rel_rms(_values(C), ref)
         assert err < 2e-5, (ra, rb, s, variant, err)
+
+
+@pytest.mark.parametrize("lp", LP)
+def test_16bit_mfma_streaming_variant(lp):
+    """The 16-bit matrix-core kernel's streaming form (A streamed past a
+    resident tile of B over the whole sum), sums of 32..128 terms, several
+    row and column tiles, batched copies, against einsum on the stored
+    values."""
+    for (m, n, k, seed) in ((10, 7, 5, 101), (9, 6, 6, 102), (11, 7, 7, 103), (8, 8, 7, 104)):
+        _say("mfma16 stream", lp, m, n, k)
+        err = _run(m, n, k, seed, lp, lp, R.ST_C64, R.KERN_MFMA16, batch=3, mma=MMA[lp],
+                   variant=R.VAR_STREAM)
+        assert err < 2e-5, (m, n, k, err)
+        err = _run(m, n, k, seed, lp, R.ST_C64, lp, R.KERN_MFMA16, batch=2, mma=MMA[lp],
+                   variant=R.VAR_STREAM)
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
