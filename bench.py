@@ -109,6 +109,8 @@ def parse():
                     help="timed steps of the reduced-precision (f16) comparison, 0 = skip")
     ap.add_argument("--tune", type=int, default=1,
                     help="per-step kernel tuning of the benchmarked plan before timing (1 = on)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="amplitude mode: requests of the serving leg (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget of the oracle CPU baseline sample, 0 = skip")
     return ap.parse_args()
@@ -509,20 +511,20 @@ def steps_mode(a):
           flush=True)
 
 
-def serve_mode(a):
-    """Continuous batching of amplitude requests over seeded circuits from 5x5
-    to 8x8 qubits at depths 10-20 (families whose plan exceeds 2^42 flops are
-    rejected), 0-10 open qubits, FP16 or FP32; Poisson arrivals at a fraction
-    of the measured saturation rate."""
+def run_serving(n_requests, load, budget_gb, grids, depths, circuits_per_family, burst):
+    """Continuous batching of amplitude requests over seeded circuits (grids x
+    depths, circuits_per_family seeds each; families whose plan exceeds 2^42
+    flops are rejected), 0-10 open qubits, FP16 or FP32 at 50/50; a burst
+    measures the saturation rate, then n_requests Poisson arrivals at
+    load x saturation; latency is submit to result."""
     import numpy as np
-    import torch
     import rqcgen
     import paper_2110_14502_amd as R
     rng = np.random.default_rng(5)
     fams, tried = [], 0
     t = time.perf_counter()
-    for (r, c) in ((5, 5), (6, 6), (7, 7), (8, 8)):
-        for d in range(10, 21, 2):
+    for (r, c) in grids:
+        for d in depths:
             tried += 1
             n = r * c
             circ = rqcgen.grid_rqc(r, c, d, 1)
@@ -537,12 +539,12 @@ def serve_mode(a):
     log(f"serve: {len(fams)}/{tried} circuit families accepted ({time.perf_counter() - t:.1f}s)")
     pool = {}
     for f in fams:
-        for sd in range(4):
+        for sd in range(circuits_per_family):
             pool[(f, sd)] = rqcgen.grid_rqc(f[0], f[1], f[2], 1000 + sd)
 
     def draw(i):
         f = fams[int(rng.integers(len(fams)))]
-        sd = int(rng.integers(4))
+        sd = int(rng.integers(circuits_per_family))
         circ = pool[(f, sd)]
         n = circ.n_qubits
         n_open = int(rng.integers(0, 11))
@@ -551,7 +553,7 @@ def serve_mode(a):
         prec = R.F16 if rng.random() < 0.5 else R.F32
         return circ, openq, bits, prec
 
-    srv = R.Server(int(a.budget_gb * (1 << 30)), max_inflight=8, n_streams=4, max_batch=32)
+    srv = R.Server(int(budget_gb * (1 << 30)), max_inflight=8, n_streams=4, max_batch=32)
 
     def submit(q):
         circ, openq, bits, prec = q
@@ -566,21 +568,21 @@ def serve_mode(a):
         return [got[t] for t in tickets]
 
     # Warm-up: one request per circuit builds and binds every plan.
+    t = time.perf_counter()
     warm = [submit((c, list(range(c.n_qubits - 2, c.n_qubits)), rqcgen.random_bits(c.n_qubits - 2, 1),
                     R.F32)) for c in pool.values()]
     collect(warm)
-    log(f"serve: warmed {len(warm)} plans")
+    log(f"serve: warmed {len(warm)} plans ({time.perf_counter() - t:.1f}s)")
     # Saturation: a burst of requests at once.
-    burst = [draw(i) for i in range(min(200, a.requests))]
+    bq = [draw(i) for i in range(burst)]
     t0 = time.perf_counter()
-    res = collect([submit(q) for q in burst])
-    t_sat = time.perf_counter() - t0
-    sat_rate = len(burst) / t_sat
+    collect([submit(q) for q in bq])
+    sat_rate = len(bq) / (time.perf_counter() - t0)
     log(f"serve: saturation {sat_rate:.1f} requests/s")
     # Poisson stream at `load` x saturation.
-    lam = a.load * sat_rate
-    arr = rqcgen.poisson_arrivals(lam, a.requests, 6)
-    stream = [draw(10000 + i) for i in range(a.requests)]
+    lam = load * sat_rate
+    arr = rqcgen.poisson_arrivals(lam, n_requests, 6)
+    stream = [draw(10000 + i) for i in range(n_requests)]
     tickets = []
     t0 = time.perf_counter()
     for q, ta in zip(stream, arr):
@@ -600,14 +602,23 @@ def serve_mode(a):
             failed[key] = failed.get(key, 0) + 1
     lat = np.array([r["t_done"] - r["t_submit"] for r in ok])
     n_amp = sum(1 << len(q[1]) for q, r in zip(stream, res) if r["status"] == 0)
-    out = {"mode": "serve", "requests": a.requests, "completed": len(ok),
-           "families_accepted": f"{len(fams)}/{tried}", "saturation_req_s": sat_rate,
-           "offered_req_s": lam, "amplitudes_per_s": n_amp / wall,
-           "requests_per_s": len(ok) / wall,
-           "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),
-                          "p99": 1000 * float(np.percentile(lat, 99))},
-           "max_inflight_seen": st["max_inflight_seen"], "plans_built": st["plans_built"],
-           "plans_reused": st["plans_reused"], "peak_bytes": st["peak_bytes"], "failed": failed}
+    return {"requests": n_requests, "completed": len(ok),
+            "families_accepted": f"{len(fams)}/{tried}", "circuits": len(pool),
+            "saturation_req_s": sat_rate, "offered_req_s": lam, "load": load,
+            "amplitudes_per_s": n_amp / wall, "requests_per_s": len(ok) / wall,
+            "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),
+                           "p99": 1000 * float(np.percentile(lat, 99))},
+            "max_inflight_seen": st["max_inflight_seen"], "plans_built": st["plans_built"],
+            "plans_reused": st["plans_reused"], "peak_bytes": st["peak_bytes"],
+            "budget_gb": budget_gb, "failed": failed}
+
+
+def serve_mode(a):
+    """Serving workload: grids 5x5 to 8x8, depths 10-20, 4 circuits per
+    family."""
+    out = run_serving(a.requests, a.load, a.budget_gb, ((5, 5), (6, 6), (7, 7), (8, 8)),
+                      range(10, 21, 2), 4, min(200, a.requests))
+    out["mode"] = "serve"
     print(json.dumps(out), flush=True)
 
 
@@ -1037,6 +1048,16 @@ def main():
         if golden is not None:
             res["reduced_precision"]["error_vs_oracle"] = _norm_err(lp_amps, golden, n)
             res["reduced_precision"]["fidelity_vs_oracle"] = _fidelity(lp_amps, golden)
+    if a.serve_requests > 0:
+        # Serving leg (continuous batching; p50 / p99 latency beside the
+        # throughput): 5x5 and 6x6 grids at depths 10-14, 4 circuits each.
+        plan.set_timing(-1)
+        del ws
+        torch.cuda.empty_cache()
+        res["serving"] = run_serving(a.serve_requests, 0.8, 64.0, ((5, 5), (6, 6)), (10, 12, 14),
+                                     4, 100)
+        res["latency_ms"]["serving_p50"] = res["serving"]["latency_ms"]["p50"]
+        res["latency_ms"]["serving_p99"] = res["serving"]["latency_ms"]["p99"]
     if a.cpu_seconds > 0:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(circ, openq, bits, plan, a.cpu_seconds)

@@ -840,9 +840,9 @@ void contract(rqc_plan* p, const uint64_t* ids_in, uint64_t n_ids, const uint8_t
   r.flops = (pd.flops_per_slice * (double)n_ids + pd.flops_per_bitstring) * (double)n_batch;
 }
 
-void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep) {
+void report(rqc_plan* p, PendingRun& r, hipStream_t s, rqc_run_report* rep, bool sync) {
   std::memset(rep, 0, sizeof *rep);
-  hip_check(hipStreamSynchronize(s), "synchronize");
+  if (sync) hip_check(hipStreamSynchronize(s), "synchronize");
   if (!r.active) return;
   p->last_timing = rqc_timing{};
   p->tms.clear();

@@ -169,7 +169,10 @@ void calibrate(rqc_plan* p, int prec, uint64_t slice_id, const uint8_t* bits, do
                double err_floor, void* ws, size_t ws_bytes, hipStream_t s, rqc_calib_report* rep);
 
 // Synchronise `s`, re-run flagged slices in FP32, fill the report.
-void report(rqc_plan* p, PendingRun& run, hipStream_t s, rqc_run_report* r);
+// sync = false: the caller knows the call's work has completed (for example
+// from an event recorded after it) and `s` is not synchronised; it is only
+// used for an FP32 re-run.
+void report(rqc_plan* p, PendingRun& run, hipStream_t s, rqc_run_report* r, bool sync = true);
 
 // Build the descriptor of one pairwise contraction given operand labels
 // (MSB first).  `kernel` is the requested kind (-1: choose) and returns the

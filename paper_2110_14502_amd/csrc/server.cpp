@@ -1,12 +1,17 @@
 // Serving loop: continuous batching of amplitude requests.
 //
 // A worker thread owns the device work.  Requests wait in arrival order;
-// the worker admits them as in-flight slots and device memory free up
-// (plans stay resident between requests and are evicted least-recently
-// used), merges waiting requests that share a plan into one batched
-// contraction (the bitstrings become the batch dimension of every step),
-// launches each call on one of several HIP streams so that calls overlap on
-// the device, and completes a request when its stream event fires.
+// the worker admits, oldest first, those whose plan is resident or built, as
+// in-flight slots and device memory free up (plans stay resident between
+// requests and are evicted least-recently used), merges waiting requests
+// that share a plan into one batched contraction (the bitstrings become the
+// batch dimension of every step), launches each call directly (no graph
+// capture on the request's path) on one of several HIP streams so that calls
+// overlap on the device, and completes a request when its call's event
+// fires, without synchronising the shared streams.  Plans of new circuits are
+// searched on host threads of their own, so that a request whose plan is
+// being searched does not hold up the requests behind it; they are bound on
+// a stream of their own.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +20,7 @@
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <future>
 #include <list>
 #include <map>
 #include <thread>
@@ -100,6 +106,33 @@ struct Call {
   double t_start = 0;
 };
 
+// A plan searched on a host thread.
+struct Built {
+  rqc_plan* plan = nullptr;
+  rqc_status st = RQC_OK;
+};
+
+Built build_plan(Req r) {
+  Built b;
+  rqc_circuit* c = nullptr;
+  rqc_network* n = nullptr;
+  b.st = rqc_circuit_create(r.n_qubits, r.gates.data(), r.gates.size(), &c);
+  if (b.st == RQC_OK) b.st = rqc_network_create(c, r.open.data(), (int32_t)r.open.size(), &n);
+  if (b.st == RQC_OK) {
+    rqc_plan_opts o;
+    rqc_plan_opts_default(&o);
+    o.max_log2_elems = r.max_log2 > 0 ? r.max_log2 : 26;
+    // The first request of a circuit waits for this search: a short one.
+    o.path_trials = 32;
+    o.reconf_rounds = 1;
+    o.seed = r.seed;
+    b.st = rqc_plan_create(n, &o, &b.plan);
+  }
+  rqc_network_destroy(n);
+  rqc_circuit_destroy(c);
+  return b;
+}
+
 uint64_t fnv(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
   const unsigned char* c = static_cast<const unsigned char*>(p);
   for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
@@ -121,6 +154,8 @@ struct rqc_server {
   std::unordered_map<uint64_t, rqc::PlanEntry> plans;
   rqc::Pool pool;
   std::vector<hipStream_t> streams;
+  hipStream_t bind_stream = nullptr;
+  std::unordered_map<uint64_t, std::future<rqc::Built>> building;  // worker thread only
   uint64_t next_ticket = 1;
   uint64_t outstanding = 0;
   bool stop = false;
@@ -148,16 +183,36 @@ void rqc_server::fail(const rqc::Req& r, rqc_status st) {
   done_cv.notify_all();
 }
 
-// Admit the oldest waiting request (plus waiting requests sharing its plan).
-// Returns false when nothing could be admitted now.
+// Admit the oldest waiting request whose plan is resident or built (plus the
+// waiting requests sharing that plan); start the search of plans not seen
+// yet.  Returns false when nothing could be admitted now.
 bool rqc_server::admit_one() {
   std::vector<rqc::Req> batch;
+  uint64_t key = 0;
+  int prec = 0;
   {
     std::lock_guard<std::mutex> g(mu);
     if (queue.empty()) return false;
     if ((int)calls.size() >= opts.max_inflight) return false;
-    const uint64_t key = queue.front().key;
-    const int prec = queue.front().prec;
+    bool found = false;
+    for (const rqc::Req& r : queue) {
+      if (plans.count(r.key)) {
+        found = true;
+      } else {
+        auto b = building.find(r.key);
+        if (b == building.end()) {
+          building.emplace(r.key, std::async(std::launch::async, rqc::build_plan, r));
+        } else if (b->second.wait_for(std::chrono::seconds(0)) == std::future_status::ready) {
+          found = true;
+        }
+      }
+      if (found) {
+        key = r.key;
+        prec = r.prec;
+        break;
+      }
+    }
+    if (!found) return false;
     for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < opts.max_batch;) {
       if (it->key == key && it->prec == prec) {
         batch.push_back(std::move(*it));
@@ -172,34 +227,22 @@ bool rqc_server::admit_one() {
     std::lock_guard<std::mutex> g(mu);
     for (auto it = batch.rbegin(); it != batch.rend(); ++it) queue.push_front(std::move(*it));
   };
-  // Plan: reuse or build.
+  // Plan: resident, or searched and now bound on the bind stream.
   rqc::PlanEntry* pe = nullptr;
-  auto pit = plans.find(r0.key);
+  auto pit = plans.find(key);
   if (pit != plans.end()) {
     pe = &pit->second;
     stats.plans_reused++;
   } else {
-    rqc_circuit* c = nullptr;
-    rqc_network* n = nullptr;
-    rqc_plan* p = nullptr;
-    rqc_status st = rqc_circuit_create(r0.n_qubits, r0.gates.data(), r0.gates.size(), &c);
-    if (st == RQC_OK) st = rqc_network_create(c, r0.open.data(), (int32_t)r0.open.size(), &n);
-    if (st == RQC_OK) {
-      rqc_plan_opts o;
-      rqc_plan_opts_default(&o);
-      o.max_log2_elems = r0.max_log2 > 0 ? r0.max_log2 : 26;
-      // Planning sits on the request's latency path: a short search.
-      o.path_trials = 32;
-      o.reconf_rounds = 1;
-      o.seed = r0.seed;
-      st = rqc_plan_create(n, &o, &p);
-    }
-    rqc_network_destroy(n);
-    rqc_circuit_destroy(c);
-    if (st != RQC_OK) {
-      for (auto& r : batch) fail(r, st);
+    auto bit = building.find(key);
+    rqc::Built b = bit->second.get();
+    building.erase(bit);
+    if (b.st != RQC_OK) {
+      rqc_plan_destroy(b.plan);
+      for (auto& r : batch) fail(r, b.st);
       return true;
     }
+    rqc_plan* p = b.plan;
     size_t rb = 0;
     rqc_plan_resident_bytes(p, &rb);
     char* res = pool.alloc(rb);
@@ -216,21 +259,25 @@ bool rqc_server::admit_one() {
       res = pool.alloc(rb);
     }
     if (!res) {
-      rqc_plan_destroy(p);
       if (calls.empty()) {
+        rqc_plan_destroy(p);
         for (auto& r : batch) fail(r, RQC_EHBM);
         return true;
       }
+      // Keep the searched plan for when memory frees up.
+      std::promise<rqc::Built> keep;
+      keep.set_value(b);
+      building.emplace(key, keep.get_future());
       requeue();
       return false;
     }
-    if (rqc_plan_bind_memory(p, res, rb, streams[0]) != RQC_OK) {
+    if (rqc_plan_bind_memory(p, res, rb, bind_stream) != RQC_OK) {
       pool.free(res);
       rqc_plan_destroy(p);
       for (auto& r : batch) fail(r, RQC_EDEVICE);
       return true;
     }
-    pe = &plans[r0.key];
+    pe = &plans[key];
     pe->plan = p;
     pe->res = res;
     stats.plans_built++;
@@ -290,7 +337,7 @@ bool rqc_server::admit_one() {
   hipStream_t s = streams[call.stream];
   try {
     rqc::contract(pe->plan, nullptr, 0, bits.data(), nb, r0.prec, ws, ws_bytes, call.out, nullptr, s,
-                  call.run);
+                  call.run, /*direct=*/true);
     rqc::hip_check(hipEventCreateWithFlags(&call.ev, hipEventDisableTiming), "event");
     rqc::hip_check(hipEventRecord(call.ev, s), "event record");
   } catch (const rqc::Error& e) {
@@ -316,7 +363,7 @@ void rqc_server::complete(rqc::Call& c, rqc_status st) {
   hipStream_t s = streams[c.stream];
   if (st == RQC_OK) {
     try {
-      rqc::report(c.pe->plan, c.run, s, &rep);
+      rqc::report(c.pe->plan, c.run, s, &rep, /*sync=*/false);
     } catch (const rqc::Error& e) {
       st = e.code;
     }
@@ -375,7 +422,9 @@ void rqc_server::loop() {
     std::unique_lock<std::mutex> lk(mu);
     if (stop && queue.empty() && calls.empty()) break;
     if (!progressed) {
-      if (calls.empty()) cv.wait(lk, [&] { return stop || !queue.empty(); });
+      // Idle: wait for a request; with calls in flight or plans being
+      // searched, poll their events and futures.
+      if (calls.empty() && building.empty()) cv.wait(lk, [&] { return stop || !queue.empty(); });
       else cv.wait_for(lk, std::chrono::microseconds(200));
     }
   }
@@ -406,15 +455,17 @@ rqc_status rqc_server_create(const rqc_server_opts* o, rqc_server** out) {
     rqc::set_error("hipSetDevice failed");
     return RQC_EDEVICE;
   }
-  for (int i = 0; i < s->opts.n_streams; ++i) {
+  for (int i = 0; i <= s->opts.n_streams; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
       for (auto x : s->streams) (void)hipStreamDestroy(x);
+      if (s->bind_stream) (void)hipStreamDestroy(s->bind_stream);
       delete s;
       rqc::set_error("stream creation failed");
       return RQC_EDEVICE;
     }
-    s->streams.push_back(st);
+    if (i == s->opts.n_streams) s->bind_stream = st;
+    else s->streams.push_back(st);
   }
   s->worker = std::thread([s] { s->loop(); });
   *out = s;
@@ -499,8 +550,13 @@ void rqc_server_destroy(rqc_server* s) {
     s->cv.notify_all();
   }
   if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->building) {
+    rqc::Built b = kv.second.get();
+    rqc_plan_destroy(b.plan);
+  }
   for (auto& kv : s->plans) rqc_plan_destroy(kv.second.plan);
   for (auto x : s->streams) (void)hipStreamDestroy(x);
+  if (s->bind_stream) (void)hipStreamDestroy(s->bind_stream);
   delete s;
 }
 

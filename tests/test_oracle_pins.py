@@ -344,3 +344,28 @@ def test_contract_ordered_rejects_bad_groups():
     tensors, out = otn.build_network(c, [0], [0, 1, 1])
     with pytest.raises(ValueError):
         oracle.contract_ordered(tensors, out, [[0, 1]], [])
+
+
+def test_ttgt_example_section_5_4():
+    """The worked example of Section 5.4: A[a,b,c,d,e,f,g] (7 indices) and
+    B[h,a,f,i] contracted over {a,f} into C[b,c,d,e,g,h,i].  The paper's
+    procedure -- B permuted to B^T[a,f,h,i], A permuted so that the kept
+    indices come first and the summed ones last, one matrix product, the
+    result in the order of C -- done here with numpy transposes and a matrix
+    product, must equal the oracle's single step (einsum)."""
+    a, b, c, d, e, f, g, h, i = range(9)
+    rng = np.random.default_rng(54)
+    A = rng.standard_normal(2 ** 7) + 1j * rng.standard_normal(2 ** 7)
+    B = rng.standard_normal(2 ** 4) + 1j * rng.standard_normal(2 ** 4)
+    la, lb, lc = [a, b, c, d, e, f, g], [h, a, f, i], [b, c, d, e, g, h, i]
+    At = A.reshape((2,) * 7).transpose(1, 2, 3, 4, 6, 0, 5).reshape(2 ** 5, 2 ** 2)  # [bcdeg | af]
+    Bt = B.reshape((2,) * 4).transpose(1, 2, 0, 3).reshape(2 ** 2, 2 ** 2)            # [af | hi]
+    C = (At @ Bt).reshape(-1)                                                          # [bcdeg hi]
+    ref = oracle.einsum_step(A, B, la, lb, lc)
+    assert np.max(np.abs(C - ref)) < 1e-13
+    # and an index-by-index sum for one entry
+    cb, cc, cd, ce, cg, ch, ci = 1, 0, 1, 1, 0, 1, 0
+    direct = sum(A.reshape((2,) * 7)[ka, cb, cc, cd, ce, kf, cg] * B.reshape((2,) * 4)[ch, ka, kf, ci]
+                 for ka in (0, 1) for kf in (0, 1))
+    idx = int("".join(map(str, (cb, cc, cd, ce, cg, ch, ci))), 2)
+    assert abs(ref[idx] - direct) < 1e-13
