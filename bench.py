@@ -38,11 +38,13 @@ KIND_LABELS = {
 }
 TIME_ALL = 4
 GOLDEN_CONFIG2 = os.path.join(ROOT, "tests", "golden", "config2_amplitudes.txt")
-# Counter summaries (FETCH_SIZE / WRITE_SIZE) of the dominant kernel of the
-# default amplitude workload, per kernel kind.
-TRAFFIC_PROFILES = {1: "k_mfma32_config2_6x6x14_fp32_traffic.md",
-                    2: "k_rows_config2_6x6x14_fp32_traffic.md",
-                    0: "k_simt_config2_6x6x14_fp32_traffic.md"}
+# Counter summaries (FETCH_SIZE / WRITE_SIZE) of the kernels of the default
+# amplitude workload, per (kernel kind, precision of the leg).
+TRAFFIC_PROFILES = {(1, "f32"): "k_mfma32_config2_6x6x14_fp32_traffic.md",
+                    (2, "f32"): "k_rows_config2_6x6x14_fp32_traffic.md",
+                    (0, "f32"): "k_simt_config2_6x6x14_fp32_traffic.md",
+                    (3, "f16"): "k_mfma16_config2_6x6x14_fp16_traffic.md",
+                    (2, "f16"): "k_rows_config2_6x6x14_fp16_traffic.md"}
 
 
 def parse():
@@ -60,6 +62,8 @@ def parse():
     ap.add_argument("--kprec", default="f32", choices=["f32", "f16", "bf16"],
                     help="kernel mode: arithmetic")
     ap.add_argument("--cases", type=int, default=12, help="steps mode: number of synthetic cases")
+    ap.add_argument("--max-cases", type=int, default=0,
+                    help="steps mode: 1 adds the (32,32,16) and (32,24,12) cases (32 GiB tensors)")
     ap.add_argument("--requests", type=int, default=600, help="serve mode: Poisson requests")
     ap.add_argument("--load", type=float, default=0.8, help="serve mode: rate / saturation rate")
     ap.add_argument("--budget-gb", type=float, default=192.0,
@@ -198,13 +202,13 @@ def kernel_source_hash(root, kind):
     return h.hexdigest()
 
 
-def _profile_traffic(kind, flops_per_launch, bytes_per_launch):
-    """HBM bytes per launch of the dominant kernel from a committed counter
+def _profile_traffic(kind, prec, flops_per_launch, bytes_per_launch):
+    """HBM bytes per launch of a kernel kind from a committed counter
     summary, or None when the summary does not match: the kernel sources
     changed since the counters were taken, or its launches were different."""
     root = os.path.dirname(os.path.abspath(__file__))
     try:
-        text = open(os.path.join(root, "profiles", TRAFFIC_PROFILES[kind])).read()
+        text = open(os.path.join(root, "profiles", TRAFFIC_PROFILES[(kind, prec)])).read()
     except (OSError, KeyError):
         return None
     vals = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
@@ -320,7 +324,7 @@ def roofline(kind, tim, a, flops_total, kind_ms):
     return {
         "bound": bound, "kernel": label, "achieved": achieved, "peak": peak, "unit": unit,
         "frac": achieved / peak,
-        "traffic": _profile_traffic(kind, fpl, bpl) if a.prec == "f32" else None,
+        "traffic": _profile_traffic(kind, a.prec, fpl, bpl),
         "algorithmic_bytes_per_launch": bpl,
         "flops_per_launch": fpl,
         "launches": tim["launches"],
@@ -331,7 +335,7 @@ def roofline(kind, tim, a, flops_total, kind_ms):
     }
 
 
-def launch_table(launches, n_reps=1):
+def launch_table(launches, n_reps=1, prec="f32"):
     """Per-launch roofline: t_min = max(F / P, B / 8 TB/s) with P the matrix
     peak of the launch's arithmetic (FP32 157.3 TFLOP/s; 16-bit matrix cores
     2.5 PFLOP/s), F and B the algorithmic flops and bytes; and per kernel
@@ -376,7 +380,10 @@ def launch_table(launches, n_reps=1):
             "roofline_frac": k["t_min_ms"] / k["ms"] if k["ms"] > 0 else None,
             "ms_per_step": k["ms"], "t_min_ms_per_step": k["t_min_ms"],
             "achieved_tflops": k["flops"] / secs / 1e12, "achieved_gbs": k["bytes"] / secs / 1e9,
-            "launches": k["launches"]}
+            "launches": k["launches"],
+            "traffic": _profile_traffic(kind, prec, k["flops"] / k["launches"],
+                                        k["bytes"] / k["launches"]),
+            "algorithmic_bytes_per_launch": k["bytes"] / k["launches"]}
     return rows, out
 
 
@@ -470,12 +477,19 @@ def kernel_mode(a):
 
 def steps_mode(a):
     """Synthetic pairwise contractions of complex64 tensors of rank 24..32
-    with random index orders: the fused kernel vs permute + GEMM + permute."""
+    with random index orders: the fused kernel (FP32, or FP16/BF16 matrix
+    cores with --kprec) vs permute + our GEMM + permute and vs permute +
+    the vendor complex GEMM (torch.matmul, rocBLAS/hipBLASLt) + permute;
+    --max-cases adds the two largest cases, (32, 32, 16) and (32, 24, 12)."""
     import numpy as np
     import torch
     import rqcgen
     import paper_2110_14502_amd as R
     cases = rqcgen.synthetic_step_cases(3, n_cases=a.cases)
+    if a.max_cases:
+        cases += [rqcgen.synthetic_step(32, 32, 16, 71), rqcgen.synthetic_step(32, 24, 12, 72)]
+    kp = R.PRECISIONS[a.kprec]
+    peak = PEAK_MFMA_FP32 if kp == R.F32 else PEAK_MFMA_16
     out = []
     for st in cases:
         ra, rb, rc = len(st.labels_a), len(st.labels_b), len(st.labels_c)
@@ -488,27 +502,50 @@ def steps_mode(a):
         Nf = [x for x in st.labels_b if x not in K]
         m, n, k = len(Mf), len(Nf), len(K)
         fl = 8.0 * 2.0 ** (m + n + k)
+        reps = a.reps if m + n + k <= 40 else 1
+        log(f"steps case mnk=({m},{n},{k}) prec={a.kprec}: fused")
         t_f = _events_time(lambda: R.pair_contract(A, B, st.labels_a, st.labels_b, st.labels_c,
-                                                   C_out=C), a.reps)
-        A2, B2, C2 = torch.empty_like(A), torch.empty_like(B), torch.empty_like(C)
+                                                   C_out=C, prec=kp), reps)
+        row = {"ranks": [ra, rb, rc], "mnk": [m, n, k], "prec": a.kprec, "fused_ms": t_f,
+               "fused_tflops": fl / t_f / 1e9, "fused_frac_of_peak": fl / t_f / 1e9 / peak}
+        if kp == R.F32:
+            A2, B2, C2 = torch.empty_like(A), torch.empty_like(B), torch.empty_like(C)
 
-        def unfused():
-            R.permute(A, st.labels_a, Mf + K, out=A2)
-            R.permute(B, st.labels_b, K + Nf, out=B2)
-            R.cgemm(A2, B2, 1 << m, 1 << n, 1 << k, out=C2)
-            R.permute(C2, Mf + Nf, st.labels_c, out=C)
-        t_u = _events_time(unfused, a.reps)
-        row = {"ranks": [ra, rb, rc], "mnk": [m, n, k], "fused_ms": t_f, "unfused_ms": t_u,
-               "fused_tflops": fl / t_f / 1e9, "unfused_tflops": fl / t_u / 1e9,
-               "speedup": t_u / t_f}
+            def unfused():
+                R.permute(A, st.labels_a, Mf + K, out=A2)
+                R.permute(B, st.labels_b, K + Nf, out=B2)
+                R.cgemm(A2, B2, 1 << m, 1 << n, 1 << k, out=C2)
+                R.permute(C2, Mf + Nf, st.labels_c, out=C)
+
+            def unfused_vendor():
+                R.permute(A, st.labels_a, Mf + K, out=A2)
+                R.permute(B, st.labels_b, K + Nf, out=B2)
+                torch.matmul(A2.view(1 << m, 1 << k), B2.view(1 << k, 1 << n),
+                             out=C2.view(1 << m, 1 << n))
+                R.permute(C2, Mf + Nf, st.labels_c, out=C)
+            log(f"  fused {t_f:.3f} ms; permute + our GEMM + permute")
+            t_u = _events_time(unfused, reps)
+            log(f"  {t_u:.3f} ms; permute + vendor GEMM + permute")
+            t_v = _events_time(unfused_vendor, reps)
+            log(f"  {t_v:.3f} ms; vendor GEMM alone")
+            t_g = _events_time(lambda: torch.matmul(A2.view(1 << m, 1 << k), B2.view(1 << k, 1 << n),
+                                                    out=C2.view(1 << m, 1 << n)), reps)
+            row.update({"unfused_ms": t_u, "unfused_tflops": fl / t_u / 1e9, "speedup": t_u / t_f,
+                        "unfused_vendor_ms": t_v, "speedup_vs_vendor_unfused": t_v / t_f,
+                        "vendor_gemm_only_tflops": fl / t_g / 1e9})
+            del A2, B2, C2
         log(json.dumps(row))
         out.append(row)
-        del A, B, C, A2, B2, C2
+        del A, B, C
         torch.cuda.empty_cache()
-    gm = float(np.exp(np.mean([np.log(r["speedup"]) for r in out])))
-    print(json.dumps({"mode": "steps", "cases": out, "geomean_speedup": gm,
-                      "median_fused_tflops": float(np.median([r["fused_tflops"] for r in out]))}),
-          flush=True)
+    res = {"mode": "steps", "prec": a.kprec, "cases": out,
+           "median_fused_tflops": float(np.median([r["fused_tflops"] for r in out])),
+           "median_frac_of_peak": float(np.median([r["fused_frac_of_peak"] for r in out]))}
+    if kp == R.F32:
+        res["geomean_speedup"] = float(np.exp(np.mean([np.log(r["speedup"]) for r in out])))
+        res["geomean_speedup_vs_vendor_unfused"] = float(
+            np.exp(np.mean([np.log(r["speedup_vs_vendor_unfused"]) for r in out])))
+    print(json.dumps(res), flush=True)
 
 
 def run_serving(n_requests, load, budget_gb, grids, depths, circuits_per_family, burst):
@@ -918,7 +955,7 @@ def main():
     step(prec, "warm")
     plan.set_timing(TIME_ALL)
     step(prec, "probe all kernels")
-    table, by_kind = launch_table(plan.launch_timings())
+    table, by_kind = launch_table(plan.launch_timings(), prec=a.prec)
     kind_ms = {k: v["ms_per_step"] / frac for k, v in by_kind.items()}
     names = {v: k for k, v in KIND_NAMES.items()}
     dom = names[max(by_kind, key=lambda k: by_kind[k]["ms_per_step"])]
@@ -1025,7 +1062,7 @@ def main():
         step16("f16 warmup")
         lp_plan.set_timing(TIME_ALL)
         step16("f16 probe all kernels")
-        table16, by_kind16 = launch_table(lp_plan.launch_timings())
+        table16, by_kind16 = launch_table(lp_plan.launch_timings(), prec="f16")
         lp_plan.set_timing(-1)
         step16("f16 graph capture")
         torch.cuda.synchronize()
