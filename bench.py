@@ -503,11 +503,15 @@ def steps_mode(a):
         m, n, k = len(Mf), len(Nf), len(K)
         fl = 8.0 * 2.0 ** (m + n + k)
         reps = a.reps if m + n + k <= 40 else 1
-        log(f"steps case mnk=({m},{n},{k}) prec={a.kprec}: fused")
+        need = R.pair_workspace_bytes(st.labels_a, st.labels_b, st.labels_c, prec=kp)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda") if need else None
+        form = "two-phase (permute + convert, 16-bit GEMM)" if need else "fused"
+        log(f"steps case mnk=({m},{n},{k}) prec={a.kprec}: {form}")
         t_f = _events_time(lambda: R.pair_contract(A, B, st.labels_a, st.labels_b, st.labels_c,
-                                                   C_out=C, prec=kp), reps)
-        row = {"ranks": [ra, rb, rc], "mnk": [m, n, k], "prec": a.kprec, "fused_ms": t_f,
-               "fused_tflops": fl / t_f / 1e9, "fused_frac_of_peak": fl / t_f / 1e9 / peak}
+                                                   C_out=C, prec=kp, workspace=ws), reps)
+        row = {"ranks": [ra, rb, rc], "mnk": [m, n, k], "prec": a.kprec, "form": form,
+               "fused_ms": t_f, "fused_tflops": fl / t_f / 1e9,
+               "fused_frac_of_peak": fl / t_f / 1e9 / peak}
         if kp == R.F32:
             A2, B2, C2 = torch.empty_like(A), torch.empty_like(B), torch.empty_like(C)
 
@@ -536,7 +540,7 @@ def steps_mode(a):
             del A2, B2, C2
         log(json.dumps(row))
         out.append(row)
-        del A, B, C
+        del A, B, C, ws
         torch.cuda.empty_cache()
     res = {"mode": "steps", "prec": a.kprec, "cases": out,
            "median_fused_tflops": float(np.median([r["fused_tflops"] for r in out])),

@@ -286,6 +286,41 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a,
                              int64_t stride_b, int64_t stride_c,
                              int32_t kernel, int32_t prec, rqc_stream stream);
 
+/* Device workspace that rqc_pair_contract_ws needs for this call, in bytes
+ * (*bytes = 0: the call runs without one, exactly as rqc_pair_contract).
+ * Nonzero only for automatic kernel choice (kernel -1) in RQC_F16 /
+ * RQC_BF16 when the sum has at least 2^8 terms and m >= 8, n >= 7 (at least
+ * one 256 x 128 output tile): then the call takes the two-phase long-sum
+ * form of Sections 5.4 and 5.5 (each operand permuted into a plain
+ * [free][summed] matrix of packed 16-bit values, then a 16-bit matrix-core
+ * GEMM that writes C in its own layout); the workspace holds the two packed
+ * operands, 4 bytes per element per distinct operand copy (a copy stride of
+ * 0 shares one copy), and, when the output has fewer than 1024 tiles of
+ * 256 x 128, FP32 partial outputs of a split sum (8 bytes per output
+ * element per split, summed afterwards in split order).  Arguments as in
+ * rqc_pair_contract; EINVAL on bad labels or ranks. */
+rqc_status rqc_pair_workspace_bytes(const int32_t* labels_a, int32_t rank_a,
+                                    const int32_t* labels_b, int32_t rank_b,
+                                    const int32_t* labels_c, int32_t rank_c,
+                                    int32_t batch_count, int64_t stride_a,
+                                    int64_t stride_b, int32_t kernel, int32_t prec,
+                                    uint64_t* bytes);
+
+/* rqc_pair_contract with a caller-owned device workspace of ws_bytes
+ * (256-byte aligned, at least rqc_pair_workspace_bytes; its contents are
+ * overwritten).  Operands are rounded to 16 bits without scaling (values
+ * must lie in the 16-bit range) and products accumulate in FP32; C is
+ * complex64.  With a batch, stride_c must be at least one output.  Calls
+ * that need no workspace behave exactly as rqc_pair_contract. */
+rqc_status rqc_pair_contract_ws(const int32_t* labels_a, int32_t rank_a,
+                                const int32_t* labels_b, int32_t rank_b,
+                                const int32_t* labels_c, int32_t rank_c,
+                                const void* A, const void* B, void* C,
+                                int32_t batch_count, int64_t stride_a,
+                                int64_t stride_b, int64_t stride_c,
+                                int32_t kernel, int32_t prec, void* workspace,
+                                uint64_t ws_bytes, rqc_stream stream);
+
 /* Bit permutation of a complex64 tensor: out (labels_out) = in (labels_in).
  * The separate-permutation baseline of Section 5.4. */
 rqc_status rqc_permute(const int32_t* labels_in, const int32_t* labels_out,

@@ -149,6 +149,14 @@ _PROTOS = {
     "rqc_pair_contract": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                C.POINTER(C.c_int32), C.c_int32, _P, _P, _P, C.c_int32,
                                C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P]),
+    "rqc_pair_workspace_bytes": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32),
+                                      C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                      C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_uint64)]),
+    "rqc_pair_contract_ws": (_S, [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                  C.POINTER(C.c_int32), C.c_int32, _P, _P, _P, C.c_int32,
+                                  C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, _P,
+                                  C.c_uint64, _P]),
     "rqc_permute": (_S, [C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32, _P, _P, _P]),
     "rqc_batch_xeb": (_S, [_P, C.c_uint64, C.c_int32, _P, C.c_uint64, _P, _P]),
     "rqc_contract_noalloc": (_S, [_P, C.POINTER(C.c_uint64), C.c_uint64, C.POINTER(C.c_uint8),
@@ -516,13 +524,40 @@ def to_complex(t):
 
 
 # ---------------------------------------------------------------- single steps
+def pair_workspace_bytes(labels_a, labels_b, labels_c, kernel=-1, batch=1, stride_a=0,
+                         stride_b=0, prec=F32):
+    """Device workspace (bytes) that a pair_contract call needs (0: none)."""
+    n = C.c_uint64()
+    _check(_lib.rqc_pair_workspace_bytes(_i32(labels_a), len(labels_a), _i32(labels_b),
+                                         len(labels_b), _i32(labels_c), len(labels_c), int(batch),
+                                         int(stride_a), int(stride_b), int(kernel), int(prec),
+                                         C.byref(n)))
+    return n.value
+
+
 def pair_contract(A, B, labels_a, labels_b, labels_c, C_out=None, kernel=-1, batch=1,
-                  stride_a=0, stride_b=0, stride_c=0, prec=F32, stream=None):
-    """C = A * B summed over shared labels (complex64 torch tensors on device)."""
+                  stride_a=0, stride_b=0, stride_c=0, prec=F32, stream=None, workspace=None):
+    """C = A * B summed over shared labels (complex64 torch tensors on
+    device).  A 16-bit call with a long sum takes the two-phase form and
+    needs a device workspace (pair_workspace_bytes); one is allocated with
+    torch unless `workspace` (a uint8 device tensor) is given."""
     import torch
+    prec = PRECISIONS.get(prec, prec) if isinstance(prec, str) else int(prec)
     if C_out is None:
         C_out = torch.empty(batch << len(labels_c), dtype=torch.complex64, device=A.device)
         stride_c = 1 << len(labels_c) if batch > 1 else stride_c
+    need = pair_workspace_bytes(labels_a, labels_b, labels_c, kernel, batch, stride_a, stride_b,
+                                prec)
+    if need:
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+        _check(_lib.rqc_pair_contract_ws(_i32(labels_a), len(labels_a), _i32(labels_b),
+                                         len(labels_b), _i32(labels_c), len(labels_c), _ptr(A),
+                                         _ptr(B), _ptr(C_out), int(batch), int(stride_a),
+                                         int(stride_b), int(stride_c), int(kernel), int(prec),
+                                         _ptr(workspace), int(workspace.numel()),
+                                         _stream_handle(stream)))
+        return C_out
     _check(_lib.rqc_pair_contract(_i32(labels_a), len(labels_a), _i32(labels_b), len(labels_b),
                                   _i32(labels_c), len(labels_c), _ptr(A), _ptr(B), _ptr(C_out),
                                   int(batch), int(stride_a), int(stride_b), int(stride_c),

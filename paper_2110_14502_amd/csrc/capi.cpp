@@ -409,6 +409,162 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a, const int3
   RQC_CATCH
 }
 
+}  // extern "C"
+
+namespace {
+
+// Two-phase long-sum form of a 16-bit contraction (permute + convert each
+// operand, then k_gemm16): taken by automatic kernel choice in FP16 / BF16
+// when the sum has at least 2^kGemm16MinK terms and the output at least one
+// 256 x 128 tile.  m < 0: the call does not take it.
+constexpr int kGemm16MinK = 8;
+struct Gemm16Shape {
+  int m = -1, n = 0, k = 0, ksplit = 0;
+  std::vector<int> Mf, Nf, K;  // A's free labels, B's free labels, summed labels (A's order)
+  uint64_t bytes_a = 0, bytes_b = 0, bytes_p = 0, copies_a = 1, copies_b = 1;
+  uint64_t total() const { return bytes_a + bytes_b + bytes_p; }
+};
+
+Gemm16Shape gemm16_shape(const std::vector<int>& la, const std::vector<int>& lb, int32_t batch,
+                         int64_t stride_a, int64_t stride_b, int32_t kernel, int32_t prec) {
+  Gemm16Shape g;
+  if ((prec != RQC_F16 && prec != RQC_BF16) || kernel != -1) return g;
+  for (int x : la) (std::find(lb.begin(), lb.end(), x) != lb.end() ? g.K : g.Mf).push_back(x);
+  for (int x : lb)
+    if (std::find(la.begin(), la.end(), x) == la.end()) g.Nf.push_back(x);
+  if ((int)g.K.size() < kGemm16MinK || g.Mf.size() < 8 || g.Nf.size() < 7) return g;
+  g.m = (int)g.Mf.size();
+  g.n = (int)g.Nf.size();
+  g.k = (int)g.K.size();
+  g.copies_a = stride_a ? (uint64_t)batch : 1;
+  g.copies_b = stride_b ? (uint64_t)batch : 1;
+  g.bytes_a = ((g.copies_a << (g.m + g.k)) * 4 + 255) & ~uint64_t(255);
+  g.bytes_b = ((g.copies_b << (g.n + g.k)) * 4 + 255) & ~uint64_t(255);
+  // Split the sum while the output tiles cannot fill the GPU (1024 work
+  // items: four per CU), keeping at least 16 chunks of 32 terms per split.
+  const uint64_t tiles = (uint64_t)batch << (g.m - 8 + g.n - 7);
+  while ((tiles << g.ksplit) < 1024 && g.k - 5 - g.ksplit > 4) ++g.ksplit;
+  if (g.ksplit) g.bytes_p = (((uint64_t)batch << g.ksplit) << (g.m + g.n)) * 8;
+  return g;
+}
+
+// Output bit i of the permutation of `in` into `out` order: its input bit.
+std::vector<int8_t> perm_sources(const std::vector<int>& in, const std::vector<int>& out) {
+  const int r = (int)in.size();
+  std::vector<int8_t> src(r);
+  for (int i = 0; i < r; ++i) {
+    const int pos = (int)(std::find(in.begin(), in.end(), out[r - 1 - i]) - in.begin());
+    src[i] = (int8_t)(r - 1 - pos);
+  }
+  return src;
+}
+
+// Labels of a pairwise call, validated (ranks, NULLs, repeats, batch).
+void pair_labels(const int32_t* labels_a, int32_t rank_a, const int32_t* labels_b, int32_t rank_b,
+                 const int32_t* labels_c, int32_t rank_c, int32_t batch_count, std::vector<int>& la,
+                 std::vector<int>& lb, std::vector<int>& lc) {
+  if (rank_a < 0 || rank_b < 0 || rank_c < 0 || rank_a > 40 || rank_b > 40 || rank_c > 40)
+    throw rqc::Error{RQC_EINVAL, "rank out of range"};
+  if ((rank_a && !labels_a) || (rank_b && !labels_b) || (rank_c && !labels_c))
+    throw rqc::Error{RQC_EINVAL, "NULL labels"};
+  if (batch_count < 1 || batch_count > 65535) throw rqc::Error{RQC_EINVAL, "batch_count out of range"};
+  la.assign(labels_a, labels_a + rank_a);
+  lb.assign(labels_b, labels_b + rank_b);
+  lc.assign(labels_c, labels_c + rank_c);
+  for (auto* l : {&la, &lb, &lc}) {
+    std::vector<int> v(*l);
+    std::sort(v.begin(), v.end());
+    if (std::adjacent_find(v.begin(), v.end()) != v.end()) throw rqc::Error{RQC_EINVAL, "repeated label"};
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+rqc_status rqc_pair_workspace_bytes(const int32_t* labels_a, int32_t rank_a,
+                                    const int32_t* labels_b, int32_t rank_b,
+                                    const int32_t* labels_c, int32_t rank_c, int32_t batch_count,
+                                    int64_t stride_a, int64_t stride_b, int32_t kernel,
+                                    int32_t prec, uint64_t* bytes) {
+  RQC_TRY
+  if (!bytes) throw rqc::Error{RQC_EINVAL, "NULL argument"};
+  std::vector<int> la, lb, lc;
+  pair_labels(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, batch_count, la, lb, lc);
+  const Gemm16Shape g = gemm16_shape(la, lb, batch_count, stride_a, stride_b, kernel, prec);
+  *bytes = g.m < 0 ? 0 : g.total();
+  return RQC_OK;
+  RQC_CATCH
+}
+
+rqc_status rqc_pair_contract_ws(const int32_t* labels_a, int32_t rank_a, const int32_t* labels_b,
+                                int32_t rank_b, const int32_t* labels_c, int32_t rank_c,
+                                const void* A, const void* B, void* C, int32_t batch_count,
+                                int64_t stride_a, int64_t stride_b, int64_t stride_c,
+                                int32_t kernel, int32_t prec, void* workspace,
+                                uint64_t ws_bytes, rqc_stream stream) {
+  RQC_TRY
+  std::vector<int> la, lb, lc;
+  pair_labels(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, batch_count, la, lb, lc);
+  const Gemm16Shape g = gemm16_shape(la, lb, batch_count, stride_a, stride_b, kernel, prec);
+  if (g.m < 0)
+    return rqc_pair_contract(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, A, B, C,
+                             batch_count, stride_a, stride_b, stride_c, kernel, prec, stream);
+  if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
+  if (!workspace || ws_bytes < g.total())
+    throw rqc::Error{RQC_EINVAL, "workspace smaller than rqc_pair_workspace_bytes"};
+  if ((uintptr_t)workspace % 256) throw rqc::Error{RQC_EINVAL, "workspace not 256-byte aligned"};
+  // The labels of C must be exactly the free labels of A and B.
+  {
+    std::vector<int> f(g.Mf);
+    f.insert(f.end(), g.Nf.begin(), g.Nf.end());
+    std::vector<int> c(lc);
+    std::sort(f.begin(), f.end());
+    std::sort(c.begin(), c.end());
+    if (f != c) throw rqc::Error{RQC_EINVAL, "labels_c must be the labels of A and B that are not summed"};
+  }
+  if (batch_count > 1 && stride_c < ((int64_t)1 << (g.m + g.n)))
+    throw rqc::Error{RQC_EINVAL, "stride_c smaller than one output"};
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int lp = prec == RQC_F16 ? rqc::ST_F16 : rqc::ST_BF16;
+  uint8_t* wa = static_cast<uint8_t*>(workspace);
+  uint8_t* wb = wa + g.bytes_a;
+  std::vector<int> oa(g.Mf), ob(g.Nf);
+  oa.insert(oa.end(), g.K.begin(), g.K.end());
+  ob.insert(ob.end(), g.K.begin(), g.K.end());
+  const std::vector<int8_t> srca = perm_sources(la, oa), srcb = perm_sources(lb, ob);
+  const uint64_t ea = uint64_t(1) << (g.m + g.k), eb = uint64_t(1) << (g.n + g.k);
+  for (uint64_t j = 0; j < g.copies_a; ++j)
+    rqc::hip_check(rqc::launch_permute(static_cast<const float2*>(A) + j * stride_a, wa + j * ea * 4,
+                                       rank_a, srca.data(), s, lp),
+                   "pack A");
+  for (uint64_t j = 0; j < g.copies_b; ++j)
+    rqc::hip_check(rqc::launch_permute(static_cast<const float2*>(B) + j * stride_b, wb + j * eb * 4,
+                                       rank_b, srcb.data(), s, lp),
+                   "pack B");
+  rqc::Gemm16Desc d{};
+  d.A = reinterpret_cast<const uint32_t*>(wa);
+  d.B = reinterpret_cast<const uint32_t*>(wb);
+  d.C = C;
+  d.sA = g.copies_a > 1 ? (int64_t)ea : 0;
+  d.sB = g.copies_b > 1 ? (int64_t)eb : 0;
+  d.sC = stride_c;
+  d.m = g.m;
+  d.n = g.n;
+  d.k = g.k;
+  d.copies = batch_count;
+  d.ksplit = g.ksplit;
+  d.P = g.ksplit ? reinterpret_cast<float2*>(wb + g.bytes_b) : nullptr;
+  auto c_bit = [&](int label) {
+    return (int8_t)(rank_c - 1 - (std::find(lc.begin(), lc.end(), label) - lc.begin()));
+  };
+  for (int b = 0; b < g.m; ++b) d.crow[b] = c_bit(g.Mf[g.m - 1 - b]);
+  for (int b = 0; b < g.n; ++b) d.ccol[b] = c_bit(g.Nf[g.n - 1 - b]);
+  rqc::hip_check(rqc::launch_gemm16(d, lp, s), "16-bit GEMM");
+  return RQC_OK;
+  RQC_CATCH
+}
+
 rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
                                     const int32_t* labels_b, int32_t rank_b,
                                     const int32_t* labels_c, int32_t rank_c, const void* A,

@@ -131,8 +131,31 @@ hipError_t launch_batch_stats(const double* amps, uint64_t n, int n_qubits, cons
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 hipError_t launch_add_f64(double* dst, const double* src, int64_t n, hipStream_t s);
+// Bit permutation out (bit i fed by input bit src_pos_of_out_bit[i]) of a
+// complex64 tensor; out_store ST_F16 / ST_BF16 writes packed 16-bit (re, im)
+// words (round to nearest, no scaling).
 hipError_t launch_permute(const void* in, void* out, int rank, const int8_t* src_pos_of_out_bit,
-                          hipStream_t s);
+                          hipStream_t s, int out_store = ST_C64);
+
+// 16-bit matrix-core GEMM of the two-phase long-sum contraction
+// (k_gemm16.hip): A [copy][2^m rows][2^k] and B [copy][2^n columns][2^k]
+// packed 16-bit (re, im) words, summed index lowest and in the same order in
+// both; C (complex64) element (row r, column c) of copy j at
+// j * sC + sum_b bit_b(r) 2^crow[b] + sum_b bit_b(c) 2^ccol[b].
+constexpr int kGemm16M = 256, kGemm16N = 128, kGemm16K = 32;  // tile rows, complex columns, chunk k
+struct Gemm16Desc {
+  const uint32_t* A;
+  const uint32_t* B;
+  void* C;
+  int64_t sA, sB, sC;  // copy strides: words of A and B (0 = shared), complex elements of C
+  int32_t m, n, k;     // bits: rows (>= 8), columns (>= 7), summed (>= 5)
+  int32_t copies;
+  int32_t ksplit;      // the sum split 2^ksplit ways (partials in P, then reduced)
+  float2* P;           // partials [copy][split][row][column], when ksplit > 0
+  int8_t crow[40];
+  int8_t ccol[40];
+};
+hipError_t launch_gemm16(const Gemm16Desc& d, int lp_kind, hipStream_t s);
 hipError_t launch_cgemm(int64_t M, int64_t N, int64_t K, const void* A, const void* B, void* C,
                         hipStream_t s);
 

@@ -170,20 +170,49 @@ hipError_t launch_add_f64(double* dst, const double* src, int64_t n, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// Stand-alone bit permutation (the separate-permutation baseline): tiles of
-// 2^5 x 2^5 elements staged through LDS so that both the reads (low input
-// bits) and the writes (low output bits) are contiguous.
+// Bit permutation (the separate-permutation baseline, and the packing phase
+// of the two-phase 16-bit contraction, which also converts to packed 16-bit
+// words): tiles of 2^5 x 2^5 elements staged through LDS so that both the
+// reads (low input bits) and the writes (low output bits) are contiguous.
 // ---------------------------------------------------------------------------
 struct PermDesc {
   int32_t rank;
   int8_t src_of_out[48];  // input bit feeding output bit i
 };
 
-__global__ __launch_bounds__(256) void k_permute(const float2* in, float2* out, PermDesc p,
+template <int OUT>
+__device__ __forceinline__ void put_elem(void* out, uint64_t i, float2 v);
+template <>
+__device__ __forceinline__ void put_elem<ST_C64>(void* out, uint64_t i, float2 v) {
+  reinterpret_cast<float2*>(out)[i] = v;
+}
+template <>
+__device__ __forceinline__ void put_elem<ST_F16>(void* out, uint64_t i, float2 v) {
+  h2 o;
+  o.x = (_Float16)v.x;
+  o.y = (_Float16)v.y;
+  reinterpret_cast<h2*>(out)[i] = o;
+}
+template <>
+__device__ __forceinline__ void put_elem<ST_BF16>(void* out, uint64_t i, float2 v) {
+  b2 o;
+  o.x = (__bf16)v.x;
+  o.y = (__bf16)v.y;
+  reinterpret_cast<b2*>(out)[i] = o;
+}
+
+template <int OUT>
+__global__ __launch_bounds__(256) void k_permute(const float2* in, void* out, PermDesc p,
                                                  int lo_in, int lo_out, uint64_t n_blocks) {
   // Tile = the lowest `lo_in` input bits  U  the lowest `lo_out` output bits.
-  // Workgroups stride over the tiles (a grid has at most 2^32 work-items).
+  // The tile's element offsets (relative to the tile base) and LDS slots are
+  // tabulated once per workgroup; workgroups stride over the tiles (a grid
+  // has at most 2^32 work-items), each tile base a sum over its set bits.
   __shared__ float2 tile[1024 + 32];
+  __shared__ int64_t toff_in[1024];   // input offset of tile element t (input order)
+  __shared__ int16_t tslot[1024];     // its slot in output order
+  __shared__ int64_t toff_out[1024];  // output offset of tile element t (output order)
+  __shared__ int64_t bin[48], bout[48];  // input / output offset of outer bit i
   const int r = p.rank;
   int out_of_in[48];
   for (int i = 0; i < r; ++i) out_of_in[p.src_of_out[i]] = i;
@@ -195,76 +224,106 @@ __global__ __launch_bounds__(256) void k_permute(const float2* in, float2* out, 
   int tb[20], nt = 0;
   for (int i = 0; i < r; ++i)
     if ((tmask >> i) & 1) tb[nt++] = i;
-  int ob[48], no = 0;
+  int no = 0;
   for (int i = 0; i < r; ++i)
-    if (!((tmask >> i) & 1)) ob[no++] = i;
-  const int nte = 1 << nt;
-  // Read phase: element t of the tile in input order (input bits ascending).
-  int tin[20], nti = 0;
-  {
-    // tile bits sorted by their input bit
-    int tmp_in[20];
-    for (int i = 0; i < nt; ++i) tmp_in[i] = p.src_of_out[tb[i]];
-    // selection sort by input bit
-    for (int i = 0; i < nt; ++i) {
-      int best = i;
-      for (int j = i + 1; j < nt; ++j)
-        if (tmp_in[j] < tmp_in[best]) best = j;
-      int x = tmp_in[i]; tmp_in[i] = tmp_in[best]; tmp_in[best] = x;
+    if (!((tmask >> i) & 1)) {
+      if ((int)threadIdx.x == no) {
+        bout[no] = int64_t(1) << i;
+        bin[no] = int64_t(1) << p.src_of_out[i];
+      }
+      ++no;
     }
-    for (int i = 0; i < nt; ++i) tin[nti++] = tmp_in[i];
+  const int nte = 1 << nt;
+  // Tile bits sorted by their input bit: element t of the read phase.
+  int tin[20];
+  for (int i = 0; i < nt; ++i) tin[i] = p.src_of_out[tb[i]];
+  for (int i = 0; i < nt; ++i) {
+    int best = i;
+    for (int j = i + 1; j < nt; ++j)
+      if (tin[j] < tin[best]) best = j;
+    const int x = tin[i];
+    tin[i] = tin[best];
+    tin[best] = x;
   }
+  // Slot bit of read-order bit i: the position of its output bit in tb.
+  int sbit[20];
+  for (int i = 0; i < nt; ++i) {
+    const int ob_i = out_of_in[tin[i]];
+    sbit[i] = 0;
+    for (int j = 0; j < nt; ++j)
+      if (tb[j] == ob_i) sbit[i] = j;
+  }
+  for (int t = threadIdx.x; t < nte; t += blockDim.x) {
+    int64_t a = 0;
+    int slot = 0;
+    for (int i = 0; i < nt; ++i)
+      if ((t >> i) & 1) {
+        a |= int64_t(1) << tin[i];
+        slot |= 1 << sbit[i];
+      }
+    toff_in[t] = a;
+    tslot[t] = (int16_t)slot;
+    int64_t o = 0;
+    for (int j = 0; j < nt; ++j)
+      if ((t >> j) & 1) o |= int64_t(1) << tb[j];
+    toff_out[t] = o;
+  }
+  __syncthreads();
   for (uint64_t blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
-    // Block base in output index space.
-    uint64_t base_out = 0;
-    for (int i = 0; i < no; ++i)
-      if ((blk >> i) & 1) base_out |= 1ull << ob[i];
-    uint64_t base_in = 0;
-    for (int i = 0; i < r; ++i)
-      if ((base_out >> i) & 1) base_in |= 1ull << p.src_of_out[i];
+    int64_t base_in = 0, base_out = 0;
+    for (uint64_t b = blk; b; b &= b - 1) {
+      const int i = __builtin_ctzll(b);
+      base_in += bin[i];
+      base_out += bout[i];
+    }
     for (int t = threadIdx.x; t < nte; t += blockDim.x) {
-      uint64_t a = base_in;
-      int slot = 0;
-      for (int i = 0; i < nti; ++i)
-        if ((t >> i) & 1) {
-          a |= 1ull << tin[i];
-          // slot index: position of the output bit inside tb[]
-          const int ob_i = out_of_in[tin[i]];
-          for (int j = 0; j < nt; ++j)
-            if (tb[j] == ob_i) slot |= 1 << j;
-        }
-      tile[slot + (slot >> 5)] = in[a];
+      const int sl = tslot[t];
+      tile[sl + (sl >> 5)] = in[base_in + toff_in[t]];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nte; t += blockDim.x) {
-      uint64_t a = base_out;
-      for (int j = 0; j < nt; ++j)
-        if ((t >> j) & 1) a |= 1ull << tb[j];
-      out[a] = tile[t + (t >> 5)];
-    }
+    for (int t = threadIdx.x; t < nte; t += blockDim.x)
+      put_elem<OUT>(out, base_out + toff_out[t], tile[t + (t >> 5)]);
     __syncthreads();
   }
 }
 
 hipError_t launch_permute(const void* in, void* out, int rank, const int8_t* src_pos_of_out_bit,
-                          hipStream_t s) {
+                          hipStream_t s, int out_store) {
   PermDesc p;
   p.rank = rank;
   for (int i = 0; i < rank; ++i) p.src_of_out[i] = src_pos_of_out_bit[i];
-  // Up to 10 tile bits: 5 lowest input bits and 5 lowest output bits.
-  int lo_in = rank < 5 ? rank : 5, lo_out = rank < 5 ? rank : 5;
-  // Count tile bits (overlap shrinks the tile).
-  uint64_t tmask = 0;
+  // Tile = the lo_in lowest input bits and the lo_out lowest output bits,
+  // at most 10 bits (1024 elements): both grown alternately while the union
+  // fits, so a permutation that keeps its low bits still gets full tiles.
   int out_of_in[48];
   for (int i = 0; i < rank; ++i) out_of_in[(int)p.src_of_out[i]] = i;
-  for (int i = 0; i < lo_out; ++i) tmask |= 1ull << i;
-  for (int i = 0; i < lo_in; ++i) tmask |= 1ull << out_of_in[i];
-  const int nt = __builtin_popcountll(tmask);
+  auto tile_bits = [&](int li, int lo) {
+    uint64_t m = 0;
+    for (int i = 0; i < lo; ++i) m |= 1ull << i;
+    for (int i = 0; i < li; ++i) m |= 1ull << out_of_in[i];
+    return __builtin_popcountll(m);
+  };
+  int lo_in = 0, lo_out = 0;
+  for (bool grew = true; grew;) {
+    grew = false;
+    if (lo_out < rank && tile_bits(lo_in, lo_out + 1) <= 10) ++lo_out, grew = true;
+    if (lo_in < rank && tile_bits(lo_in + 1, lo_out) <= 10) ++lo_in, grew = true;
+  }
+  const int nt = tile_bits(lo_in, lo_out);
   const uint64_t blocks = 1ull << (rank - nt);
-  const uint64_t grid = blocks < (1ull << 20) ? blocks : (1ull << 20);
-  hipLaunchKernelGGL(k_permute, dim3((unsigned)grid), dim3(256), 0, s,
-                     reinterpret_cast<const float2*>(in), reinterpret_cast<float2*>(out), p, lo_in,
-                     lo_out, blocks);
+  // Eight workgroups per CU, each walking many tiles (its tables are built
+  // once).
+  const uint64_t grid = blocks < 2048 ? blocks : 2048;
+  const float2* src = reinterpret_cast<const float2*>(in);
+  if (out_store == ST_F16)
+    hipLaunchKernelGGL(k_permute<ST_F16>, dim3((unsigned)grid), dim3(256), 0, s, src, out, p, lo_in,
+                       lo_out, blocks);
+  else if (out_store == ST_BF16)
+    hipLaunchKernelGGL(k_permute<ST_BF16>, dim3((unsigned)grid), dim3(256), 0, s, src, out, p,
+                       lo_in, lo_out, blocks);
+  else
+    hipLaunchKernelGGL(k_permute<ST_C64>, dim3((unsigned)grid), dim3(256), 0, s, src, out, p,
+                       lo_in, lo_out, blocks);
   return hipGetLastError();
 }
 

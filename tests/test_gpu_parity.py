@@ -370,6 +370,45 @@ def test_lp_mfma_short_sum_vs_einsum(prec, tol):
 
 
 
+@pytest.mark.parametrize("prec,tol", [("f16", 6e-3), ("bf16", 4e-2)])
+def test_lp_long_sum_two_phase_vs_einsum(prec, tol):
+    """Long sums in FP16 / BF16 take the two-phase form (operands permuted
+    and converted into plain 16-bit matrices, then the 256 x 128-tile
+    matrix-core GEMM writing C in its own layout): random index orders of A,
+    B and C; one tile, several tiles in the XCD-aware order, and a batch of
+    two with a shared B; sums split 2 and 8 ways over one output tile."""
+    for (ra, rb, s, seed) in ((16, 15, 8, 51), (18, 16, 8, 52), (19, 17, 9, 53),
+                              (18, 17, 10, 58), (20, 19, 12, 59)):
+        _say("lp long sum", prec, ra, rb, s)
+        st = rqcgen.synthetic_step(ra, rb, s, seed)
+        assert R.pair_workspace_bytes(st.labels_a, st.labels_b, st.labels_c,
+                                      prec=R.PRECISIONS[prec]) > 0
+        a = rqcgen.random_complex(1 << ra, seed)
+        b = rqcgen.random_complex(1 << rb, seed + 1)
+        ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
+        c = R.pair_contract(_dev_c64(a), _dev_c64(b), st.labels_a, st.labels_b, st.labels_c,
+                            prec=R.PRECISIONS[prec])
+        torch.cuda.synchronize()
+        err = _rel_rms(c.cpu().numpy().astype(np.complex128), ref)
+        assert err < tol, (ra, rb, s, err)
+        assert err > 1e-6  # 16-bit operands
+    # batch of two copies of A (stride), one shared B (stride 0)
+    _say("lp long sum batch", prec)
+    st = rqcgen.synthetic_step(17, 15, 8, 54)
+    ra, rb, rc = len(st.labels_a), len(st.labels_b), len(st.labels_c)
+    a = np.concatenate([rqcgen.random_complex(1 << ra, 55), rqcgen.random_complex(1 << ra, 56)])
+    b = rqcgen.random_complex(1 << rb, 57)
+    c = R.pair_contract(_dev_c64(a), _dev_c64(b), st.labels_a, st.labels_b, st.labels_c, batch=2,
+                        stride_a=1 << ra, stride_b=0, prec=R.PRECISIONS[prec])
+    torch.cuda.synchronize()
+    got = c.cpu().numpy().astype(np.complex128)
+    for j in range(2):
+        ref = oracle.einsum_step(a[j << ra:(j + 1) << ra], b, st.labels_a, st.labels_b,
+                                 st.labels_c)
+        err = _rel_rms(got[j << rc:(j + 1) << rc], ref)
+        assert 1e-6 < err < tol, (j, err)
+
+
 def test_config3_full_rank_steps_sampled():
     """Two of the rank-24..32 synthetic steps at full size (random index
     orders of both operands and the output), 256 sampled outputs each vs
@@ -392,7 +431,14 @@ def test_config3_full_rank_steps_sampled():
         got = C[torch.from_numpy(coords).cuda()].cpu().numpy()
         scale = np.sqrt(2.0 ** k)  # RMS of a sum of 2^k unit-variance products
         assert np.max(np.abs(got - ref)) / scale < fp32_step_tol(k)
-        del A, B, C
+        # FP16: the two-phase long-sum form (operand rounding 2^-11 per
+        # component; the relative error of the sum stays near 2 u)
+        C16 = R.pair_contract(A, B, la, lb, lc, prec=R.F16)
+        torch.cuda.synchronize()
+        got16 = C16[torch.from_numpy(coords).cuda()].cpu().numpy()
+        err16 = np.max(np.abs(got16 - ref)) / scale
+        assert 1e-6 < err16 < 6e-3, err16
+        del A, B, C, C16
 
 
 def test_ttgt_example_section_5_4_on_the_gpu():

@@ -149,3 +149,34 @@ def test_restarts_keep_the_cheapest_plan_and_are_deterministic():
     assert cost(p4) <= cost(p1) * (1 + 1e-9)
     with pytest.raises(R.RqcError):
         _plan(4, 4, 8, 1, 2, restarts=-1)
+
+
+def test_two_phase_16_bit_workspace_sizes():
+    """The workspace query picks the two-phase long-sum form only in FP16 /
+    BF16 with automatic kernel choice, sums of >= 2^8 terms and at least one
+    256 x 128 output tile; it holds both packed operands (4 bytes per element
+    per distinct copy, A's part rounded up to 256 bytes)."""
+    st = rqcgen.synthetic_step(17, 15, 8, 3)  # m = 9, n = 7, k = 8: 2 tiles, no split
+    la, lb, lc = st.labels_a, st.labels_b, st.labels_c
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F32) == 0
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F16, kernel=1) == 0
+    want = 4 * (1 << 17) + 4 * (1 << 15)
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F16) == want
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.BF16) == want
+    # a batch of 3 with A per copy and B shared
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F16, batch=3, stride_a=1 << 17,
+                                  stride_b=0) == 3 * 4 * (1 << 17) + 4 * (1 << 15)
+    # a long sum over few tiles is split until there are 1024 work items or
+    # 16 chunks of 32 terms per split: m = 9, n = 7, k = 12 (2 tiles, 128
+    # chunks) splits 2^3 ways, with FP32 partials of 8 bytes per output
+    st = rqcgen.synthetic_step(21, 19, 12, 5)
+    la, lb, lc = st.labels_a, st.labels_b, st.labels_c
+    ks = 3
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F16) == (
+        4 * (1 << 21) + 4 * (1 << 19) + 8 * (1 << ks) * (1 << 16))
+    # too short a sum, too few rows or columns
+    for (ra, rb, s) in ((16, 14, 7), (15, 16, 8), (16, 14, 8)):
+        st = rqcgen.synthetic_step(ra, rb, s, 4)
+        assert R.pair_workspace_bytes(st.labels_a, st.labels_b, st.labels_c, prec=R.F16) == 0
+    with pytest.raises(R.RqcError):
+        R.pair_workspace_bytes([1, 1], [1], [], prec=R.F16)
