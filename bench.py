@@ -924,7 +924,7 @@ def main():
     chosen, probe, plan, lp_plan = select_plan(R, net, bits, a)
     t_plan = time.perf_counter() - t
     info = plan.info()
-    log(f"plan: {t_plan:.1f}s, log2 flops/slice {math.log2(info['flops_per_slice']):.2f}, "
+    log(f"plan: {t_plan:.1f}s, log2 flops/slice {math.log2(max(info['flops_per_slice'], 1.0)):.2f}, "
         f"width {info['max_log2_elems']}, {info['n_slices']} slices")
     ids = None
     frac = 1.0

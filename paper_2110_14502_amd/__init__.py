@@ -19,6 +19,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(
         f"{LIB_PATH} is missing: build it with `python paper_2110_14502_amd/build.py`")
 
+# One HIP runtime per process: torch loads its own copy of the HIP and HSA
+# runtimes by path, and a second copy loaded before it (by this library's
+# dependencies) cannot see the device once torch has initialised it.  Loading
+# torch first makes the library bind to torch's copy.
+try:
+    import torch  # noqa: F401
+except ImportError:  # host-only use (planning, CPU tests) works without it
+    pass
+
 _lib = C.CDLL(LIB_PATH)
 
 # ---------------------------------------------------------------- constants

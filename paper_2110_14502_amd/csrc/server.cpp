@@ -450,9 +450,9 @@ rqc_status rqc_server_create(const rqc_server_opts* o, rqc_server** out) {
   std::memset(&s->stats, 0, sizeof s->stats);
   s->t0 = std::chrono::steady_clock::now();
   s->pool.init(static_cast<char*>(o->device_pool), o->hbm_budget_bytes);
-  if (hipSetDevice(o->device) != hipSuccess) {
+  if (const hipError_t e = hipSetDevice(o->device); e != hipSuccess) {
     delete s;
-    rqc::set_error("hipSetDevice failed");
+    rqc::set_error(std::string("hipSetDevice failed: ") + hipGetErrorName(e));
     return RQC_EDEVICE;
   }
   for (int i = 0; i <= s->opts.n_streams; ++i) {
