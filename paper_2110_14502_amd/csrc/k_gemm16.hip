@@ -56,12 +56,14 @@ __device__ __forceinline__ floatx16 g16_mfma<ST_BF16>(g16_u32x4 a, g16_u32x4 b, 
                                                  __builtin_bit_cast(g16_bf16x8, b), c, 0, 0, 0);
 }
 
-// B_r words of a lane from four packed complex values of its column.
-__device__ __forceinline__ g16_u32x4 g16_expand_b(g16_u32x4 w, bool swap_halves) {
+// B_r words of a lane from four packed complex values of its column:
+// (re, -im) for output column parity 0, (im, re) for parity 1, as a rotation
+// by `rot` (0 or 16 bits) and an xor with `flip`, both fixed per lane (no
+// select on the loaded words, which the compiler turns into branches).
+__device__ __forceinline__ g16_u32x4 g16_expand_b(g16_u32x4 w, uint32_t rot, uint32_t flip) {
   g16_u32x4 o;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    o[i] = swap_halves ? ((w[i] >> 16) | (w[i] << 16)) : (w[i] ^ 0x80000000u);
+  for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbit(w[i], w[i], rot) ^ flip;
   return o;
 }
 
@@ -161,7 +163,8 @@ __global__ __launch_bounds__(512, 1) void k_gemm16(Gemm16Desc d) {
   const int lrow = lane & 31;
   const int kq = (lane >> 5) * 4;      // first complex k of the lane's 8 real k
   const int ncol = (lane & 31) >> 1;   // complex column inside a 32-column real block
-  const bool bswap = (lane & 1) != 0;  // C_r column parity 1: (im, re)
+  // C_r column parity 1 takes (im, re), parity 0 (re, -im).
+  const uint32_t brot = (lane & 1) ? 16u : 0u, bflip = (lane & 1) ? 0u : 0x80000000u;
 
   floatx16 acc[4][2];
 #pragma unroll
@@ -182,7 +185,8 @@ __global__ __launch_bounds__(512, 1) void k_gemm16(Gemm16Desc d) {
         a[i] = *reinterpret_cast<const g16_u32x4*>(As + i * 32 * kG16Row + kk * 8);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        b[j] = g16_expand_b(*reinterpret_cast<const g16_u32x4*>(Bs + j * 16 * kG16Row + kk * 8), bswap);
+        b[j] = g16_expand_b(*reinterpret_cast<const g16_u32x4*>(Bs + j * 16 * kG16Row + kk * 8), brot,
+                            bflip);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll

@@ -59,12 +59,22 @@ __device__ __forceinline__ floatx16 mfma16<ST_BF16>(u32x4 a, u32x4 b, floatx16 c
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// B_r words of a lane from four packed complex values of its column.
-__device__ __forceinline__ u32x4 expand_b(u32x4 w, bool swap_halves) {
+// B_r words of a lane from four packed complex values of its column:
+// (re, -im) for output column parity 0, (im, re) for parity 1.  Branch-free:
+// a rotation by `rot` (0 or 16 bits) and an xor with `flip` (the sign bit of
+// the high half, or 0), both fixed per lane.  (A select between the two
+// forms of an LDS-loaded word is compiled into a branch per word, each with
+// a wait for the LDS read.)
+struct BExpand {
+  uint32_t rot, flip;
+};
+__device__ __forceinline__ BExpand b_expand_of(bool swap_halves) {
+  return BExpand{swap_halves ? 16u : 0u, swap_halves ? 0u : 0x80000000u};
+}
+__device__ __forceinline__ u32x4 expand_b(u32x4 w, BExpand e) {
   u32x4 o;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    o[i] = swap_halves ? ((w[i] >> 16) | (w[i] << 16)) : (w[i] ^ 0x80000000u);
+  for (int i = 0; i < 4; ++i) o[i] = __builtin_amdgcn_alignbit(w[i], w[i], e.rot) ^ e.flip;
   return o;
 }
 
@@ -170,7 +180,7 @@ __device__ __forceinline__ void mfma16_body(const StepDesc& d, uint64_t n_items,
   const int lrow = lane & 31;
   const int kq = (lane >> 5) * 4;      // first complex k of the lane's 8 real k
   const int ncol = (lane & 31) >> 1;
-  const bool bswap = (lane & 1) != 0;  // C_r column parity 1: (im, re)
+  const BExpand bswap = b_expand_of((lane & 1) != 0);  // C_r column parity 1: (im, re)
 
   auto copy_scale = [&](int js, int jb) { return lp_copy_scale<LP, SA, SB>(d, js, jb); };
 
@@ -454,7 +464,7 @@ __device__ __forceinline__ void mfma16_stream_body(const StepDesc& d, uint64_t n
   const int lrow = lane & 31;
   const int kq = (lane >> 5) * 4;
   const int ncol = (lane & 31) >> 1;
-  const bool bswap = (lane & 1) != 0;
+  const BExpand bswap = b_expand_of((lane & 1) != 0);
 
   // Items: copy, then column tile, then row tile (fastest); contiguous
   // ranges per workgroup.  Chunk q of the range: item t0 + (q >> n_ko),
