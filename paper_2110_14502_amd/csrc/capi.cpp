@@ -425,13 +425,24 @@ struct Gemm16Shape {
   uint64_t total() const { return bytes_a + bytes_b + bytes_p; }
 };
 
-Gemm16Shape gemm16_shape(const std::vector<int>& la, const std::vector<int>& lb, int32_t batch,
-                         int64_t stride_a, int64_t stride_b, int32_t kernel, int32_t prec) {
+Gemm16Shape gemm16_shape(const std::vector<int>& la, const std::vector<int>& lb,
+                         const std::vector<int>& lc, int32_t batch, int64_t stride_a,
+                         int64_t stride_b, int32_t kernel, int32_t prec) {
   Gemm16Shape g;
   if ((prec != RQC_F16 && prec != RQC_BF16) || kernel != -1) return g;
   for (int x : la) (std::find(lb.begin(), lb.end(), x) != lb.end() ? g.K : g.Mf).push_back(x);
   for (int x : lb)
     if (std::find(la.begin(), la.end(), x) == la.end()) g.Nf.push_back(x);
+  // Rows and columns of the packed operands in C's order (the lowest row
+  // and column bits are C's lowest address bits among them), so that the
+  // GEMM's output tiles write runs of C that are as long as possible.
+  auto c_order = [&](std::vector<int>& v) {
+    std::stable_sort(v.begin(), v.end(), [&](int x, int y) {
+      return std::find(lc.begin(), lc.end(), x) < std::find(lc.begin(), lc.end(), y);
+    });
+  };
+  c_order(g.Mf);
+  c_order(g.Nf);
   if ((int)g.K.size() < kGemm16MinK || g.Mf.size() < 8 || g.Nf.size() < 7) return g;
   g.m = (int)g.Mf.size();
   g.n = (int)g.Nf.size();
@@ -491,7 +502,7 @@ rqc_status rqc_pair_workspace_bytes(const int32_t* labels_a, int32_t rank_a,
   if (!bytes) throw rqc::Error{RQC_EINVAL, "NULL argument"};
   std::vector<int> la, lb, lc;
   pair_labels(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, batch_count, la, lb, lc);
-  const Gemm16Shape g = gemm16_shape(la, lb, batch_count, stride_a, stride_b, kernel, prec);
+  const Gemm16Shape g = gemm16_shape(la, lb, lc, batch_count, stride_a, stride_b, kernel, prec);
   *bytes = g.m < 0 ? 0 : g.total();
   return RQC_OK;
   RQC_CATCH
@@ -506,7 +517,7 @@ rqc_status rqc_pair_contract_ws(const int32_t* labels_a, int32_t rank_a, const i
   RQC_TRY
   std::vector<int> la, lb, lc;
   pair_labels(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, batch_count, la, lb, lc);
-  const Gemm16Shape g = gemm16_shape(la, lb, batch_count, stride_a, stride_b, kernel, prec);
+  const Gemm16Shape g = gemm16_shape(la, lb, lc, batch_count, stride_a, stride_b, kernel, prec);
   if (g.m < 0)
     return rqc_pair_contract(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, A, B, C,
                              batch_count, stride_a, stride_b, stride_c, kernel, prec, stream);
