@@ -201,9 +201,41 @@ __device__ __forceinline__ void put_elem<ST_BF16>(void* out, uint64_t i, float2 
   reinterpret_cast<b2*>(out)[i] = o;
 }
 
+// Four consecutive output elements from one aligned group (the output's two
+// lowest bits are the tile's): one 16-byte store of packed 16-bit words, or
+// two of complex64.
+template <int OUT>
+__device__ __forceinline__ void put_elem4(void* out, uint64_t i, float2 a, float2 b, float2 c,
+                                          float2 e) {
+  if constexpr (OUT == ST_C64) {
+    float4* o = reinterpret_cast<float4*>(reinterpret_cast<float2*>(out) + i);
+    o[0] = make_float4(a.x, a.y, b.x, b.y);
+    o[1] = make_float4(c.x, c.y, e.x, e.y);
+  } else {
+    uint32_t w[4];
+    const float2 v[4] = {a, b, c, e};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (OUT == ST_F16) {
+        h2 x;
+        x.x = (_Float16)v[j].x;
+        x.y = (_Float16)v[j].y;
+        w[j] = __builtin_bit_cast(uint32_t, x);
+      } else {
+        b2 x;
+        x.x = (__bf16)v[j].x;
+        x.y = (__bf16)v[j].y;
+        w[j] = __builtin_bit_cast(uint32_t, x);
+      }
+    }
+    *reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(out) + i) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
 template <int OUT>
 __global__ __launch_bounds__(256) void k_permute(const float2* in, void* out, PermDesc p,
-                                                 int lo_in, int lo_out, uint64_t n_blocks) {
+                                                 int lo_in, int lo_out, uint64_t n_blocks,
+                                                 int vec) {
   // Tile = the lowest `lo_in` input bits  U  the lowest `lo_out` output bits.
   // The tile's element offsets (relative to the tile base) and LDS slots are
   // tabulated once per workgroup; workgroups stride over the tiles (a grid
@@ -276,6 +308,26 @@ __global__ __launch_bounds__(256) void k_permute(const float2* in, void* out, Pe
       base_in += bin[i];
       base_out += bout[i];
     }
+    if (vec) {
+      // Full tile, 16-byte aligned operands, tile bits 0 and 1 being input
+      // bits 0, 1 and output bits 0, 1: thread u moves elements 4u .. 4u+3,
+      // contiguous on both sides.
+      const int t = 4 * (int)threadIdx.x;
+      const float4* src = reinterpret_cast<const float4*>(in + base_in + toff_in[t]);
+      const float4 v0 = src[0], v1 = src[1];
+      const float2 e[4] = {make_float2(v0.x, v0.y), make_float2(v0.z, v0.w),
+                           make_float2(v1.x, v1.y), make_float2(v1.z, v1.w)};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int sl = tslot[t + j];
+        tile[sl + (sl >> 5)] = e[j];
+      }
+      __syncthreads();
+      const int c = t + (t >> 5);
+      put_elem4<OUT>(out, base_out + toff_out[t], tile[c], tile[c + 1], tile[c + 2], tile[c + 3]);
+      __syncthreads();
+      continue;
+    }
     for (int t = threadIdx.x; t < nte; t += blockDim.x) {
       const int sl = tslot[t];
       tile[sl + (sl >> 5)] = in[base_in + toff_in[t]];
@@ -315,15 +367,21 @@ hipError_t launch_permute(const void* in, void* out, int rank, const int8_t* src
   // once).
   const uint64_t grid = blocks < 2048 ? blocks : 2048;
   const float2* src = reinterpret_cast<const float2*>(in);
+  // Vector form: full 1024-element tiles (the kernel runs 256 threads of four
+  // elements), the two lowest input and output bits inside the tile, both
+  // buffers 16-byte aligned.
+  const int vec = nt == 10 && lo_in >= 2 && lo_out >= 2 &&
+                  (reinterpret_cast<uintptr_t>(in) & 15) == 0 &&
+                  (reinterpret_cast<uintptr_t>(out) & 15) == 0;
   if (out_store == ST_F16)
     hipLaunchKernelGGL(k_permute<ST_F16>, dim3((unsigned)grid), dim3(256), 0, s, src, out, p, lo_in,
-                       lo_out, blocks);
+                       lo_out, blocks, vec);
   else if (out_store == ST_BF16)
     hipLaunchKernelGGL(k_permute<ST_BF16>, dim3((unsigned)grid), dim3(256), 0, s, src, out, p,
-                       lo_in, lo_out, blocks);
+                       lo_in, lo_out, blocks, vec);
   else
     hipLaunchKernelGGL(k_permute<ST_C64>, dim3((unsigned)grid), dim3(256), 0, s, src, out, p,
-                       lo_in, lo_out, blocks);
+                       lo_in, lo_out, blocks, vec);
   return hipGetLastError();
 }
 
