@@ -177,21 +177,38 @@ __global__ __launch_bounds__(512, 1) void k_gemm16(Gemm16Desc d) {
   auto multiply = [&](int cb) {
     const uint32_t* As = Abuf + cb * kG16ABuf + (wr * 128 + lrow) * kG16Row + kq;
     const uint32_t* Bs = Bbuf + cb * kG16BBuf + (wc * 32 + ncol) * kG16Row + kq;
-#pragma unroll
-    for (int kk = 0; kk < kGemm16K / 8; ++kk) {
-      g16_u32x4 a[4], b[2];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-        a[i] = *reinterpret_cast<const g16_u32x4*>(As + i * 32 * kG16Row + kk * 8);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-        b[j] = g16_expand_b(*reinterpret_cast<const g16_u32x4*>(Bs + j * 16 * kG16Row + kk * 8), brot,
-                            bflip);
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = g16_mfma<LP>(a[i], b[j], acc[i][j]);
-    }
+    // The fragments of step kk + 1 are read from LDS before the products of
+    // step kk are issued.
+    g16_u32x4 a0[4], b0[2], a1[4], b1[2];
+#define G16_FRAGS(A, B, kk)                                                                 \
+  _Pragma("unroll") for (int i = 0; i < 4; ++i)                                            \
+      A[i] = *reinterpret_cast<const g16_u32x4*>(As + i * 32 * kG16Row + (kk) * 8);       \
+  _Pragma("unroll") for (int j = 0; j < 2; ++j)                                            \
+      B[j] = *reinterpret_cast<const g16_u32x4*>(Bs + j * 16 * kG16Row + (kk) * 8);
+#define G16_PRODUCTS(A, B)                                                                  \
+  {                                                                                         \
+    g16_u32x4 be[2];                                                                        \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) be[j] = g16_expand_b(B[j], brot, bflip); \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i)                                          \
+        _Pragma("unroll") for (int j = 0; j < 2; ++j) acc[i][j] =                          \
+            g16_mfma<LP>(A[i], be[j], acc[i][j]);                                           \
+  }
+    G16_FRAGS(a0, b0, 0)
+    G16_FRAGS(a1, b1, 1)
+    __builtin_amdgcn_sched_barrier(0);
+    G16_PRODUCTS(a0, b0)
+    __builtin_amdgcn_sched_barrier(0);
+    G16_FRAGS(a0, b0, 2)
+    __builtin_amdgcn_sched_barrier(0);
+    G16_PRODUCTS(a1, b1)
+    __builtin_amdgcn_sched_barrier(0);
+    G16_FRAGS(a1, b1, 3)
+    __builtin_amdgcn_sched_barrier(0);
+    G16_PRODUCTS(a0, b0)
+    __builtin_amdgcn_sched_barrier(0);
+    G16_PRODUCTS(a1, b1)
+#undef G16_FRAGS
+#undef G16_PRODUCTS
   };
 
   // Chunk i sits in LDS buffer i & 1; chunk i + 1 in set Y (i even) or X
