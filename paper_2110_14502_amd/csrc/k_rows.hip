@@ -146,21 +146,19 @@ __device__ __forceinline__ void unpack_raw(const RawRow<S, K, NJ>& r, int g, flo
   }
 }
 
-// This lane's raw quarters of its four rows of a 256-row tile, K chunk kc
-// (zeros past the tile's rows).
+// This lane's raw quarters of its four rows of a 256-row tile, K chunk kc.
+// Rows past the tile's R read row R-1 instead (their products are never
+// staged): with no load under a per-lane condition the prefetch's wait
+// counts stay exact, so multiplying a chunk does not wait for the next one.
 template <int SA, int K, int NJ>
 __device__ __forceinline__ void load_tile_rows(const StepDesc& d, int64_t oA, int KT, int kc,
                                                int R, int wave, int lc, int g,
                                                RawRow<SA, K, NJ> (&dst)[4]) {
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
-    const int r = wave * 64 + rb * 16 + lc;
-    if (r < R) {
-      load_raw<SA, K, NJ>(d.A, oA + (int64_t)r * KT + kc * K, g, dst[rb]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < RawRow<SA, K, NJ>::W; ++i) dst[rb].w[i] = 0u;
-    }
+    const int r0 = wave * 64 + rb * 16 + lc;
+    const int r = r0 < R ? r0 : R - 1;
+    load_raw<SA, K, NJ>(d.A, oA + (int64_t)r * KT + kc * K, g, dst[rb]);
   }
 }
 
@@ -227,6 +225,11 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
     outer_offsets(d, t & rmask, 0, copy % d.gs_c, copy / d.gs_c, oA, oB, oC);
     load_tile_rows<SA, K, NJ>(d, oA, KT, 0, R, wave, lc, g, a);
   }
+  // Wait for the first tile's rows here (s_waitcnt vmcnt(0)): entering the
+  // tile loop with those loads pending, the compiler's wait counting merges
+  // them with the loop's own prefetch and waits for the prefetch too, in
+  // every chunk.
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   int cur = -1, cjs = 0, cjb = 0;
   bool wexp = false;
   Scale sc{0, 0};
@@ -319,19 +322,22 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
         // MFMA j takes real k g*NJ + 8j .. +7 of every lane quarter: the raw
         // words 4j .. 4j+3 of A, and four packed complex values of B
         // expanded to (Br, -Bi) (column parity 0) or (Bi, Br) (parity 1).
+        // Lanes past the chunk's columns read column NC-1 (their results are
+        // never stored), so that no read is conditional; the expansion is a
+        // rotation by 0 / 16 bits and an xor with a per-lane sign mask (a
+        // select between the two forms of a loaded word would be compiled
+        // into a branch per word).
         const uint32_t* Bw = reinterpret_cast<const uint32_t*>(Bs);
+        const int ncl = (lc >> 1) < NC ? (lc >> 1) : NC - 1;
+        const uint32_t brot = (lc & 1) ? 16u : 0u, bflip = (lc & 1) ? 0u : 0x80000000u;
 #pragma unroll
         for (int h = 0; h < NCH; ++h) {
-          const int n = h * NC + (lc >> 1), q = lc & 1;
-          const bool col_ok = (lc >> 1) < NC;
+          const int n = h * NC + ncl;
 #pragma unroll
           for (int j = 0; j < NJ / 8; ++j) {
-            u32x4r bw = {0u, 0u, 0u, 0u};
-            if (col_ok)
-              bw = *reinterpret_cast<const u32x4r*>(Bw + n * KT + kc * K + g * (NJ / 2) + 4 * j);
+            u32x4r bw = *reinterpret_cast<const u32x4r*>(Bw + n * KT + kc * K + g * (NJ / 2) + 4 * j);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              bw[i] = q ? ((bw[i] >> 16) | (bw[i] << 16)) : (bw[i] ^ 0x80000000u);
+            for (int i = 0; i < 4; ++i) bw[i] = __builtin_amdgcn_alignbit(bw[i], bw[i], brot) ^ bflip;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) {
               const u32x4r aw = {a[rb].w[4 * j], a[rb].w[4 * j + 1], a[rb].w[4 * j + 2],
@@ -348,14 +354,16 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
         for (int h = 0; h < NCH; ++h) {
           // B operand: real column lc of column chunk h (complex column
           // h*NC + lc/2, part lc&1), real summation index of MFMA j.
+          // Unconditional reads (clamped column and summation index: the
+          // lanes they serve either hold zero rows of A, K = 1, or columns
+          // that are never stored), so that no LDS read sits in a branch.
           float bop[NJ];
-          const int n = h * NC + (lc >> 1), q = lc & 1;
-          const bool col_ok = (lc >> 1) < NC;
+          const int n = h * NC + ((lc >> 1) < NC ? (lc >> 1) : NC - 1), q = lc & 1;
   #pragma unroll
           for (int j = 0; j < NJ; ++j) {
             const int rk = K >= 2 ? g * NJ + j : g;
-            const bool ok = col_ok && rk < 2 * K;
-            const float2 b = ok ? Bs[n * KT + kc * K + (rk >> 1)] : make_float2(0.f, 0.f);
+            const int kk = (rk >> 1) < K ? (rk >> 1) : K - 1;
+            const float2 b = Bs[n * KT + kc * K + kk];
             bop[j] = (rk & 1) == 0 ? (q == 0 ? b.x : b.y) : (q == 0 ? -b.y : b.x);
           }
   #pragma unroll
