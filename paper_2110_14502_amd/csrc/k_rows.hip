@@ -457,11 +457,18 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
 template <int KB, int NCH>
 static hipError_t launch_rows_n(const StepDesc& d, int sa, dim3 grid, size_t lds, hipStream_t s) {
   const bool fp32 = (d.variant & kVarFP32Math) != 0;
-  if (sa == ST_F16 && fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16, false>), grid, dim3(256), lds, s, d);
-  else if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16, true>), grid, dim3(256), lds, s, d);
-  else if (sa == ST_BF16 && fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16, false>), grid, dim3(256), lds, s, d);
-  else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16, true>), grid, dim3(256), lds, s, d);
-  else hipLaunchKernelGGL((k_rows<KB, NCH, ST_C64, true>), grid, dim3(256), lds, s, d);
+  if constexpr (KB == 5) {
+    // 32-value chunks: 16-bit stored A on the 16-bit matrix cores only.
+    if (sa == ST_F16 && !fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16, true>), grid, dim3(256), lds, s, d);
+    else if (sa == ST_BF16 && !fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16, true>), grid, dim3(256), lds, s, d);
+    else return hipErrorInvalidValue;
+  } else {
+    if (sa == ST_F16 && fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16, false>), grid, dim3(256), lds, s, d);
+    else if (sa == ST_F16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_F16, true>), grid, dim3(256), lds, s, d);
+    else if (sa == ST_BF16 && fp32) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16, false>), grid, dim3(256), lds, s, d);
+    else if (sa == ST_BF16) hipLaunchKernelGGL((k_rows<KB, NCH, ST_BF16, true>), grid, dim3(256), lds, s, d);
+    else hipLaunchKernelGGL((k_rows<KB, NCH, ST_C64, true>), grid, dim3(256), lds, s, d);
+  }
   return hipGetLastError();
 }
 
@@ -485,9 +492,13 @@ static hipError_t launch_rows(const StepDesc& d, int sa, dim3 grid, hipStream_t 
 }
 
 // K chunks: the whole sum for k <= 4, chunks of 16 complex values beyond
-// (a 32-value chunk would hold twice the rows' registers and halve the
-// number of resident waves).
+// (a 32-value complex64 chunk would hold twice the rows' registers and halve
+// the number of resident waves).  A 16-bit stored A on the 16-bit matrix
+// cores takes 32-value chunks: the same registers, and a chunk of each row
+// is one whole 128-byte line (16-value chunks read each line in two halves,
+// at different times, and fetched up to 1.7 times the bytes).
 hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
+  if (d.kt >= 5 && sa != ST_C64 && !(d.variant & kVarFP32Math)) return launch_rows<5>(d, sa, grid, s);
   switch (d.kt) {
     case 0: return launch_rows<0>(d, sa, grid, s);
     case 1: return launch_rows<1>(d, sa, grid, s);
