@@ -472,8 +472,14 @@ __device__ __forceinline__ void mfma16_stream_body(const StepDesc& d, uint64_t n
   const int n_ko = d.n_ko, n_kc = 1 << n_ko;
   const int tbits = d.n_ro + d.n_no;
   const uint64_t tmask = (uint64_t(1) << tbits) - 1, rmask = (uint64_t(1) << d.n_ro) - 1;
-  const uint64_t per = (n_items + gridDim.x - 1) / gridDim.x;
-  const uint64_t t0 = (uint64_t)blockIdx.x * per;
+  // Workgroup w takes the w-th contiguous range; w is dealt so that
+  // consecutive ranges run on the same XCD (blocks go round-robin to the 8
+  // XCDs): the ranges of one copy's column tiles then stream the same rows of
+  // A at the same time and share them in that XCD's L2.
+  const uint64_t G = gridDim.x;
+  const uint64_t w = (G & 7) == 0 ? (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : blockIdx.x;
+  const uint64_t per = (n_items + G - 1) / G;
+  const uint64_t t0 = w * per;
   const uint64_t t1 = t0 + per < n_items ? t0 + per : n_items;
   if (t0 >= t1) return;
   const uint64_t n_q = (t1 - t0) << n_ko;
