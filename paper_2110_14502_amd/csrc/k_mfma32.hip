@@ -288,7 +288,11 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
         item_offsets(t + G, pA, pB, pC);
         load_chunk(pA, pB, 0);
       }
+      // The products run at raised wave priority, so that the other
+      // workgroup's epilogue on this CU does not hold back their issue.
+      __builtin_amdgcn_s_setprio(1);
       chunk_mfma<M3>(Abuf + cb * kABuf, Bbuf + cb * kBBuf, lane, wm, wn, acc);
+      __builtin_amdgcn_s_setprio(0);
       if (more) store_chunk(cb ^ 1);
       __syncthreads();
     }
@@ -400,7 +404,9 @@ __global__ __launch_bounds__(256, M3 ? 2 : 3) void k_mfma32_tiles(StepDesc d) {
       const int cb = kc & 1;
       const bool more = kc + 1 < n_kc;
       if (more) load_chunk(kc + 1);
+      __builtin_amdgcn_s_setprio(1);
       chunk_mfma<M3>(Abuf + cb * kABuf, Bbuf + cb * kBBuf, lane, wm, wn, acc);
+      __builtin_amdgcn_s_setprio(0);
       if (more) store_chunk(cb ^ 1);
       __syncthreads();
     }

@@ -392,6 +392,21 @@ def test_lp_long_sum_two_phase_vs_einsum(prec, tol):
         err = _rel_rms(c.cpu().numpy().astype(np.complex128), ref)
         assert err < tol, (ra, rb, s, err)
         assert err > 1e-6  # 16-bit operands
+    # batch of two copies of B (stride), one shared A (stride 0)
+    _say("lp long sum batch, shared A", prec)
+    st = rqcgen.synthetic_step(16, 16, 8, 60)
+    ra, rb, rc = len(st.labels_a), len(st.labels_b), len(st.labels_c)
+    a = rqcgen.random_complex(1 << ra, 61)
+    b = np.concatenate([rqcgen.random_complex(1 << rb, 62), rqcgen.random_complex(1 << rb, 63)])
+    c = R.pair_contract(_dev_c64(a), _dev_c64(b), st.labels_a, st.labels_b, st.labels_c, batch=2,
+                        stride_a=0, stride_b=1 << rb, prec=R.PRECISIONS[prec])
+    torch.cuda.synchronize()
+    got = c.cpu().numpy().astype(np.complex128)
+    for j in range(2):
+        ref = oracle.einsum_step(a, b[j << rb:(j + 1) << rb], st.labels_a, st.labels_b,
+                                 st.labels_c)
+        err = _rel_rms(got[j << rc:(j + 1) << rc], ref)
+        assert 1e-6 < err < tol, (j, err)
     # batch of two copies of A (stride), one shared B (stride 0)
     _say("lp long sum batch", prec)
     st = rqcgen.synthetic_step(17, 15, 8, 54)
