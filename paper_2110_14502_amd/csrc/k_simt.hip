@@ -99,6 +99,17 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
   // thread multiplies, and the quarters are added in order at the end.
   const bool quarters = nC <= 64 && K >= 4;
   const int qk = K >> 2, q = tid >> 6;
+  // Blocked form of the tiny tiles: 4 x 4 output blocks per thread, the
+  // sum split over 256 / blocks parts; a thread reads 8 LDS values per 16
+  // products instead of 2 per 1 (the tile loop is bound by LDS reads).  The
+  // parts are added in part order at the end through the operand buffers.
+  const int nbr = R >> 2, nbc = N >> 2, nblk = nbr * nbc;
+  const bool blocked = quarters && (R & 3) == 0 && (N & 3) == 0 && nblk > 0 &&
+                       K >= kSimtBlock / nblk && R * ldA + K * ldB >= 16 * kSimtBlock;
+  const int parts = blocked ? kSimtBlock / nblk : 1;
+  const int kpart = blocked ? K / parts : 0;
+  const int blk = tid % (blocked ? nblk : 1), part = tid / (blocked ? nblk : 1);
+  const int br0 = (blk / (nbc > 0 ? nbc : 1)) * 4, bc0 = (blk % (nbc > 0 ? nbc : 1)) * 4;
   int qrow = 0, qcol = 0;
   int64_t qg = 0;
   if (quarters) {
@@ -114,6 +125,11 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
     float2 acc[kSimtMaxC];
 #pragma unroll
     for (int i = 0; i < kSimtMaxC; ++i) acc[i] = make_float2(0.f, 0.f);
+    float bx[4][4], by[4][4];  // blocked form: the thread's 4 x 4 outputs
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bx[i][j] = by[i][j] = 0.f;
     for (int kc = kc0; kc < kc0 + n_kc; ++kc) {
       int64_t kA, kB;
       k_offsets(d, kc, kA, kB);
@@ -123,6 +139,28 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
       simt_stage<SA>(d.A, oA + kA + gAlo, ta, cAlo, nA, tid, As);
       simt_stage<SB>(d.B, oB + kB + gBlo, tb, cBlo, nB, tid, Bs);
       __syncthreads();
+      if (blocked) {
+        const float2* ar = As + br0 * ldA + part * kpart;
+        const float2* bc = Bs + bc0 + part * kpart * ldB;
+        for (int k = 0; k < kpart; ++k) {
+          float2 a[4], b[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a[i] = ar[i * ldA + k];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = bc[k * ldB + j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              bx[i][j] = fmaf(a[i].x, b[j].x, bx[i][j]);
+              bx[i][j] = fmaf(-a[i].y, b[j].y, bx[i][j]);
+              by[i][j] = fmaf(a[i].x, b[j].y, by[i][j]);
+              by[i][j] = fmaf(a[i].y, b[j].x, by[i][j]);
+            }
+        }
+        __syncthreads();
+        continue;
+      }
       if (quarters) {
         if (lane < nC) {
           const float2* ar = As + qrow * ldA + q * qk;
@@ -158,7 +196,28 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
       }
       __syncthreads();
     }
-    if (quarters) {
+    if (blocked) {
+      // Partials of thread (part, block) at [part][block][16] in the operand
+      // buffers (free after the last chunk); output (qrow, qcol) of lane
+      // `lane` of wave 0 = their sum over the parts, in part order.
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          smem2[(part * nblk + blk) * 16 + i * 4 + j] = make_float2(bx[i][j], by[i][j]);
+      __syncthreads();
+      if (q == 0 && lane < nC) {
+        const int ob = (qrow >> 2) * nbc + (qcol >> 2), os = (qrow & 3) * 4 + (qcol & 3);
+        float sx = 0.f, sy = 0.f;
+        for (int pp = 0; pp < parts; ++pp) {
+          const float2 v = smem2[(pp * nblk + ob) * 16 + os];
+          sx += v.x;
+          sy += v.y;
+        }
+        acc[0] = make_float2(sx, sy);
+      }
+      __syncthreads();
+    } else if (quarters) {
       // Output lane of wave 0 = sum of the four quarters, in wave order.
       qsum[tid] = acc[0];
       __syncthreads();
@@ -172,6 +231,8 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
         acc[0] = make_float2(sx, sy);
       }
       __syncthreads();
+    }
+    if (quarters) {
       if (d.ksplit) {
         if (q == 0 && lane < nC) d.P[(int64_t)split * d.p_stride + oC + qg] = acc[0];
         continue;

@@ -57,6 +57,8 @@ STEP_CASES = [
     (5, 3, 0, 7, 0),     # outer product
     (18, 16, 9, 8, 1),   # long sum: one tile per workgroup (k >= 8)
     (17, 17, 8, 9, -1),
+    (15, 15, 12, 10, 0),  # 8 x 8 output, long sum: blocked tiny-tile form
+    (14, 13, 11, 11, 0),  # 8 x 4 output
 ]
 
 
