@@ -354,6 +354,7 @@ def launch_table(launches, n_reps=1, prec="f32"):
         rows.append({"step": L["step"], "kernel": KIND_NAMES.get(L["kernel"], str(L["kernel"])),
                      "mnk": [L["m"], L["n"], L["k"]], "copies": L["copies"],
                      "store": [L["store_a"], L["store_b"], L["store_c"]],
+                     "variant": L["variant"],
                      "flops": L["flops"], "bytes": L["bytes"], "ms": round(ms, 5),
                      "t_min_ms": round(t_min, 5), "bound": "mfma" if t_f >= t_b else "hbm",
                      "frac": round(t_min / ms, 4) if ms > 0 else None})

@@ -534,7 +534,7 @@ typedef struct rqc_launch_timing {
   int32_t m, n, k;      /* bits of C[m,n] = A[m,k] B[k,n] */
   int32_t copies;       /* independent problems of the launch */
   int32_t store_a, store_b, store_c; /* 0 complex64, 1 FP16, 2 BF16 pairs */
-  int32_t reserved;
+  int32_t variant;      /* kernel variant bits (as in rqc_pair_contract_stored) */
   double ms, flops, bytes;
 } rqc_launch_timing;
 
@@ -562,8 +562,10 @@ rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias,
  * product instead of three, 2 = one tile per workgroup, 4 = persistent
  * walk; any kernel: 8 = FP32 arithmetic on 16-bit stored operands; 16-bit
  * matrix cores: 16 = stream A past a resident tile of B, for sums of 32 to
- * 128 terms with A stored in 16 bits).  EINVAL when the kernel's shape or
- * layout conditions are not met (no fallback). */
+ * 128 terms with A stored in 16 bits; FP32 matrix cores: 32 = the operands
+ * exchanged inside the kernel, B taking the tile rows and A the columns,
+ * same result).  EINVAL when the kernel's shape or layout conditions are not
+ * met (no fallback). */
 rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
                                     const int32_t* labels_b, int32_t rank_b,
                                     const int32_t* labels_c, int32_t rank_c,

@@ -93,7 +93,7 @@ class rqc_timing(C.Structure):
 class rqc_launch_timing(C.Structure):
     _fields_ = [("step", C.c_int32), ("kernel", C.c_int32), ("m", C.c_int32), ("n", C.c_int32),
                 ("k", C.c_int32), ("copies", C.c_int32), ("store_a", C.c_int32),
-                ("store_b", C.c_int32), ("store_c", C.c_int32), ("reserved", C.c_int32),
+                ("store_b", C.c_int32), ("store_c", C.c_int32), ("variant", C.c_int32),
                 ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
 
 
@@ -578,7 +578,7 @@ ST_C64, ST_F16, ST_BF16 = 0, 1, 2
 KERN_SIMT, KERN_MFMA, KERN_ROWS, KERN_MFMA16 = 0, 1, 2, 3
 
 
-VAR_4M, VAR_TILES, VAR_PERSISTENT, VAR_FP32_MATH, VAR_STREAM = 1, 2, 4, 8, 16
+VAR_4M, VAR_TILES, VAR_PERSISTENT, VAR_FP32_MATH, VAR_STREAM, VAR_SWAP = 1, 2, 4, 8, 16, 32
 
 
 def pair_contract_stored(A, B, C_out, labels_a, labels_b, labels_c, store_a, store_b, store_c,

@@ -360,6 +360,7 @@ rqc_status rqc_plan_get_launch_timing(const rqc_plan* p, uint64_t i, rqc_launch_
   out->store_a = r.sa;
   out->store_b = r.sb;
   out->store_c = r.sc;
+  out->variant = r.variant;
   out->ms = p->tms[i];
   out->flops = r.flops;
   out->bytes = r.bytes;
@@ -612,8 +613,12 @@ rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
     std::sort(v.begin(), v.end());
     if (std::adjacent_find(v.begin(), v.end()) != v.end()) throw rqc::Error{RQC_EINVAL, "repeated label"};
   }
+  if (variant < 0 || variant > 63) throw rqc::Error{RQC_EINVAL, "variant out of range"};
+  const bool swap = (variant & rqc::kVarSwap) != 0;
+  if (swap && kernel != rqc::KERN_MFMA)
+    throw rqc::Error{RQC_EINVAL, "exchanged operands need the FP32 matrix-core kernel"};
   int kern = kernel;
-  rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, kern);
+  rqc::StepDesc d = swap ? rqc::make_pair_desc(lb, la, lc, kern) : rqc::make_pair_desc(la, lb, lc, kern);
   if (kern != kernel) throw rqc::Error{RQC_EINVAL, "shape or layout not supported by the requested kernel"};
   d.A = A;
   d.B = B;
@@ -623,11 +628,11 @@ rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
   d.sC_s = stride_c;
   d.gs_c = batch_count;
   d.copies = batch_count;
-  if (variant < 0 || variant > 31) throw rqc::Error{RQC_EINVAL, "variant out of range"};
   d.variant = variant;
+  if (swap) rqc::swap_operands(d);
   const int lp_kind = kernel == rqc::KERN_MFMA16 ? (mma_prec == RQC_F16 ? rqc::ST_F16 : rqc::ST_BF16) : 0;
-  rqc::hip_check(rqc::launch_step(d, kern, store_a, store_b, store_c, lp_kind,
-                                  static_cast<hipStream_t>(stream)),
+  rqc::hip_check(rqc::launch_step(d, kern, swap ? store_b : store_a, swap ? store_a : store_b, store_c,
+                                  lp_kind, static_cast<hipStream_t>(stream)),
                  "pair contract (stored)");
   return RQC_OK;
   RQC_CATCH

@@ -32,6 +32,22 @@ static int pos_in(const std::vector<int>& l, int x) {
 // ---------------------------------------------------------------------------
 // Tile selection for one step (the permutation folded into the tiles)
 // ---------------------------------------------------------------------------
+StepDesc step_desc(const Step& st, int& kernel, int variant) {
+  return variant & kVarSwap ? make_pair_desc(st.lb, st.la, st.lc, kernel)
+                            : make_pair_desc(st.la, st.lb, st.lc, kernel);
+}
+
+void swap_operands(StepDesc& d) {
+  std::swap(d.A, d.B);
+  std::swap(d.expA, d.expB);
+  std::swap(d.maxA, d.maxB);
+  std::swap(d.maxA_const, d.maxB_const);
+  std::swap(d.sA_s, d.sB_s);
+  std::swap(d.sA_b, d.sB_b);
+  std::swap(d.eA_s, d.eB_s);
+  std::swap(d.eA_b, d.eB_b);
+}
+
 StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
                         const std::vector<int>& lc, int& kernel) {
   StepDesc d;
@@ -61,8 +77,9 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   auto pb = [&](int x) { return pos_in(lb, x); };
   auto pc = [&](int x) { return pos_in(lc, x); };
   // Row-streaming kernel: K is the lowest k address bits of both A and B, in
-  // the same order; B small.
-  bool rows_ok = k <= 7 && n <= 5 && (int64_t(1) << (n + k)) <= 4096;
+  // the same order; B small.  Outputs of 64 or 128 columns only with sums of
+  // at most 16 (one K chunk, the columns walked in groups).
+  bool rows_ok = k <= 7 && (n <= 5 || (n <= 7 && k <= 4)) && (int64_t(1) << (n + k)) <= 4096;
   for (int p = 0; p < k && rows_ok; ++p) {
     const int xa = la[la.size() - 1 - p];
     rows_ok = pos_in(lb, xa) == p;
@@ -293,15 +310,20 @@ void select_steps(rqc_plan* p) {
       const bool lp_math = m != RQC_F32 && p->lp_on[m][i] && !storage_only;
       int k = lp_math ? p->kern_lp[i] : p->kern[i];
       StepDesc d = lp_math ? p->tmpl_lp[i] : p->tmpl[i];
+      int var = p->tuned_var[m][i];
       if (p->tuned_kern[m][i] >= 0) {
         int kt = p->tuned_kern[m][i];
-        StepDesc dt = make_pair_desc(st.la, st.lb, st.lc, kt);
+        StepDesc dt = step_desc(st, kt, var);
         if (kt == p->tuned_kern[m][i]) {
           k = kt;
           d = dt;
+        } else {
+          var &= ~kVarSwap;
         }
+      } else {
+        var &= ~kVarSwap;
       }
-      d.variant = p->tuned_var[m][i];
+      d.variant = var;
       if (m != RQC_F32 && !lp_math) d.variant |= kVarFP32Math;
       p->sel_desc[m][i] = d;
       p->sel_kern[m][i] = k;
@@ -369,6 +391,7 @@ void bind_plan(rqc_plan* p, void* dev, size_t bytes, hipStream_t s) {
     d.lp_out = 0;
     d.copies = 1;
     d.gs_c = 1;
+    if (d.variant & kVarSwap) swap_operands(d);
     hip_check(launch_step(d, kern, ST_C64, ST_C64, ST_C64, 0, s), "invariant step");
   }
   hip_check(hipStreamSynchronize(s), "bind");
@@ -598,6 +621,7 @@ StepDesc bind_step(rqc_plan* p, const GroupLayout& L, const WsLayout& W, char* w
   d.flag = gflags;
   d.dep_s_c = C.dep_s;
   d.flag_n = gsc;
+  if (d.variant & kVarSwap) swap_operands(d);
   if (L.ksplit[i]) {
     d.ksplit = L.ksplit[i];
     d.P = reinterpret_cast<float2*>(arena + L.p_off[i]);
@@ -611,8 +635,9 @@ hipError_t launch_bound_step(const rqc_plan* p, const GroupLayout& L, size_t i, 
                              int kern, hipStream_t s) {
   const Step& st = p->pd.steps[i];
   const int lp_kind = L.prec == RQC_F16 ? ST_F16 : (L.prec == RQC_BF16 ? ST_BF16 : 0);
-  return launch_step(d, kern, L.place[st.a].store, L.place[st.b].store, L.place[st.node].store,
-                     lp_kind, s);
+  const bool swap = (d.variant & kVarSwap) != 0;
+  const int sa = L.place[swap ? st.b : st.a].store, sb = L.place[swap ? st.a : st.b].store;
+  return launch_step(d, kern, sa, sb, L.place[st.node].store, lp_kind, s);
 }
 
 void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, uint64_t n_ids,
@@ -684,6 +709,7 @@ void record_call(rqc_plan* p, const GroupLayout& L, const WsLayout& W, uint64_t 
           lr.m = st.m, lr.n = st.n, lr.k = st.k;
           lr.copies = d.copies;
           lr.sa = A.store, lr.sb = B.store, lr.sc = C.store;
+          lr.variant = d.variant;
           lr.flops = 8.0 * std::ldexp(1.0, st.m + st.n + st.k) * cp;
           lr.bytes = elsize(A.store) * std::ldexp(1.0, st.m + st.k) * ca +
                      elsize(B.store) * std::ldexp(1.0, st.n + st.k) * cb +

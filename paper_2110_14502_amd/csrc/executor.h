@@ -82,7 +82,7 @@ struct GraphEntry {
 
 // One probed launch of the timing hook.
 struct LaunchRecord {
-  int step, kernel, m, n, k, copies, sa, sb, sc;
+  int step, kernel, m, n, k, copies, sa, sb, sc, variant;
   double flops, bytes;
 };
 
@@ -179,6 +179,15 @@ void report(rqc_plan* p, PendingRun& run, hipStream_t s, rqc_run_report* r, bool
 // kind actually used (MFMA and row-streaming need their shape conditions).
 StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
                         const std::vector<int>& lc, int& kernel);
+
+// The descriptor of step `st` for kernel `kernel` (updated as by
+// make_pair_desc) and variant bits `variant`: built from (B, A) when the
+// variant exchanges the operands (kVarSwap).
+StepDesc step_desc(const Step& st, int& kernel, int variant);
+
+// Exchanges the bound A and B operands of a descriptor (pointers, copy
+// strides and scale arrays); the tile geometry is left as it is.
+void swap_operands(StepDesc& d);
 
 void hip_check(hipError_t e, const char* what);
 

@@ -15,9 +15,10 @@ namespace rqc {
 // steps of one item per workgroup, the workgroups of an XCD taking
 // consecutive items, so that the tiles in flight on an XCD share rows of A.
 // A workgroup loads the first chunk of its next tile while its current
-// tile's last chunk is multiplied and the output stored; the scale and the
-// running max-abs are flushed when the copy changes.  53 KB of LDS; two
-// workgroups per CU.
+// tile's last chunk is multiplied, and writes it to LDS before the current
+// tile's output stores go out, so that those stores drain during the next
+// tile's products; the scale and the running max-abs are flushed when the
+// copy changes.  62 KB of LDS; two workgroups per CU.
 // ---------------------------------------------------------------------------
 constexpr unsigned kMfmaGrid = 256 * 2;
 
@@ -146,14 +147,22 @@ __device__ __forceinline__ void stage_acc(float* Cs, const Acc32<M3>& acc, int l
     }
 }
 
+// LDS of the persistent kernel: buffer b holds A's chunk at b * kPersPair
+// and B's right after it; the output staging area starts at buffer 1 and
+// runs past it, so that buffer 0 can take the next tile's first chunk while
+// the current tile's output is staged.
+constexpr int kPersPair = kABuf + 2 * kBBuf;
+constexpr int kPersFloats = kPersPair + kCHalf;
+static_assert(kPersFloats >= 2 * kPersPair && kPersPair % 4 == 0, "persistent LDS layout");
+
 template <int SA, int SB, int SC, bool M3>
 __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items) {
-  __shared__ float lds[kMainFloats + 16];
+  __shared__ float lds[kPersFloats + 16];
   __shared__ TileTab tcs;
   __shared__ OuterTab ot;
-  float* Abuf = lds;                                          // [2][kTK][2][kAPlane]
-  float2* Bbuf = reinterpret_cast<float2*>(lds + 2 * kABuf);  // [2][kTK][kBStride]
-  float* red = lds + kMainFloats;
+  float* Abuf = lds;                                      // [2][kTK][2][kAPlane], pair stride
+  float2* Bbuf = reinterpret_cast<float2*>(lds + kABuf);  // [2][kTK][kBStride], pair stride
+  float* red = lds + kPersFloats;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
@@ -223,8 +232,8 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
     for (int j = 0; j < 4; ++j) rb[j] = load_c<SB>(d.B, oB + kB + gB[j]);
   };
   auto store_chunk = [&](int buf) {
-    float* An = Abuf + buf * kABuf;
-    float2* Bn = Bbuf + buf * kBBuf;
+    float* An = Abuf + buf * kPersPair;
+    float2* Bn = Bbuf + buf * (kPersPair / 2);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       An[lA[j]] = ra[j].x;
@@ -274,31 +283,49 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
     Acc32<M3> acc;
     acc_zero(acc);
 
-    for (int kc = 0; kc < n_kc; ++kc) {
+    // Every chunk but the last: the next chunk is loaded while this one is
+    // multiplied.  The products run at raised wave priority, so that the
+    // other workgroup's epilogue on this CU does not hold back their issue.
+    for (int kc = 0; kc + 1 < n_kc; ++kc) {
       const int cb = kc & 1;
-      const bool more = kc + 1 < n_kc;
-      // Next chunk of this tile, or the first chunk of the next tile (kept
-      // in registers until the output of this tile has left the LDS).
-      if (more) {
-        load_chunk(oA, oB, kc + 1);
-      } else if (next_tile) {
-        const int cn = (int)((t + G) >> tb);
-        if (cn != copy) nsc = compute_scale(d, cn % d.gs_c, cn / d.gs_c);
-        int64_t pA, pB, pC;
-        item_offsets(t + G, pA, pB, pC);
-        load_chunk(pA, pB, 0);
-      }
-      // The products run at raised wave priority, so that the other
-      // workgroup's epilogue on this CU does not hold back their issue.
+      load_chunk(oA, oB, kc + 1);
       __builtin_amdgcn_s_setprio(1);
-      chunk_mfma<M3>(Abuf + cb * kABuf, Bbuf + cb * kBBuf, lane, wm, wn, acc);
+      chunk_mfma<M3>(Abuf + cb * kPersPair, Bbuf + cb * (kPersPair / 2), lane, wm, wn, acc);
       __builtin_amdgcn_s_setprio(0);
-      if (more) store_chunk(cb ^ 1);
+      store_chunk(cb ^ 1);
       __syncthreads();
     }
+    // The last chunk: meanwhile the next tile's first chunk is loaded, and
+    // at a copy change the next copy's scale inputs before it.
+    bool new_copy = false;
+    ScaleIn nin{0, 0, 0.f, 0.f};
+    if (next_tile) {
+      const int cn = (int)((t + G) >> tb);
+      new_copy = cn != copy;
+      if (new_copy) nin = load_scale(d, cn % d.gs_c, cn / d.gs_c);
+      int64_t pA, pB, pC;
+      item_offsets(t + G, pA, pB, pC);
+      load_chunk(pA, pB, 0);
+    }
+    {
+      const int cb = (n_kc - 1) & 1;
+      __builtin_amdgcn_s_setprio(1);
+      chunk_mfma<M3>(Abuf + cb * kPersPair, Bbuf + cb * (kPersPair / 2), lane, wm, wn, acc);
+      __builtin_amdgcn_s_setprio(0);
+    }
+    __syncthreads();
+    // The next tile's first chunk goes to buffer 0 (free since the barrier
+    // above) before this tile's output stores are issued: the vector memory
+    // counter completes in issue order, so a wait for these loads placed
+    // after the stores would also wait for the stores to finish.
+    if (next_tile) {
+      store_chunk(0);
+      if (new_copy) nsc = scale_of(d, nin);
+    }
 
-    // Epilogue: two halves of 64 rows staged in the operand buffers.
-    float* Cs = lds;
+    // Epilogue: two halves of 64 rows staged from buffer 1 on; the first
+    // barrier also publishes buffer 0.
+    float* Cs = lds + kPersPair;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (wm == h) stage_acc<M3>(Cs, acc, lane, wn);
@@ -307,10 +334,6 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
         store_half4<SC>(d, Cs, tcs, oC + g_lo4 + (h ? g_half : 0), c_lo4, tid, sc, lmax, bad);
       else
         store_half<SC, 8>(d, Cs, tcs, oC + g_lane + (h ? g_half : 0), c_lane, wave, sc, lmax, bad);
-      __syncthreads();
-    }
-    if (next_tile) {
-      store_chunk(0);
       __syncthreads();
     }
   }

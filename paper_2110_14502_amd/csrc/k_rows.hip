@@ -168,7 +168,10 @@ __device__ __forceinline__ void load_tile_rows(const StepDesc& d, int64_t oA, in
 // and the running max-abs change only with the copy; the rows of the next
 // tile (or K chunk) are loaded while the current one is multiplied and
 // written.  KB: bits of one K chunk (the whole sum when k <= 4); NCH: chunks
-// of 8 complex output columns, whose accumulators stay in registers.
+// of 8 complex output columns, whose accumulators stay in registers.  Wider
+// outputs (up to 128 columns, sums of at most 16) are walked in groups of
+// NCH chunks with the tile's rows held in registers, so that an
+// output-heavy step streams its output at the same register cost.
 template <int KB, int NCH, int SA, bool ALLOW16>
 __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   constexpr int K = 1 << KB;
@@ -176,14 +179,16 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
   constexpr bool LPM = ALLOW16 && SA != ST_C64 && KB >= 4;  // 16-bit matrix cores
   extern __shared__ __attribute__((aligned(16))) float2 rows_lds[];  // 16-byte B reads
   __shared__ TileTab tc;
-  __shared__ int64_t bofs[64];
+  __shared__ int64_t bofs[128];  // B offset of output column n (N <= 128)
   __shared__ int64_t stepA[kMaxOuter], stepC[kMaxOuter];
-  __shared__ int64_t gch_tab[4];  // C offset of column chunk h
+  __shared__ int64_t gch_tab[16];  // C offset of column chunk h
   __shared__ float red[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, lc = lane & 15;
   const int N = 1 << d.nt, R = 1 << d.rt, NC = 1 << d.ncb;
   const int KT = 1 << d.kt, nkc = 1 << (d.kt - KB);
+  const int nch_all = N / NC;                          // column chunks of NC columns
+  const int ncg = nch_all > NCH ? nch_all / NCH : 1;   // groups of NCH (nkc == 1 when > 1)
   // Row tile ro -> ro + 1 sets the lowest zero bit b of ro and clears the
   // bits below it: the offsets move by stepA[b] / stepC[b].
   for (int b = tid; b < d.n_ro; b += 256) {
@@ -195,7 +200,7 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
     stepA[b] = sa;
     stepC[b] = sc;
   }
-  if (tid < NCH) {
+  if (tid < nch_all) {
     int64_t g = 0;
     for (int j = 0; j < d.nt - d.ncb; ++j)
       if ((tid >> j) & 1) g += int64_t(1) << d.nh_C[j];
@@ -295,157 +300,168 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
       __syncthreads();
     }
     wexp = wexp || ro == 0;
-    floatx4 acc[4][NCH];
+    for (int cg = 0; cg < ncg; ++cg) {
+      const bool last_cg = cg + 1 == ncg;
+      floatx4 acc[4][NCH];
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int h = 0; h < NCH; ++h) acc[rb][h] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < nkc; ++kc) {
-      // Prefetch the next K chunk, or the first chunk of the next tile; the
-      // registers are handed over only after this chunk (or, for the next
-      // tile, after the stores), so the loads stay in flight meanwhile.
-      if (kc + 1 < nkc) {
-        load_tile_rows<SA, K, NJ>(d, oA, KT, kc + 1, R, wave, lc, g, an);
-      } else if (t + 1 < t_end) {
-        const uint64_t tn = t + 1;
-        int64_t pA;
-        if ((tn & rmask) != 0) {
-          pA = oA + stepA[__builtin_ctzll(~ro)];
-        } else {
-          const int cn = (int)(tn >> rsh);
-          int64_t pB, pC;
-          outer_offsets(d, 0, 0, cn % d.gs_c, cn / d.gs_c, pA, pB, pC);
+        for (int h = 0; h < NCH; ++h) acc[rb][h] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int kc = 0; kc < nkc; ++kc) {
+        // Prefetch the next K chunk, or the first chunk of the next tile; the
+        // registers are handed over only after this chunk (or, for the next
+        // tile, at its end), so the loads stay in flight meanwhile.
+        if (kc + 1 < nkc) {
+          load_tile_rows<SA, K, NJ>(d, oA, KT, kc + 1, R, wave, lc, g, an);
+        } else if (last_cg && t + 1 < t_end) {
+          const uint64_t tn = t + 1;
+          int64_t pA;
+          if ((tn & rmask) != 0) {
+            pA = oA + stepA[__builtin_ctzll(~ro)];
+          } else {
+            const int cn = (int)(tn >> rsh);
+            int64_t pB, pC;
+            outer_offsets(d, 0, 0, cn % d.gs_c, cn / d.gs_c, pA, pB, pC);
+          }
+          load_tile_rows<SA, K, NJ>(d, pA, KT, 0, R, wave, lc, g, an);
         }
-        load_tile_rows<SA, K, NJ>(d, pA, KT, 0, R, wave, lc, g, an);
-      }
-      if constexpr (LPM) {
-        // MFMA j takes real k g*NJ + 8j .. +7 of every lane quarter: the raw
-        // words 4j .. 4j+3 of A, and four packed complex values of B
-        // expanded to (Br, -Bi) (column parity 0) or (Bi, Br) (parity 1).
-        // Lanes past the chunk's columns read column NC-1 (their results are
-        // never stored), so that no read is conditional; the expansion is a
-        // rotation by 0 / 16 bits and an xor with a per-lane sign mask (a
-        // select between the two forms of a loaded word would be compiled
-        // into a branch per word).
-        const uint32_t* Bw = reinterpret_cast<const uint32_t*>(Bs);
-        const int ncl = (lc >> 1) < NC ? (lc >> 1) : NC - 1;
-        const uint32_t brot = (lc & 1) ? 16u : 0u, bflip = (lc & 1) ? 0u : 0x80000000u;
+        if constexpr (LPM) {
+          // MFMA j takes real k g*NJ + 8j .. +7 of every lane quarter: the raw
+          // words 4j .. 4j+3 of A, and four packed complex values of B
+          // expanded to (Br, -Bi) (column parity 0) or (Bi, Br) (parity 1).
+          // Lanes past the chunk's columns read column NC-1 (their results are
+          // never stored), so that no read is conditional; the expansion is a
+          // rotation by 0 / 16 bits and an xor with a per-lane sign mask (a
+          // select between the two forms of a loaded word would be compiled
+          // into a branch per word).
+          const uint32_t* Bw = reinterpret_cast<const uint32_t*>(Bs);
+          const int ncl = (lc >> 1) < NC ? (lc >> 1) : NC - 1;
+          const uint32_t brot = (lc & 1) ? 16u : 0u, bflip = (lc & 1) ? 0u : 0x80000000u;
 #pragma unroll
-        for (int h = 0; h < NCH; ++h) {
-          const int n = h * NC + ncl;
+          for (int h = 0; h < NCH; ++h) {
+            const int n = (cg * NCH + h) * NC + ncl;
 #pragma unroll
-          for (int j = 0; j < NJ / 8; ++j) {
-            u32x4r bw = *reinterpret_cast<const u32x4r*>(Bw + n * KT + kc * K + g * (NJ / 2) + 4 * j);
+            for (int j = 0; j < NJ / 8; ++j) {
+              u32x4r bw =
+                *reinterpret_cast<const u32x4r*>(Bw + n * KT + kc * K + g * (NJ / 2) + 4 * j);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) bw[i] = __builtin_amdgcn_alignbit(bw[i], bw[i], brot) ^ bflip;
+              for (int i = 0; i < 4; ++i)
+                bw[i] = __builtin_amdgcn_alignbit(bw[i], bw[i], brot) ^ bflip;
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-              const u32x4r aw = {a[rb].w[4 * j], a[rb].w[4 * j + 1], a[rb].w[4 * j + 2],
-                                 a[rb].w[4 * j + 3]};
-              acc[rb][h] = mfma_lp16<LPM ? SA : ST_F16>(aw, bw, acc[rb][h]);
+              for (int rb = 0; rb < 4; ++rb) {
+                const u32x4r aw = {a[rb].w[4 * j], a[rb].w[4 * j + 1], a[rb].w[4 * j + 2],
+                                   a[rb].w[4 * j + 3]};
+                acc[rb][h] = mfma_lp16<LPM ? SA : ST_F16>(aw, bw, acc[rb][h]);
+              }
             }
           }
-        }
-      } else {
-        float af[4][NJ];
-  #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) unpack_raw<SA, K, NJ>(a[rb], g, af[rb]);
-  #pragma unroll
-        for (int h = 0; h < NCH; ++h) {
-          // B operand: real column lc of column chunk h (complex column
-          // h*NC + lc/2, part lc&1), real summation index of MFMA j.
-          // Unconditional reads (clamped column and summation index: the
-          // lanes they serve either hold zero rows of A, K = 1, or columns
-          // that are never stored), so that no LDS read sits in a branch.
-          float bop[NJ];
-          const int n = h * NC + ((lc >> 1) < NC ? (lc >> 1) : NC - 1), q = lc & 1;
-  #pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            const int rk = K >= 2 ? g * NJ + j : g;
-            const int kk = (rk >> 1) < K ? (rk >> 1) : K - 1;
-            const float2 b = Bs[n * KT + kc * K + kk];
-            bop[j] = (rk & 1) == 0 ? (q == 0 ? b.x : b.y) : (q == 0 ? -b.y : b.x);
+        } else {
+          float af[4][NJ];
+    #pragma unroll
+          for (int rb = 0; rb < 4; ++rb) unpack_raw<SA, K, NJ>(a[rb], g, af[rb]);
+    #pragma unroll
+          for (int h = 0; h < NCH; ++h) {
+            // B operand: real column lc of column chunk h (complex column
+            // h*NC + lc/2, part lc&1), real summation index of MFMA j.
+            // Unconditional reads (clamped column and summation index: the
+            // lanes they serve either hold zero rows of A, K = 1, or columns
+            // that are never stored), so that no LDS read sits in a branch.
+            float bop[NJ];
+            const int n = (cg * NCH + h) * NC + ((lc >> 1) < NC ? (lc >> 1) : NC - 1), q = lc & 1;
+    #pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+              const int rk = K >= 2 ? g * NJ + j : g;
+              const int kk = (rk >> 1) < K ? (rk >> 1) : K - 1;
+              const float2 b = Bs[n * KT + kc * K + kk];
+              bop[j] = (rk & 1) == 0 ? (q == 0 ? b.x : b.y) : (q == 0 ? -b.y : b.x);
+            }
+    #pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+    #pragma unroll
+              for (int j = 0; j < NJ; ++j)
+                acc[rb][h] =
+                    __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][j], bop[j], acc[rb][h], 0, 0, 0);
           }
-  #pragma unroll
+        }
+        if (kc + 1 < nkc) {
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb) a[rb] = an[rb];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) {
+        __syncthreads();
+        // Lane holds rows 4g..4g+3 of each 16-row block at real column lc.
+        if (lc < 2 * NC) {
+#pragma unroll
           for (int rb = 0; rb < 4; ++rb)
-  #pragma unroll
-            for (int j = 0; j < NJ; ++j)
-              acc[rb][h] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][j], bop[j], acc[rb][h], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int r = wave * 64 + rb * 16 + 4 * g + i;
+              if (r < R) Cs[r * kRowsLdc + lc] = acc[rb][h][i];
+            }
         }
-      }
-      if (kc + 1 < nkc) {
+        __syncthreads();
+        // The next tile's rows (loaded during this tile) are waited for here,
+        // before this tile's stores are issued: the vector memory counter
+        // completes in issue order, so the compiler's wait for them at the
+        // hand-over below would also wait for the stores to finish.
+        if (h == 0 && last_cg) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        const int64_t gch = gch_tab[cg * NCH + h];
+        // At most 2048 staged elements (256 rows x 8 columns): eight per
+        // thread, or two groups of four.  Table and staging reads are issued
+        // together before the stores so that their latencies overlap.
+        if (d.vec_c) {
+          int64_t g[2];
+          int32_t cc[2];
+          float2 x[2][4];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) a[rb] = an[rb];
-      }
-    }
-#pragma unroll
-    for (int h = 0; h < NCH; ++h) {
-      __syncthreads();
-      // Lane holds rows 4g..4g+3 of each 16-row block at real column lc.
-      if (lc < 2 * NC) {
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = wave * 64 + rb * 16 + 4 * g + i;
-            if (r < R) Cs[r * kRowsLdc + lc] = acc[rb][h][i];
-          }
-      }
-      __syncthreads();
-      const int64_t gch = gch_tab[h];
-      // At most 2048 staged elements (256 rows x 8 columns): eight per
-      // thread, or two groups of four.  Table and staging reads are issued
-      // together before the stores so that their latencies overlap.
-      if (d.vec_c) {
-        int64_t g[2];
-        int32_t cc[2];
-        float2 x[2][4];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int v = tid + 256 * u;
-          const int hi = 64 + (v < (nC >> 2) ? (v >> 4) : 0);
-          g[u] = tc.g[hi];
-          cc[u] = tc.c[hi];
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int c = clo4[i] + cc[u];
-            x[u][i] = make_float2(Cs[c], Cs[c + 1]);
+          for (int u = 0; u < 2; ++u) {
+            const int v = tid + 256 * u;
+            const int hi = 64 + (v < (nC >> 2) ? (v >> 4) : 0);
+            g[u] = tc.g[hi];
+            cc[u] = tc.c[hi];
           }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (tid + 256 * u >= (nC >> 2)) break;
-          const int64_t at = oC + gch + glo4 + g[u];
-          if (d.sc_store == ST_F16) store_out4<ST_F16>(d, at, x[u], sc, lmax, bad);
-          else if (d.sc_store == ST_BF16) store_out4<ST_BF16>(d, at, x[u], sc, lmax, bad);
-          else store_out4<ST_C64>(d, at, x[u], sc, lmax, bad);
-        }
-      } else {
-        int64_t g[8];
-        int32_t cc[8];
-        float2 x[8];
+          for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int e = tid + 256 * u;
-          const int hi = 64 + (e < nC ? (e >> 6) : 0);
-          g[u] = tc.g[hi];
-          cc[u] = clo + tc.c[hi];
-        }
+            for (int i = 0; i < 4; ++i) {
+              const int c = clo4[i] + cc[u];
+              x[u][i] = make_float2(Cs[c], Cs[c + 1]);
+            }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = make_float2(Cs[cc[u]], Cs[cc[u] + 1]);
+          for (int u = 0; u < 2; ++u) {
+            if (tid + 256 * u >= (nC >> 2)) break;
+            const int64_t at = oC + gch + glo4 + g[u];
+            if (d.sc_store == ST_F16) store_out4<ST_F16>(d, at, x[u], sc, lmax, bad);
+            else if (d.sc_store == ST_BF16) store_out4<ST_BF16>(d, at, x[u], sc, lmax, bad);
+            else store_out4<ST_C64>(d, at, x[u], sc, lmax, bad);
+          }
+        } else {
+          int64_t g[8];
+          int32_t cc[8];
+          float2 x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (tid + 256 * u >= nC) break;
-          const int64_t at = oC + gch + glo + g[u];
-          if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, x[u], sc, lmax, bad);
-          else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, x[u], sc, lmax, bad);
-          else store_out<ST_C64>(d, at, x[u], sc, lmax, bad);
+          for (int u = 0; u < 8; ++u) {
+            const int e = tid + 256 * u;
+            const int hi = 64 + (e < nC ? (e >> 6) : 0);
+            g[u] = tc.g[hi];
+            cc[u] = clo + tc.c[hi];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] = make_float2(Cs[cc[u]], Cs[cc[u] + 1]);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (tid + 256 * u >= nC) break;
+            const int64_t at = oC + gch + glo + g[u];
+            if (d.sc_store == ST_F16) store_out<ST_F16>(d, at, x[u], sc, lmax, bad);
+            else if (d.sc_store == ST_BF16) store_out<ST_BF16>(d, at, x[u], sc, lmax, bad);
+            else store_out<ST_C64>(d, at, x[u], sc, lmax, bad);
+          }
         }
       }
     }
-    // The next tile's rows (loaded during this tile) become current.
+    // The next tile's rows become current.
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) a[rb] = an[rb];
   }
@@ -476,8 +492,9 @@ template <int KB>
 static hipError_t launch_rows(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
   const int N = 1 << d.nt, R = 1 << d.rt, NC = 1 << d.ncb, KT = 1 << d.kt;
   const int nch = N / NC;
+  // More than four chunks: groups of four, for a single K chunk only.
   if (R > kRowsRows || NC > 8 || N * KT > kRowsMaxB || d.ncb > d.nt || d.kt < KB ||
-      (d.kt > KB && NC != N && nch > 4) || nch > 4)
+      (d.kt > KB && NC != N && nch > 4) || nch > 16 || (nch > 4 && d.kt != KB))
     return hipErrorInvalidValue;
   const size_t lds = sizeof(float2) * (size_t)N * KT + sizeof(float) * (size_t)R * kRowsLdc;
   // Persistent grid: enough workgroups to fill every CU several times over.
@@ -486,7 +503,9 @@ static hipError_t launch_rows(const StepDesc& d, int sa, dim3 grid, hipStream_t 
   switch (nch) {
     case 1: return launch_rows_n<KB, 1>(d, sa, grid, lds, s);
     case 2: return launch_rows_n<KB, 2>(d, sa, grid, lds, s);
-    case 4: return launch_rows_n<KB, 4>(d, sa, grid, lds, s);
+    case 4:
+    case 8:
+    case 16: return launch_rows_n<KB, 4>(d, sa, grid, lds, s);
   }
   return hipErrorInvalidValue;
 }

@@ -95,8 +95,12 @@ struct LeafJob {
 // operands (the row kernel would otherwise use the 16-bit matrix cores).
 // 16-bit matrix-core kernel: kVarStream streams A past a resident B tile
 // (sums of 32..128 terms, A stored in 16 bits).
+// kVarSwap: the operands are exchanged (the kernel's A is the step's B), so
+// that a step with a 128-column output takes one row tile of the kernel and
+// its large operand is read once instead of once per column tile.  The
+// descriptor is built from (B, A) and the executor binds B's data as A.
 constexpr int32_t kVar4M = 1, kVarTiles = 2, kVarPersistent = 4, kVarFP32Math = 8,
-                  kVarStream = 16;
+                  kVarStream = 16, kVarSwap = 32;
 
 // Kernel kinds of a step.
 // KERN_MFMA16: FP16/BF16 matrix cores, 32 complex k per chunk (reduced

@@ -64,9 +64,9 @@ std::vector<std::pair<int, int>> candidates(rqc_plan* p, int m, size_t i) {
   const int cur = p->sel_kern[m][i];
   const int base_var = p->sel_desc[m][i].variant & kVarFP32Math;
   std::vector<std::pair<int, int>> c{{cur, p->sel_desc[m][i].variant}};
-  auto valid = [&](int k) {
+  auto valid = [&](int k, int v = 0) {
     int kk = k;
-    make_pair_desc(st.la, st.lb, st.lc, kk);
+    step_desc(st, kk, v);
     return kk == k;
   };
   auto add = [&](int k, int v) {
@@ -79,7 +79,15 @@ std::vector<std::pair<int, int>> candidates(rqc_plan* p, int m, size_t i) {
   if (fp32_mma && valid(KERN_MFMA))
     for (int v : {kVarTiles, kVarTiles | kVar4M, kVarPersistent, kVarPersistent | kVar4M})
       add(KERN_MFMA, v);
+  // Exchanged operands: a 128- or 256-column output becomes one or two row
+  // tiles, so the large operand is read once or twice instead of two or
+  // four times (the small one stays in L2).
+  if (fp32_mma && st.n >= 7 && st.m > st.n && valid(KERN_MFMA, kVarSwap))
+    for (int v : {kVarTiles, kVarPersistent}) add(KERN_MFMA, v | kVarSwap);
   if (cur == KERN_MFMA16 && st.k >= 5 && st.k <= 7) add(KERN_MFMA16, kVarStream);
+  // Reduced precision: a row-kernel step that the 16-bit matrix-core kernel
+  // can also take.
+  if (m != RQC_F32 && cur == KERN_ROWS && !base_var && valid(KERN_MFMA16)) add(KERN_MFMA16, 0);
   if ((cur == KERN_MFMA || cur == KERN_MFMA16) && valid(KERN_ROWS)) add(KERN_ROWS, 0);
   if (c.size() == 1) c.clear();
   return c;
@@ -168,7 +176,7 @@ void autotune(rqc_plan* p, int prec, uint64_t n_ids, uint64_t n_batch, void* ws_
       double best_ms = 1e30;
       for (size_t c = 0; c < cand.size(); ++c) {
         int k = cand[c].first;
-        StepDesc d0 = make_pair_desc(pd.steps[i].la, pd.steps[i].lb, pd.steps[i].lc, k);
+        StepDesc d0 = step_desc(pd.steps[i], k, cand[c].second);
         if (k != cand[c].first) continue;
         d0.variant = cand[c].second;
         p->sel_desc[prec][i] = d0;

@@ -326,6 +326,34 @@ def test_row_streaming_kernel_plan_layout():
         assert _rel_rms(c.cpu().numpy(), ref) < 2e-5, (m, n, k)
 
 
+def test_row_streaming_kernel_wide_outputs():
+    """Row-streaming kernel on 64- and 128-column outputs with sums of at
+    most 16: the columns are walked in groups of 32 with the rows held in
+    registers.  Full and partial row tiles, every sum length up to 16, and a
+    batch of copies with a shared B."""
+    _say("rows kernel wide")
+    for (m, n, k, seed) in ((12, 6, 4, 121), (13, 7, 4, 122), (9, 7, 2, 123), (7, 6, 3, 124),
+                            (10, 7, 0, 125), (11, 7, 1, 126)):
+        M = list(range(m))
+        N = list(range(100, 100 + n))
+        K = list(range(200, 200 + k))
+        rng = np.random.default_rng(seed)
+        la = [M[i] for i in rng.permutation(m)] + K
+        lb = [N[i] for i in rng.permutation(n)] + K
+        lc = [x for x in (M + N)]
+        lc = [lc[i] for i in rng.permutation(len(lc))]
+        batch = 3 if seed == 122 else 1
+        a = rqcgen.random_complex(batch << (m + k), seed).reshape(batch, -1)
+        b = rqcgen.random_complex(1 << (n + k), seed + 1)
+        c = R.pair_contract(_dev_c64(a.reshape(-1)), _dev_c64(b), la, lb, lc, kernel=2,
+                            batch=batch, stride_a=1 << (m + k), stride_b=0)
+        torch.cuda.synchronize()
+        got = c.cpu().numpy().reshape(batch, -1)
+        for i in range(batch):
+            ref = oracle.einsum_step(a[i], b, la, lb, lc)
+            assert _rel_rms(got[i], ref) < 2e-5, (m, n, k, i)
+
+
 @pytest.mark.parametrize("prec,tol", [("f16", 6e-3), ("bf16", 4e-2)])
 def test_lp_mfma_kernel_vs_einsum(prec, tol):
     """FP16 / BF16 matrix-core contraction: operands rounded to 16 bits

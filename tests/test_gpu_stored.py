@@ -117,6 +117,18 @@ def test_rows_kernel_16bit_matrix_cores(lp):
 
 
 @pytest.mark.parametrize("lp", LP)
+def test_rows_kernel_wide_outputs_16bit(lp):
+    """Row-streaming kernel on 64- and 128-column outputs with a 16-bit
+    stored A: sums of 16 on the 16-bit matrix cores, shorter sums in FP32."""
+    for (m, n, k, seed) in ((12, 7, 4, 131), (11, 6, 4, 132), (12, 7, 3, 133), (9, 6, 1, 134)):
+        _say("rows wide 16-bit", lp, m, n, k)
+        err = _run(m, n, k, seed, lp, lp, R.ST_C64, R.KERN_ROWS, batch=2)
+        assert err < 2e-5, (m, n, k, err)
+        err = _run(m, n, k, seed, lp, lp, lp, R.KERN_ROWS)
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+
+
+@pytest.mark.parametrize("lp", LP)
 def test_rows_kernel_half_storage_fp32_arithmetic(lp):
     """Row-streaming kernel with short sums (k <= 3) on a 16-bit stored A:
     the values are converted and multiplied in FP32."""
@@ -197,6 +209,39 @@ def test_fp32_mfma_variants_vs_einsum(variant):
         ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
         err = _rel_rms(_values(C), ref)
         assert err < 2e-5, (ra, rb, s, variant, err)
+
+
+@pytest.mark.parametrize("variant", [R.VAR_SWAP, R.VAR_SWAP | R.VAR_TILES,
+                                     R.VAR_SWAP | R.VAR_PERSISTENT, R.VAR_SWAP | R.VAR_4M])
+def test_fp32_mfma_exchanged_operands_vs_einsum(variant):
+    """The FP32 matrix-core kernel with A and B exchanged inside the kernel
+    (B's free indices on the tile rows) against einsum: outputs of 128 and
+    256 columns on random index orders, one and several K chunks, and a
+    batch with a per-copy A and a shared B (strides exchanged with the
+    operands)."""
+    _say("mfma32 exchanged operands", variant)
+    for (ra, rb, s, seed) in ((14, 12, 5, 13), (18, 15, 8, 14), (20, 16, 8, 15), (13, 11, 4, 16)):
+        st = rqcgen.synthetic_step(ra, rb, s, seed)
+        a = rqcgen.random_complex(1 << ra, seed + 100)
+        b = rqcgen.random_complex(1 << rb, seed + 200)
+        A, _ = _store(a, R.ST_C64)
+        B, _ = _store(b, R.ST_C64)
+        C = _empty(1 << len(st.labels_c), R.ST_C64)
+        R.pair_contract_stored(A, B, C, st.labels_a, st.labels_b, st.labels_c, R.ST_C64,
+                               R.ST_C64, R.ST_C64, R.KERN_MFMA, variant=variant)
+        torch.cuda.synchronize()
+        ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
+        err = _rel_rms(_values(C), ref)
+        assert err < 2e-5, (ra, rb, s, variant, err)
+    err = _run(9, 7, 5, 17, R.ST_C64, R.ST_C64, R.ST_C64, R.KERN_MFMA, batch=3, variant=variant)
+    assert err < 2e-5, err
+    # B's free indices must fill a row tile: seven or more.
+    la, lb, lc = _plan_layout(10, 6, 4, 18)
+    A, _ = _store(rqcgen.random_complex(1 << 14, 1), R.ST_C64)
+    B, _ = _store(rqcgen.random_complex(1 << 10, 2), R.ST_C64)
+    C = _empty(1 << 16, R.ST_C64)
+    with pytest.raises(R.RqcError):
+        R.pair_contract_stored(A, B, C, la, lb, lc, 0, 0, 0, R.KERN_MFMA, variant=variant)
 
 
 @pytest.mark.parametrize("lp", LP)
