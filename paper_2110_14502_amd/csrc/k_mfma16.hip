@@ -87,8 +87,8 @@ struct CopyScale {
 };
 template <int LP, int SA, int SB>
 __device__ __forceinline__ CopyScale lp_copy_scale(const StepDesc& d, int js, int jb) {
-  const float mA = d.maxA ? d.maxA[js * d.eA_s + jb * d.eA_b] : d.maxA_const;
-  const float mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
+  const float mA = max_abs_of(d.maxA, js * d.eA_s + jb * d.eA_b, d.maxA_const);
+  const float mB = max_abs_of(d.maxB, js * d.eB_s + jb * d.eB_b, d.maxB_const);
   const int EA = mA > 0.f ? ceil_log2(mA) : 0, EB = mB > 0.f ? ceil_log2(mB) : 0;
   CopyScale r;
   r.pA = (SA == LP || mA <= 0.f) ? 0 : 14 - EA;

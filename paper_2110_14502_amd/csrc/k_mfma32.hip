@@ -296,13 +296,12 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
       __syncthreads();
     }
     // The last chunk: meanwhile the next tile's first chunk is loaded, and
-    // at a copy change the next copy's scale inputs before it.
-    bool new_copy = false;
+    // the scale inputs of its copy before it (unconditionally: loads and
+    // uses under one condition keep the compiler's wait counts exact).
     ScaleIn nin{0, 0, 0.f, 0.f};
     if (next_tile) {
       const int cn = (int)((t + G) >> tb);
-      new_copy = cn != copy;
-      if (new_copy) nin = load_scale(d, cn % d.gs_c, cn / d.gs_c);
+      nin = load_scale(d, cn % d.gs_c, cn / d.gs_c);
       int64_t pA, pB, pC;
       item_offsets(t + G, pA, pB, pC);
       load_chunk(pA, pB, 0);
@@ -320,7 +319,7 @@ __global__ __launch_bounds__(256, 2) void k_mfma32(StepDesc d, uint64_t n_items)
     // after the stores would also wait for the stores to finish.
     if (next_tile) {
       store_chunk(0);
-      if (new_copy) nsc = scale_of(d, nin);
+      nsc = scale_of(d, nin);
     }
 
     // Epilogue: two halves of 64 rows staged from buffer 1 on; the first

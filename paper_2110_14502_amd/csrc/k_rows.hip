@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
       // removes (the stored exponent is unchanged).
       int pB = 0;
       if (LPM && d.sb_store == ST_C64) {
-        const float mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
+        const float mB = max_abs_of(d.maxB, js * d.eB_s + jb * d.eB_b, d.maxB_const);
         if (mB > 0.f && mB <= 3.0e38f) pB = 14 - ceil_log2(mB);
       }
       for (int i = tid; i < N * KT; i += 256) {

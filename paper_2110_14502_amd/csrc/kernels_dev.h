@@ -109,6 +109,17 @@ struct Scale {
 __device__ __forceinline__ int target_log2(const StepDesc& d) {
   return d.lp_out ? 15 + d.bias : kC64Target;
 }
+// An operand's max-abs value: the array entry, or the step's constant when
+// there is no array.  The load stays a global-memory load: written as
+// `p ? p[i] : c` the compiler may select between the two addresses and load
+// through a generic pointer, and a pending generic (FLAT) load makes every
+// later wait of the wave wait for all of its memory operations.
+typedef __attribute__((address_space(1))) const float global_float;
+__device__ __forceinline__ float max_abs_of(const float* p, int64_t i, float c) {
+  if (!p) return c;
+  return ((global_float*)p)[i];
+}
+
 // The operands' exponents and max-abs values of copy (js, jb): read by
 // load_scale, turned into the copy's Scale by scale_of.  Kept apart so that a
 // kernel can issue the reads early and use them later.
@@ -122,8 +133,8 @@ __device__ __forceinline__ ScaleIn load_scale(const StepDesc& d, int js, int jb)
   if (!d.track) return r;
   r.eA = d.expA ? d.expA[js * d.eA_s + jb * d.eA_b] : 0;
   r.eB = d.expB ? d.expB[js * d.eB_s + jb * d.eB_b] : 0;
-  r.mA = d.maxA ? d.maxA[js * d.eA_s + jb * d.eA_b] : d.maxA_const;
-  r.mB = d.maxB ? d.maxB[js * d.eB_s + jb * d.eB_b] : d.maxB_const;
+  r.mA = max_abs_of(d.maxA, js * d.eA_s + jb * d.eA_b, d.maxA_const);
+  r.mB = max_abs_of(d.maxB, js * d.eB_s + jb * d.eB_b, d.maxB_const);
   return r;
 }
 
