@@ -297,6 +297,157 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(StepDesc d) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Streaming dot products for tiny outputs with long contiguous sums (the last
+// steps of an amplitude contraction: up to 8 x 8 outputs, 2^18 summed terms):
+// the summed indices are the lowest address bits of A and B, in the same
+// order, so every row of A and every column of B is a contiguous run of K
+// complex values.  Each thread reads two consecutive complex values of every
+// row and column per 16-byte load (consecutive lanes, consecutive values)
+// straight into registers and keeps all 2^LOGN outputs in registers; no LDS
+// staging.  Workgroup `split` of a copy sums its K range; the 64 lanes of a
+// wave are combined by recursive halving (each exchange step halves the
+// outputs a lane holds, so lane l ends with output l), the four waves in wave
+// order, and the partial goes to the split-K buffer, summed by
+// k_splitk_reduce in split order: the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <int RT, int NT>
+__global__ __launch_bounds__(kSimtBlock) void k_dot(StepDesc d) {
+  constexpr int M = 1 << RT, N = 1 << NT, LOGN = RT + NT, NOUT = M * N;
+  __shared__ int64_t coff[NOUT];
+  __shared__ float2 wsum[kSimtBlock / 64][NOUT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < NOUT; i += kSimtBlock) {
+    int64_t c = 0;  // C offset of output i = r * N + n
+    for (int x = 0; x < d.tC.nbits; ++x) {
+      const int v = d.tC.role[x] == 0 ? i / N : i % N;
+      if ((v >> d.tC.cbit[x]) & 1) c += int64_t(1) << d.tC.gpos[x];
+    }
+    coff[i] = c;
+  }
+  // Offsets of the rows of A and the columns of B (the same in every
+  // thread, so the compiler keeps them in scalar registers).
+  int64_t arow[M], bcol[N];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    arow[i] = 0;
+    for (int x = 0; x < d.tA.nbits; ++x)
+      if (d.tA.role[x] == 0 && ((i >> d.tA.cbit[x]) & 1)) arow[i] += int64_t(1) << d.tA.gpos[x];
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    bcol[j] = 0;
+    for (int x = 0; x < d.tB.nbits; ++x)
+      if (d.tB.role[x] == 1 && ((j >> d.tB.cbit[x]) & 1)) bcol[j] += int64_t(1) << d.tB.gpos[x];
+  }
+  __syncthreads();
+  const int64_t Ks = int64_t(1) << (d.k_total - d.ksplit);
+  const int64_t k0 = (int64_t)blockIdx.x * Ks;
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
+    const int js = copy % d.gs_c, jb = copy / d.gs_c;
+    const int64_t oA = js * d.sA_s + jb * d.sA_b, oB = js * d.sB_s + jb * d.sB_b;
+    const int64_t oC = js * d.sC_s + jb * d.sC_b;
+    // Row i of A from summed index k0 on, as 16-byte pairs of complex values.
+    const f4v* pa[M];
+    const f4v* pb[N];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+      pa[i] = reinterpret_cast<const f4v*>(reinterpret_cast<const float2*>(d.A) + oA + arow[i] + k0);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      pb[j] = reinterpret_cast<const f4v*>(reinterpret_cast<const float2*>(d.B) + oB + bcol[j] + k0);
+    float ax[NOUT], ay[NOUT];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) ax[o] = ay[o] = 0.f;
+    const int npair = (int)(Ks >> 1);
+    for (int p = tid; p < npair; p += kSimtBlock) {
+      f4v a[M], b[N];
+#pragma unroll
+      for (int i = 0; i < M; ++i) a[i] = pa[i][p];
+#pragma unroll
+      for (int j = 0; j < N; ++j) b[j] = pb[j][p];
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) {
+        const f4v& x = a[o / N];
+        const f4v& y = b[o % N];
+        ax[o] += x[0] * y[0] - x[1] * y[1] + x[2] * y[2] - x[3] * y[3];
+        ay[o] += x[0] * y[1] + x[1] * y[0] + x[2] * y[3] + x[3] * y[2];
+      }
+    }
+    // Recursive halving over the wave: at offset s a lane keeps the lower
+    // or upper half of its outputs ((lane & s) set: upper) and adds the
+    // partner's copy of that half.
+    int cnt = NOUT;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+      if (cnt > 1) {
+        const int h = cnt >> 1;
+        const bool up = (lane & s) != 0;
+#pragma unroll
+        for (int o = 0; o < NOUT / 2; ++o) {
+          if (o < h) {
+            const float sx = up ? ax[o] : ax[o + h], sy = up ? ay[o] : ay[o + h];
+            const float kx = up ? ax[o + h] : ax[o], ky = up ? ay[o + h] : ay[o];
+            ax[o] = kx + __shfl_xor(sx, s, 64);
+            ay[o] = ky + __shfl_xor(sy, s, 64);
+          }
+        }
+        cnt = h;
+      } else {
+        ax[0] += __shfl_xor(ax[0], s, 64);
+        ay[0] += __shfl_xor(ay[0], s, 64);
+      }
+    }
+    // Lane l holds output l >> (6 - LOGN).
+    if ((lane & ((64 >> LOGN) - 1)) == 0) wsum[wave][lane >> (6 - LOGN)] = make_float2(ax[0], ay[0]);
+    __syncthreads();
+    if (tid < NOUT) {
+      float sx = 0.f, sy = 0.f;
+#pragma unroll
+      for (int w = 0; w < kSimtBlock / 64; ++w) {
+        sx += wsum[w][tid].x;
+        sy += wsum[w][tid].y;
+      }
+      d.P[(int64_t)blockIdx.x * d.p_stride + oC + coff[tid]] = make_float2(sx, sy);
+    }
+    __syncthreads();
+  }
+}
+
+// Whether a step fits k_dot: one output tile of at most 8 x 8 elements,
+// split K, complex64 operands whose summed indices are the lowest address
+// bits of both, in the same order, and at least 512 summed values per split.
+static bool dot_fits(const StepDesc& d, int sa, int sb, uint64_t tiles) {
+  if (tiles != 1 || d.ksplit == 0 || sa != ST_C64 || sb != ST_C64) return false;
+  if (d.rt > 3 || d.nt > 3 || d.k_total - d.ksplit < 9 || d.n_ro != 0 || d.n_no != 0) return false;
+  for (const TileMap* t : {&d.tA, &d.tB})
+    for (int x = 0; x < t->nbits; ++x)
+      if (t->role[x] == 2 && t->gpos[x] != t->cbit[x]) return false;
+  for (int i = 0; i < d.n_ko; ++i)
+    if (d.ko_A[i] != d.kt + i || d.ko_B[i] != d.kt + i) return false;
+  return true;
+}
+
+template <int RT>
+static void launch_dot_rt(const StepDesc& d, dim3 grid, hipStream_t s) {
+  switch (d.nt) {
+    case 0: hipLaunchKernelGGL((k_dot<RT, 0>), grid, dim3(kSimtBlock), 0, s, d); break;
+    case 1: hipLaunchKernelGGL((k_dot<RT, 1>), grid, dim3(kSimtBlock), 0, s, d); break;
+    case 2: hipLaunchKernelGGL((k_dot<RT, 2>), grid, dim3(kSimtBlock), 0, s, d); break;
+    default: hipLaunchKernelGGL((k_dot<RT, 3>), grid, dim3(kSimtBlock), 0, s, d); break;
+  }
+}
+
+static void launch_dot(const StepDesc& d, dim3 grid, hipStream_t s) {
+  switch (d.rt) {
+    case 0: launch_dot_rt<0>(d, grid, s); break;
+    case 1: launch_dot_rt<1>(d, grid, s); break;
+    case 2: launch_dot_rt<2>(d, grid, s); break;
+    default: launch_dot_rt<3>(d, grid, s); break;
+  }
+}
+
 #define RQC_SIMT_CASE(a, b, c)                                                         \
   if (sa == a && sb == b && sc == c) {                                                 \
     hipLaunchKernelGGL((k_simt<a, b, c>), grid, dim3(kSimtBlock), lds, s, d);         \
@@ -312,6 +463,11 @@ hipError_t launch_simt_kernel(const StepDesc& d, int sa, int sb, int sc, uint64_
   const unsigned gy = (unsigned)(d.copies < 65535 ? d.copies : 65535);
   dim3 grid((unsigned)(tiles << d.ksplit), gy);
   hipError_t e = hipSuccess;
+  if (dot_fits(d, sa, sb, tiles)) {
+    launch_dot(d, grid, s);
+    e = hipGetLastError();
+    goto reduce;
+  }
   {
     const size_t lds = sizeof(float2) * ((size_t)(1 << d.rt) * ((1 << d.kt) + 1) +
                                          (size_t)(1 << d.kt) * ((1 << d.nt) + 1));
