@@ -297,8 +297,13 @@ rqc_status rqc_pair_contract(const int32_t* labels_a, int32_t rank_a,
  * operands, 4 bytes per element per distinct operand copy (a copy stride of
  * 0 shares one copy), and, when the output has fewer than 1024 tiles of
  * 256 x 128, FP32 partial outputs of a split sum (8 bytes per output
- * element per split, summed afterwards in split order).  Arguments as in
- * rqc_pair_contract; EINVAL on bad labels or ranks. */
+ * element per split, summed afterwards in split order).  Also nonzero for
+ * RQC_F32 calls that run on the generic kernel (kernel -1 or 0) with output
+ * tiles too few to fill the GPU and a long sum: the sum is split over
+ * workgroups (as for plan steps) and the workspace holds the complex64
+ * partial outputs, 8 bytes per output element per copy per split, added
+ * afterwards in split order.  Arguments as in rqc_pair_contract; EINVAL on
+ * bad labels or ranks. */
 rqc_status rqc_pair_workspace_bytes(const int32_t* labels_a, int32_t rank_a,
                                     const int32_t* labels_b, int32_t rank_b,
                                     const int32_t* labels_c, int32_t rank_c,
@@ -310,7 +315,9 @@ rqc_status rqc_pair_workspace_bytes(const int32_t* labels_a, int32_t rank_a,
  * (256-byte aligned, at least rqc_pair_workspace_bytes; its contents are
  * overwritten).  Operands are rounded to 16 bits without scaling (values
  * must lie in the 16-bit range) and products accumulate in FP32; C is
- * complex64.  With a batch, stride_c must be at least one output.  Calls
+ * complex64.  With a batch, stride_c must be at least one output.  A split
+ * FP32 sum on the generic kernel needs a batch's outputs back to back
+ * (stride_c = 2^rank_c); with another stride the call runs unsplit.  Calls
  * that need no workspace behave exactly as rqc_pair_contract. */
 rqc_status rqc_pair_contract_ws(const int32_t* labels_a, int32_t rank_a,
                                 const int32_t* labels_b, int32_t rank_b,

@@ -460,6 +460,33 @@ Gemm16Shape gemm16_shape(const std::vector<int>& la, const std::vector<int>& lb,
   return g;
 }
 
+// Split sum of an FP32 call on the generic kernel whose output tiles cannot
+// fill the GPU (as the planner's layouts split plan steps): 2^ks workgroups
+// per output tile, each summing a contiguous range of the summed indices into
+// its own partial buffer (complex64, batch copies of C back to back), added
+// in split order afterwards.  ks = 0: no split.
+struct SimtSplit {
+  int ks = 0;
+  uint64_t bytes = 0;
+};
+
+SimtSplit simt_split(const std::vector<int>& la, const std::vector<int>& lb,
+                     const std::vector<int>& lc, int32_t batch, int32_t kernel, int32_t prec) {
+  SimtSplit sp;
+  if (prec != RQC_F32) return sp;
+  int kern = kernel;
+  const rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, kern);
+  if (kern != rqc::KERN_SIMT || d.n_ko < 2) return sp;
+  const int64_t work = (int64_t)d.n_row_tiles * d.n_col_tiles * batch;
+  int ks = 0;
+  while (ks < d.n_ko && ((work << ks) < 4096 || d.n_ko - ks > 12)) ++ks;
+  const int64_t cbytes = ((int64_t)batch << lc.size()) * 8;
+  while (ks > 0 && (cbytes << ks) > (int64_t(1) << 30)) --ks;
+  sp.ks = ks;
+  sp.bytes = ks ? (uint64_t)(((cbytes << ks) + 255) & ~int64_t(255)) : 0;
+  return sp;
+}
+
 // Output bit i of the permutation of `in` into `out` order: its input bit.
 std::vector<int8_t> perm_sources(const std::vector<int>& in, const std::vector<int>& out) {
   const int r = (int)in.size();
@@ -504,7 +531,7 @@ rqc_status rqc_pair_workspace_bytes(const int32_t* labels_a, int32_t rank_a,
   std::vector<int> la, lb, lc;
   pair_labels(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, batch_count, la, lb, lc);
   const Gemm16Shape g = gemm16_shape(la, lb, lc, batch_count, stride_a, stride_b, kernel, prec);
-  *bytes = g.m < 0 ? 0 : g.total();
+  *bytes = g.m >= 0 ? g.total() : simt_split(la, lb, lc, batch_count, kernel, prec).bytes;
   return RQC_OK;
   RQC_CATCH
 }
@@ -519,9 +546,33 @@ rqc_status rqc_pair_contract_ws(const int32_t* labels_a, int32_t rank_a, const i
   std::vector<int> la, lb, lc;
   pair_labels(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, batch_count, la, lb, lc);
   const Gemm16Shape g = gemm16_shape(la, lb, lc, batch_count, stride_a, stride_b, kernel, prec);
-  if (g.m < 0)
-    return rqc_pair_contract(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, A, B, C,
-                             batch_count, stride_a, stride_b, stride_c, kernel, prec, stream);
+  if (g.m < 0) {
+    const SimtSplit sp = simt_split(la, lb, lc, batch_count, kernel, prec);
+    if (sp.ks == 0 || (batch_count > 1 && stride_c != ((int64_t)1 << rank_c)))
+      return rqc_pair_contract(labels_a, rank_a, labels_b, rank_b, labels_c, rank_c, A, B, C,
+                               batch_count, stride_a, stride_b, stride_c, kernel, prec, stream);
+    if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
+    if (!workspace || ws_bytes < sp.bytes)
+      throw rqc::Error{RQC_EINVAL, "workspace smaller than rqc_pair_workspace_bytes"};
+    if ((uintptr_t)workspace % 256) throw rqc::Error{RQC_EINVAL, "workspace not 256-byte aligned"};
+    int kern = kernel;
+    rqc::StepDesc d = rqc::make_pair_desc(la, lb, lc, kern);
+    d.A = A;
+    d.B = B;
+    d.C = C;
+    d.sA_s = stride_a;
+    d.sB_s = stride_b;
+    d.sC_s = stride_c;
+    d.gs_c = batch_count;
+    d.copies = batch_count;
+    d.ksplit = sp.ks;
+    d.P = static_cast<float2*>(workspace);
+    d.p_stride = (int64_t)batch_count << rank_c;
+    rqc::hip_check(rqc::launch_step(d, kern, rqc::ST_C64, rqc::ST_C64, rqc::ST_C64, 0,
+                                    static_cast<hipStream_t>(stream)),
+                   "pair contract (split sum)");
+    return RQC_OK;
+  }
   if (!A || !B || !C) throw rqc::Error{RQC_EINVAL, "NULL device pointer"};
   if (!workspace || ws_bytes < g.total())
     throw rqc::Error{RQC_EINVAL, "workspace smaller than rqc_pair_workspace_bytes"};

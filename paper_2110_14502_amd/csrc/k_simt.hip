@@ -417,10 +417,10 @@ __global__ __launch_bounds__(kSimtBlock) void k_dot(StepDesc d) {
 
 // Whether a step fits k_dot: one output tile of at most 8 x 8 elements,
 // split K, complex64 operands whose summed indices are the lowest address
-// bits of both, in the same order, and at least 512 summed values per split.
+// bits of both, in the same order, and at least 64 summed values per split.
 static bool dot_fits(const StepDesc& d, int sa, int sb, uint64_t tiles) {
   if (tiles != 1 || d.ksplit == 0 || sa != ST_C64 || sb != ST_C64) return false;
-  if (d.rt > 3 || d.nt > 3 || d.k_total - d.ksplit < 9 || d.n_ro != 0 || d.n_no != 0) return false;
+  if (d.rt > 3 || d.nt > 3 || d.k_total - d.ksplit < 6 || d.n_ro != 0 || d.n_no != 0) return false;
   for (const TileMap* t : {&d.tA, &d.tB})
     for (int x = 0; x < t->nbits; ++x)
       if (t->role[x] == 2 && t->gpos[x] != t->cbit[x]) return false;

@@ -326,6 +326,39 @@ def test_row_streaming_kernel_plan_layout():
         assert _rel_rms(c.cpu().numpy(), ref) < 2e-5, (m, n, k)
 
 
+def test_dot_kernel_tiny_outputs_long_sums():
+    """Tiny outputs (up to 8 x 8) with long sums whose indices are the lowest
+    address bits of both operands in the same order: the streaming dot
+    kernel with split sums (a workspace of partial outputs, added in split
+    order), against einsum; a batch with per-copy A and shared B; and the
+    same shapes with the summed indices not lowest (generic kernel)."""
+    _say("dot kernel")
+    for (m, n, k, batch, seed, lowest) in ((3, 3, 18, 2, 141, True), (2, 3, 16, 1, 142, True),
+                                           (3, 0, 17, 3, 143, True), (1, 1, 14, 1, 144, True),
+                                           (3, 3, 16, 1, 145, False)):
+        M = list(range(m))
+        N = list(range(100, 100 + n))
+        K = list(range(200, 200 + k))
+        rng = np.random.default_rng(seed)
+        la = [M[i] for i in rng.permutation(m)] + K
+        lb = [N[i] for i in rng.permutation(n)] + K
+        if not lowest:
+            la = la[m + 2:] + la[:m + 2]
+        lc = [x for x in (M + N)]
+        lc = [lc[i] for i in rng.permutation(len(lc))]
+        need = R.pair_workspace_bytes(la, lb, lc, -1, batch, 1 << (m + k), 0, R.F32)
+        assert need >= 8 * (batch << (m + n)) * 2, (m, n, k, need)
+        a = rqcgen.random_complex(batch << (m + k), seed).reshape(batch, -1)
+        b = rqcgen.random_complex(1 << (n + k), seed + 1)
+        c = R.pair_contract(_dev_c64(a.reshape(-1)), _dev_c64(b), la, lb, lc, batch=batch,
+                            stride_a=1 << (m + k), stride_b=0)
+        torch.cuda.synchronize()
+        got = c.cpu().numpy().reshape(batch, -1)
+        for i in range(batch):
+            ref = oracle.einsum_step(a[i], b, la, lb, lc)
+            assert _rel_rms(got[i], ref) < fp32_step_tol(k), (m, n, k, i, lowest)
+
+
 def test_row_streaming_kernel_wide_outputs():
     """Row-streaming kernel on 64- and 128-column outputs with sums of at
     most 16: the columns are walked in groups of 32 with the rows held in

@@ -151,6 +151,26 @@ def test_restarts_keep_the_cheapest_plan_and_are_deterministic():
         _plan(4, 4, 8, 1, 2, restarts=-1)
 
 
+def test_fp32_split_sum_workspace_sizes():
+    """FP32 calls on the generic kernel with a tiny output and a long sum take
+    a workspace of complex64 partial outputs: an 8 x 8 output summed over
+    2^18 terms is staged 2^8 terms per chunk (the LDS bound of the generic
+    tile), leaving 2^10 chunks, and splits until 4096 work items or 2^10
+    splits: 8 bytes x 64 outputs x copies x 2^10."""
+    M, N, K = [0, 1, 2], [100, 101, 102], list(range(200, 218))
+    la, lb, lc = M + K, N + K, M + N
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F32) == 8 * 64 * 1024
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F32, kernel=0) == 8 * 64 * 1024
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F32, batch=2, stride_a=1 << 21,
+                                  stride_b=0) == 8 * 128 * 1024
+    # a batch of 64 fills 4096 work items after 2^6 splits
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F32, batch=64, stride_a=1 << 21,
+                                  stride_b=0) == 8 * 64 * 64 * 64
+    assert R.pair_workspace_bytes(la, lb, lc, prec=R.F16) == 0   # 16-bit: no split form here
+    # a short sum is not split
+    assert R.pair_workspace_bytes(M + K[:4], N + K[:4], lc, prec=R.F32) == 0
+
+
 def test_two_phase_16_bit_workspace_sizes():
     """The workspace query picks the two-phase long-sum form only in FP16 /
     BF16 with automatic kernel choice, sums of >= 2^8 terms and at least one
