@@ -302,18 +302,31 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(StepDesc d) {
 // steps of an amplitude contraction: up to 8 x 8 outputs, 2^18 summed terms):
 // the summed indices are the lowest address bits of A and B, in the same
 // order, so every row of A and every column of B is a contiguous run of K
-// complex values.  Each thread reads two consecutive complex values of every
-// row and column per 16-byte load (consecutive lanes, consecutive values)
-// straight into registers and keeps all 2^LOGN outputs in registers; no LDS
-// staging.  Workgroup `split` of a copy sums its K range; the 64 lanes of a
+// complex values.  Each thread reads two consecutive complex64 values (four
+// packed 16-bit pairs) of every row and column per 16-byte load (consecutive
+// lanes, consecutive values) straight into registers and keeps all 2^LOGN
+// outputs in registers, accumulating in FP32; no LDS staging.  Workgroup `split` of a copy sums its K range; the 64 lanes of a
 // wave are combined by recursive halving (each exchange step halves the
 // outputs a lane holds, so lane l ends with output l), the four waves in wave
 // order, and the partial goes to the split-K buffer, summed by
 // k_splitk_reduce in split order: the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
-template <int RT, int NT>
+template <int S>
+__device__ __forceinline__ float2 word_c(uint32_t w) {
+  if constexpr (S == ST_F16) {
+    const h2 h = __builtin_bit_cast(h2, w);
+    return make_float2((float)h.x, (float)h.y);
+  } else {
+    const b2 h = __builtin_bit_cast(b2, w);
+    return make_float2((float)h.x, (float)h.y);
+  }
+}
+
+template <int RT, int NT, int S>
 __global__ __launch_bounds__(kSimtBlock) void k_dot(StepDesc d) {
   constexpr int M = 1 << RT, N = 1 << NT, LOGN = RT + NT, NOUT = M * N;
+  constexpr int G = S == ST_C64 ? 2 : 4;  // complex values per 16-byte load
+  constexpr int EB = S == ST_C64 ? 8 : 4;  // bytes per complex value
   __shared__ int64_t coff[NOUT];
   __shared__ float2 wsum[kSimtBlock / 64][NOUT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -344,35 +357,59 @@ __global__ __launch_bounds__(kSimtBlock) void k_dot(StepDesc d) {
   const int64_t Ks = int64_t(1) << (d.k_total - d.ksplit);
   const int64_t k0 = (int64_t)blockIdx.x * Ks;
   typedef float f4v __attribute__((ext_vector_type(4)));
+  typedef unsigned int u4v __attribute__((ext_vector_type(4)));
   for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     const int64_t oA = js * d.sA_s + jb * d.sA_b, oB = js * d.sB_s + jb * d.sB_b;
     const int64_t oC = js * d.sC_s + jb * d.sC_b;
-    // Row i of A from summed index k0 on, as 16-byte pairs of complex values.
-    const f4v* pa[M];
-    const f4v* pb[N];
+    // Row i of A from summed index k0 on, in 16-byte groups of G values.
+    const u4v* pa[M];
+    const u4v* pb[N];
 #pragma unroll
     for (int i = 0; i < M; ++i)
-      pa[i] = reinterpret_cast<const f4v*>(reinterpret_cast<const float2*>(d.A) + oA + arow[i] + k0);
+      pa[i] = reinterpret_cast<const u4v*>(static_cast<const char*>(d.A) + EB * (oA + arow[i] + k0));
 #pragma unroll
     for (int j = 0; j < N; ++j)
-      pb[j] = reinterpret_cast<const f4v*>(reinterpret_cast<const float2*>(d.B) + oB + bcol[j] + k0);
+      pb[j] = reinterpret_cast<const u4v*>(static_cast<const char*>(d.B) + EB * (oB + bcol[j] + k0));
     float ax[NOUT], ay[NOUT];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) ax[o] = ay[o] = 0.f;
-    const int npair = (int)(Ks >> 1);
-    for (int p = tid; p < npair; p += kSimtBlock) {
-      f4v a[M], b[N];
+    const int ngroup = (int)(Ks / G);
+    for (int p = tid; p < ngroup; p += kSimtBlock) {
+      u4v a[M], b[N];
 #pragma unroll
       for (int i = 0; i < M; ++i) a[i] = pa[i][p];
 #pragma unroll
       for (int j = 0; j < N; ++j) b[j] = pb[j][p];
+      if constexpr (S == ST_C64) {
 #pragma unroll
-      for (int o = 0; o < NOUT; ++o) {
-        const f4v& x = a[o / N];
-        const f4v& y = b[o % N];
-        ax[o] += x[0] * y[0] - x[1] * y[1] + x[2] * y[2] - x[3] * y[3];
-        ay[o] += x[0] * y[1] + x[1] * y[0] + x[2] * y[3] + x[3] * y[2];
+        for (int o = 0; o < NOUT; ++o) {
+          const f4v x = __builtin_bit_cast(f4v, a[o / N]);
+          const f4v y = __builtin_bit_cast(f4v, b[o % N]);
+          ax[o] += x[0] * y[0] - x[1] * y[1] + x[2] * y[2] - x[3] * y[3];
+          ay[o] += x[0] * y[1] + x[1] * y[0] + x[2] * y[3] + x[3] * y[2];
+        }
+      } else {
+        float2 bf[N][4];
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bf[j][q] = word_c<S>(b[j][q]);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          float2 af[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) af[q] = word_c<S>(a[i][q]);
+#pragma unroll
+          for (int j = 0; j < N; ++j) {
+            const int o = i * N + j;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              ax[o] += af[q].x * bf[j][q].x - af[q].y * bf[j][q].y;
+              ay[o] += af[q].x * bf[j][q].y + af[q].y * bf[j][q].x;
+            }
+          }
+        }
       }
     }
     // Recursive halving over the wave: at offset s a lane keeps the lower
@@ -416,10 +453,11 @@ __global__ __launch_bounds__(kSimtBlock) void k_dot(StepDesc d) {
 }
 
 // Whether a step fits k_dot: one output tile of at most 8 x 8 elements,
-// split K, complex64 operands whose summed indices are the lowest address
-// bits of both, in the same order, and at least 64 summed values per split.
+// split K, operands in one storage type (complex64, or both FP16 or both
+// BF16) whose summed indices are the lowest address bits of both, in the
+// same order, and at least 64 summed values per split.
 static bool dot_fits(const StepDesc& d, int sa, int sb, uint64_t tiles) {
-  if (tiles != 1 || d.ksplit == 0 || sa != ST_C64 || sb != ST_C64) return false;
+  if (tiles != 1 || d.ksplit == 0 || sa != sb) return false;
   if (d.rt > 3 || d.nt > 3 || d.k_total - d.ksplit < 6 || d.n_ro != 0 || d.n_no != 0) return false;
   for (const TileMap* t : {&d.tA, &d.tB})
     for (int x = 0; x < t->nbits; ++x)
@@ -429,23 +467,30 @@ static bool dot_fits(const StepDesc& d, int sa, int sb, uint64_t tiles) {
   return true;
 }
 
-template <int RT>
+template <int RT, int S>
 static void launch_dot_rt(const StepDesc& d, dim3 grid, hipStream_t s) {
   switch (d.nt) {
-    case 0: hipLaunchKernelGGL((k_dot<RT, 0>), grid, dim3(kSimtBlock), 0, s, d); break;
-    case 1: hipLaunchKernelGGL((k_dot<RT, 1>), grid, dim3(kSimtBlock), 0, s, d); break;
-    case 2: hipLaunchKernelGGL((k_dot<RT, 2>), grid, dim3(kSimtBlock), 0, s, d); break;
-    default: hipLaunchKernelGGL((k_dot<RT, 3>), grid, dim3(kSimtBlock), 0, s, d); break;
+    case 0: hipLaunchKernelGGL((k_dot<RT, 0, S>), grid, dim3(kSimtBlock), 0, s, d); break;
+    case 1: hipLaunchKernelGGL((k_dot<RT, 1, S>), grid, dim3(kSimtBlock), 0, s, d); break;
+    case 2: hipLaunchKernelGGL((k_dot<RT, 2, S>), grid, dim3(kSimtBlock), 0, s, d); break;
+    default: hipLaunchKernelGGL((k_dot<RT, 3, S>), grid, dim3(kSimtBlock), 0, s, d); break;
   }
 }
 
-static void launch_dot(const StepDesc& d, dim3 grid, hipStream_t s) {
+template <int S>
+static void launch_dot_s(const StepDesc& d, dim3 grid, hipStream_t s) {
   switch (d.rt) {
-    case 0: launch_dot_rt<0>(d, grid, s); break;
-    case 1: launch_dot_rt<1>(d, grid, s); break;
-    case 2: launch_dot_rt<2>(d, grid, s); break;
-    default: launch_dot_rt<3>(d, grid, s); break;
+    case 0: launch_dot_rt<0, S>(d, grid, s); break;
+    case 1: launch_dot_rt<1, S>(d, grid, s); break;
+    case 2: launch_dot_rt<2, S>(d, grid, s); break;
+    default: launch_dot_rt<3, S>(d, grid, s); break;
   }
+}
+
+static void launch_dot(const StepDesc& d, int sa, dim3 grid, hipStream_t s) {
+  if (sa == ST_F16) launch_dot_s<ST_F16>(d, grid, s);
+  else if (sa == ST_BF16) launch_dot_s<ST_BF16>(d, grid, s);
+  else launch_dot_s<ST_C64>(d, grid, s);
 }
 
 #define RQC_SIMT_CASE(a, b, c)                                                         \
@@ -464,7 +509,7 @@ hipError_t launch_simt_kernel(const StepDesc& d, int sa, int sb, int sc, uint64_
   dim3 grid((unsigned)(tiles << d.ksplit), gy);
   hipError_t e = hipSuccess;
   if (dot_fits(d, sa, sb, tiles)) {
-    launch_dot(d, grid, s);
+    launch_dot(d, sa, grid, s);
     e = hipGetLastError();
     goto reduce;
   }
