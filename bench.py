@@ -202,26 +202,49 @@ def kernel_source_hash(root, kind):
     return h.hexdigest()
 
 
-def _profile_traffic(kind, prec, flops_per_launch, bytes_per_launch):
-    """HBM bytes per launch of a kernel kind from a committed counter
-    summary, or None when the summary does not match: the kernel sources
-    changed since the counters were taken, or its launches were different."""
+def _profile_traffic(kind, prec, launches):
+    """Counter traffic over algorithmic bytes of a kernel kind's launches,
+    from a committed counter summary: each launch takes the measured ratio of
+    its shape (m, n, k, copies) in the summary's table, or the ratio of the
+    summary's remaining small launches; None when the kernel sources changed
+    since the counters were taken, or when launches of shapes the table does
+    not hold carry more than 5% of the bytes (the tuner put a step the
+    summary did not see on this kernel)."""
     root = os.path.dirname(os.path.abspath(__file__))
     try:
         text = open(os.path.join(root, "profiles", TRAFFIC_PROFILES[(kind, prec)])).read()
     except (OSError, KeyError):
         return None
     vals = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
-    try:
-        if vals.get("kernel_source_sha256") != kernel_source_hash(root, kind):
-            return None
-        if abs(float(vals["flops_per_launch"]) / flops_per_launch - 1) > 1e-5:
-            return None
-        if abs(float(vals["algorithmic_bytes_per_launch"]) / bytes_per_launch - 1) > 1e-5:
-            return None
-        return float(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError, ZeroDivisionError):
+    if vals.get("kernel_source_sha256") != kernel_source_hash(root, kind):
         return None
+    shapes, others = {}, None
+    for row in re.findall(r"^\| (\S+) \| (\S+) \| (\S+) \| \S+ \| \S+ \| (\S+) \| (\S+) \| \S+ \|$",
+                          text, re.M):
+        try:
+            scaled, alg = float(row[3]), float(row[4])
+        except ValueError:
+            continue
+        if row[0] == "others":
+            others = (scaled, alg)
+            continue
+        key = (tuple(int(x) for x in row[1].split(",")), int(row[2]))
+        s0, a0 = shapes.get(key, (0.0, 0.0))
+        shapes[key] = (s0 + scaled, a0 + alg)
+    total = covered = traffic = 0.0
+    for L in launches:
+        key = (tuple(L["mnk"]), L["copies"])
+        total += L["bytes"]
+        if key in shapes:
+            covered += L["bytes"]
+            traffic += L["bytes"] * shapes[key][0] / shapes[key][1]
+        elif others is not None and others[1] > 0:
+            traffic += L["bytes"] * others[0] / others[1]
+        else:
+            return None
+    if total <= 0 or covered < 0.95 * total:
+        return None
+    return traffic / total
 
 
 def plan_cost(plan):
@@ -305,7 +328,7 @@ def select_plan(R, net, bits, a):
     return chosen, info, plan, lp_plan
 
 
-def roofline(kind, tim, a, flops_total, kind_ms):
+def roofline(kind, tim, a, flops_total, kind_ms, traffic_ratio=None):
     """Roofline entry of the dominant kernel kind from the timing probe."""
     n = max(1, tim["launches"])
     secs = tim["total_ms"] / 1000.0
@@ -324,7 +347,7 @@ def roofline(kind, tim, a, flops_total, kind_ms):
     return {
         "bound": bound, "kernel": label, "achieved": achieved, "peak": peak, "unit": unit,
         "frac": achieved / peak,
-        "traffic": _profile_traffic(kind, a.prec, fpl, bpl),
+        "traffic": (None if traffic_ratio is None else traffic_ratio * bpl),
         "algorithmic_bytes_per_launch": bpl,
         "flops_per_launch": fpl,
         "launches": tim["launches"],
@@ -368,6 +391,7 @@ def launch_table(launches, n_reps=1, prec="f32"):
         k["t_min_mfma_ms"] += t_min if t_f >= t_b else 0.0
     out = {}
     for kind, k in kinds.items():
+        k["ratio"] = _profile_traffic(kind, prec, [r for r in rows if r["kernel"] == KIND_NAMES.get(kind)])
         secs = k["ms"] / 1e3
         mfma = k["t_min_mfma_ms"] >= 0.5 * k["t_min_ms"]
         peak = PEAK_MFMA_16 if kind == 3 else PEAK_MFMA_FP32
@@ -382,9 +406,9 @@ def launch_table(launches, n_reps=1, prec="f32"):
             "ms_per_step": k["ms"], "t_min_ms_per_step": k["t_min_ms"],
             "achieved_tflops": k["flops"] / secs / 1e12, "achieved_gbs": k["bytes"] / secs / 1e9,
             "launches": k["launches"],
-            "traffic": _profile_traffic(kind, prec, k["flops"] / k["launches"],
-                                        k["bytes"] / k["launches"]),
-            "algorithmic_bytes_per_launch": k["bytes"] / k["launches"]}
+            "traffic": (None if k["ratio"] is None else k["ratio"] * k["bytes"] / k["launches"]),
+            "algorithmic_bytes_per_launch": k["bytes"] / k["launches"],
+            "traffic_over_algorithmic": k["ratio"]}
     return rows, out
 
 
@@ -1016,7 +1040,8 @@ def main():
         "tflops": step_flops / (ms / 1000.0) / 1e12,
         "latency_ms": {"p50": 1000 * float(np.percentile(lat, 50)),
                        "p99": 1000 * float(np.percentile(lat, 99))},
-        "roofline": roofline(dom, tim, a, step_flops * frac * a.steps, kind_ms),
+        "roofline": roofline(dom, tim, a, step_flops * frac * a.steps, kind_ms,
+                             by_kind[KIND_NAMES[dom]].get("traffic_over_algorithmic")),
         "roofline_by_kernel": by_kind,
         "launch_table": table,
         "autotune": tune,
