@@ -350,6 +350,7 @@ template <int SA, int SB, int SC, bool M3>
 __global__ __launch_bounds__(256, M3 ? 2 : 3) void k_mfma32_tiles(StepDesc d) {
   __shared__ float lds[kMainFloats + 16];
   __shared__ OuterTab ot;
+  __shared__ TileMap maps[3];  // A, B, C
   float* Abuf = lds;
   float2* Bbuf = reinterpret_cast<float2*>(lds + 2 * kABuf);
   float* red = lds + kMainFloats;
@@ -371,9 +372,11 @@ __global__ __launch_bounds__(256, M3 ? 2 : 3) void k_mfma32_tiles(StepDesc d) {
   {
     TileTab* ta = reinterpret_cast<TileTab*>(lds);
     TileTab* tb = ta + 1;
-    build_tab(d.tA, 1, 0, kAStride, *ta);
-    build_tab(d.tB, 0, 1, kBStride, *tb);
+    stage_maps(d, maps);
     build_outer(d, ot);
+    __syncthreads();
+    build_tab(maps[0], 1, 0, kAStride, *ta);
+    build_tab(maps[1], 0, 1, kBStride, *tb);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -387,9 +390,9 @@ __global__ __launch_bounds__(256, M3 ? 2 : 3) void k_mfma32_tiles(StepDesc d) {
     }
   }
   int hb = 0;
-  for (int b = 0; b < d.tC.nbits; ++b)
-    if (d.tC.role[b] == 0 && d.tC.cbit[b] == 6) hb = b;
-  const int64_t g_half = int64_t(1) << d.tC.gpos[hb];
+  for (int b = 0; b < maps[2].nbits; ++b)
+    if (maps[2].role[b] == 0 && maps[2].cbit[b] == 6) hb = b;
+  const int64_t g_half = int64_t(1) << maps[2].gpos[hb];
 
   const int n_kc = 1 << d.n_ko;
   float2 ra[8], rb[4];
@@ -418,6 +421,9 @@ __global__ __launch_bounds__(256, M3 ? 2 : 3) void k_mfma32_tiles(StepDesc d) {
     };
     Acc32<M3> acc;
     acc_zero(acc);
+    // The copy's scale inputs are read before the first chunk, whose wait
+    // covers them; they are used only in the epilogue.
+    ScaleIn sin = load_scale(d, js, jb);
     load_chunk(0);
     __syncthreads();  // the tables (or the previous copy's output) are done with
     store_chunk(0);
@@ -436,8 +442,9 @@ __global__ __launch_bounds__(256, M3 ? 2 : 3) void k_mfma32_tiles(StepDesc d) {
     // Epilogue: the C table and two halves of 64 rows in the operand buffers.
     float* Cs = lds;
     TileTab* tcs = reinterpret_cast<TileTab*>(lds + kCHalf);
-    build_tab_skip(d.tC, hb, kCStride, 2, *tcs);
-    const Scale sc = compute_scale(d, js, jb);
+    build_tab_skip(maps[2], hb, kCStride, 2, *tcs);
+    asm volatile("" : "+v"(sin.eA), "+v"(sin.eB), "+v"(sin.mA), "+v"(sin.mB));
+    const Scale sc = scale_of(d, sin);
     float lmax = 0.f;
     int bad = 0;
     __syncthreads();

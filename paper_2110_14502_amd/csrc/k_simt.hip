@@ -63,9 +63,14 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
   float2* As = smem2;
   float2* Bs = As + R * ldA;
   const int tid = threadIdx.x, lane = tid & 63;
-  build_tab(d.tA, ldA, 0, 1, ta);
-  build_tab(d.tB, 0, 1, ldB, tb);
-  build_tab(d.tC, 4096, 1, 0, tcc);  // coordinate = row * 4096 + col
+  __shared__ TileMap maps[3];
+  __shared__ OuterTab ot;
+  stage_maps(d, maps);
+  build_outer(d, ot);
+  __syncthreads();
+  build_tab(maps[0], ldA, 0, 1, ta);
+  build_tab(maps[1], 0, 1, ldB, tb);
+  build_tab(maps[2], 4096, 1, 0, tcc);  // coordinate = row * 4096 + col
   const uint64_t tiles = (uint64_t)d.n_row_tiles * (uint64_t)d.n_col_tiles;
   const uint64_t split = blockIdx.x / tiles;
   const uint64_t tile = blockIdx.x % tiles;
@@ -121,7 +126,7 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
   for (int copy = blockIdx.y; copy < d.copies; copy += gridDim.y) {
     const int js = copy % d.gs_c, jb = copy / d.gs_c;
     int64_t oA, oB, oC;
-    outer_offsets(d, ro, no, js, jb, oA, oB, oC);
+    outer_offsets(d, ot, ro, no, js, jb, oA, oB, oC);
     float2 acc[kSimtMaxC];
 #pragma unroll
     for (int i = 0; i < kSimtMaxC; ++i) acc[i] = make_float2(0.f, 0.f);
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(kSimtBlock) void k_simt(StepDesc d) {
       for (int j = 0; j < 4; ++j) bx[i][j] = by[i][j] = 0.f;
     for (int kc = kc0; kc < kc0 + n_kc; ++kc) {
       int64_t kA, kB;
-      k_offsets(d, kc, kA, kB);
+      k_offsets(d, ot, kc, kA, kB);
       // Up to 16 elements of each operand per thread (tiles hold at most
       // 4096): all loads of an operand are issued, as raw stored words,
       // before any is converted and written.
@@ -270,7 +275,10 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(StepDesc d) {
   __shared__ TileTab tcc;
   __shared__ float red[16];
   const int tid = threadIdx.x;
-  build_tab(d.tC, 0, 0, 0, tcc);
+  __shared__ TileMap maps[3];
+  stage_maps(d, maps);
+  __syncthreads();
+  build_tab(maps[2], 0, 0, 0, tcc);
   const uint64_t ro = blockIdx.x % (uint64_t)d.n_row_tiles;
   const uint64_t no = blockIdx.x / (uint64_t)d.n_row_tiles;
   const int nC = 1 << (d.rt + d.nt);

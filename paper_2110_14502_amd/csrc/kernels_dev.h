@@ -229,12 +229,15 @@ struct OuterTab {
 
 __device__ __forceinline__ void build_outer(const StepDesc& d, OuterTab& o) {
   for (int i = threadIdx.x; i < kMaxOuter; i += blockDim.x) {
-    o.rA[i] = i < d.n_ro ? int64_t(1) << d.ro_A[i] : 0;
-    o.rC[i] = i < d.n_ro ? int64_t(1) << d.ro_C[i] : 0;
-    o.nB[i] = i < d.n_no ? int64_t(1) << d.no_B[i] : 0;
-    o.nC[i] = i < d.n_no ? int64_t(1) << d.no_C[i] : 0;
-    o.kA[i] = i < d.n_ko ? int64_t(1) << d.ko_A[i] : 0;
-    o.kB[i] = i < d.n_ko ? int64_t(1) << d.ko_B[i] : 0;
+    // All six bytes are read before any is used (one round trip).
+    const int ra = d.ro_A[i], rc = d.ro_C[i], nb = d.no_B[i], nc = d.no_C[i];
+    const int ka = d.ko_A[i], kb = d.ko_B[i];
+    o.rA[i] = i < d.n_ro ? int64_t(1) << ra : 0;
+    o.rC[i] = i < d.n_ro ? int64_t(1) << rc : 0;
+    o.nB[i] = i < d.n_no ? int64_t(1) << nb : 0;
+    o.nC[i] = i < d.n_no ? int64_t(1) << nc : 0;
+    o.kA[i] = i < d.n_ko ? int64_t(1) << ka : 0;
+    o.kB[i] = i < d.n_ko ? int64_t(1) << kb : 0;
   }
 }
 
@@ -382,6 +385,22 @@ constexpr int kCHalf = 64 * kCStride;     // floats of one staged half
 constexpr int kTabFloats = (int)(sizeof(TileTab) / sizeof(float));
 static_assert(kCHalf + kTabFloats <= kMainFloats, "C staging must fit the operand buffers");
 static_assert(2 * kTabFloats <= kMainFloats, "operand tables must fit the operand buffers");
+
+// Copies the descriptor's three tile maps into LDS (threads 0..38 one word
+// each, one round trip); the caller synchronises before use.  Tables built
+// straight from the kernel-argument block read its byte fields under per-lane
+// indices, one global byte load and one wait at a time: several memory round
+// trips before a workgroup's first load, which kernels with one tile per
+// workgroup pay in every workgroup.
+__device__ __forceinline__ void stage_maps(const StepDesc& d, TileMap (&m)[3]) {
+  static_assert(sizeof(TileMap) % 4 == 0, "tile map copied as words");
+  constexpr int W = (int)(sizeof(TileMap) / 4);
+  const int t = threadIdx.x;
+  if (t < 3 * W) {
+    const TileMap* src = t < W ? &d.tA : (t < 2 * W ? &d.tB : &d.tC);
+    reinterpret_cast<int*>(&m[t / W])[t % W] = reinterpret_cast<const int*>(src)[t % W];
+  }
+}
 
 // Table over the tile bits of `t` except bit `skip` (lo: first six, hi: rest).
 __device__ __forceinline__ void build_tab_skip(const TileMap& t, int skip, int row_stride,
