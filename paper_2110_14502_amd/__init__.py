@@ -261,8 +261,10 @@ class Circuit:
         return cls(circ.n_qubits, circ.gates)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _lib.rqc_circuit_destroy(self.h)
+        # At interpreter exit the module's globals may already be gone.
+        lib = _lib
+        if getattr(self, "h", None) and lib is not None:
+            lib.rqc_circuit_destroy(self.h)
             self.h = None
 
 
@@ -275,8 +277,10 @@ class Network:
         self.n_qubits = circuit.n_qubits
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _lib.rqc_network_destroy(self.h)
+        # At interpreter exit the module's globals may already be gone.
+        lib = _lib
+        if getattr(self, "h", None) and lib is not None:
+            lib.rqc_network_destroy(self.h)
             self.h = None
 
 
@@ -316,8 +320,10 @@ class Plan:
         self._ws = None
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _lib.rqc_plan_destroy(self.h)
+        # At interpreter exit the module's globals may already be gone.
+        lib = _lib
+        if getattr(self, "h", None) and lib is not None:
+            lib.rqc_plan_destroy(self.h)
             self.h = None
 
     # ---- host-side description
