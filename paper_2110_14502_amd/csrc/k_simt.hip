@@ -423,11 +423,15 @@ __global__ __launch_bounds__(kSimtBlock) void k_dot(StepDesc d) {
     // Recursive halving over the wave: at offset s a lane keeps the lower
     // or upper half of its outputs ((lane & s) set: upper) and adds the
     // partner's copy of that half.
-    int cnt = NOUT;
+    // The step counter t is the unrolled induction variable, so every count
+    // and index below is a compile-time constant (a run-time index would put
+    // the output arrays in scratch memory).
 #pragma unroll
-    for (int s = 32; s > 0; s >>= 1) {
-      if (cnt > 1) {
-        const int h = cnt >> 1;
+    for (int t = 0; t < 6; ++t) {
+      const int s = 32 >> t;
+      const int c = NOUT >> t;  // outputs a lane holds before this step
+      if (c > 1) {
+        const int h = c >> 1;
         const bool up = (lane & s) != 0;
 #pragma unroll
         for (int o = 0; o < NOUT / 2; ++o) {
@@ -438,7 +442,6 @@ __global__ __launch_bounds__(kSimtBlock) void k_dot(StepDesc d) {
             ay[o] = ky + __shfl_xor(sy, s, 64);
           }
         }
-        cnt = h;
       } else {
         ax[0] += __shfl_xor(ax[0], s, 64);
         ay[0] += __shfl_xor(ay[0], s, 64);
