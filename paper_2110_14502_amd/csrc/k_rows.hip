@@ -126,7 +126,11 @@ template <int S, int K, int NJ>
 __device__ __forceinline__ void unpack_raw(const RawRow<S, K, NJ>& r, int g, float (&out)[NJ]) {
   if (K <= 2) {
     if (S == ST_C64) {
-      out[0] = __uint_as_float((g & 1) ? r.w[1] : r.w[0]);
+      // A select between the two words by value: written as (g & 1) ? w[1] :
+      // w[0] it is turned into an indexed load, which puts the rows in
+      // scratch memory.
+      const uint32_t m = 0u - (uint32_t)(g & 1);
+      out[0] = __uint_as_float(r.w[0] ^ ((r.w[0] ^ r.w[1]) & m));
     } else {
       const float2 c = unpack_word<S>(r.w[0]);
       out[0] = (g & 1) ? c.y : c.x;
