@@ -77,9 +77,10 @@ StepDesc make_pair_desc(const std::vector<int>& la, const std::vector<int>& lb,
   auto pb = [&](int x) { return pos_in(lb, x); };
   auto pc = [&](int x) { return pos_in(lc, x); };
   // Row-streaming kernel: K is the lowest k address bits of both A and B, in
-  // the same order; B small.  Outputs of 64 or 128 columns only with sums of
-  // at most 16 (one K chunk, the columns walked in groups).
-  bool rows_ok = k <= 7 && (n <= 5 || (n <= 7 && k <= 4)) && (int64_t(1) << (n + k)) <= 4096;
+  // the same order; B small (N K <= 4096, staged whole in LDS).  Outputs of
+  // 64 or 128 columns only with sums of at most 16 (one K chunk, the columns
+  // walked in groups).
+  bool rows_ok = k <= 12 && (n <= 5 || (n <= 7 && k <= 4)) && (int64_t(1) << (n + k)) <= 4096;
   for (int p = 0; p < k && rows_ok; ++p) {
     const int xa = la[la.size() - 1 - p];
     rows_ok = pos_in(lb, xa) == p;

@@ -530,7 +530,12 @@ hipError_t launch_rows_kernel(const StepDesc& d, int sa, dim3 grid, hipStream_t 
     case 4: return launch_rows<4>(d, sa, grid, s);
     case 5:
     case 6:
-    case 7: return launch_rows<4>(d, sa, grid, s);
+    case 7:
+    case 8:
+    case 9:
+    case 10:
+    case 11:
+    case 12: return launch_rows<4>(d, sa, grid, s);
   }
   return hipErrorInvalidValue;
 }

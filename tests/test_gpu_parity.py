@@ -309,7 +309,8 @@ def test_row_streaming_kernel_plan_layout():
     both operands in the same order, small B, several row tiles."""
     _say("rows kernel")
     for (m, n, k, seed) in ((14, 3, 3, 21), (12, 6, 5, 22), (9, 0, 2, 23), (13, 2, 0, 24),
-                            (12, 5, 7, 25), (11, 4, 6, 26)):  # B of 4096 / 1024 elements
+                            (12, 5, 7, 25), (11, 4, 6, 26),  # B of 4096 / 1024 elements
+                            (12, 4, 8, 27), (10, 3, 9, 28), (9, 2, 10, 29)):  # sums of 256-1024
         M = list(range(m))
         N = list(range(100, 100 + n))
         K = list(range(200, 200 + k))

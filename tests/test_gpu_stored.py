@@ -100,10 +100,11 @@ LP = [R.ST_F16, R.ST_BF16]
 
 @pytest.mark.parametrize("lp", LP)
 def test_rows_kernel_16bit_matrix_cores(lp):
-    """Row-streaming kernel with A stored in 16 bits and sums of 16..128
+    """Row-streaming kernel with A stored in 16 bits and sums of 16..256
     complex values: the 16-bit matrix-core path (16x16x32), in one chunk of
-    16, then in one, two and four chunks of 32."""
-    for (m, n, k, seed) in ((13, 3, 4, 51), (12, 5, 5, 52), (11, 2, 6, 53), (10, 3, 7, 54)):
+    16, then in one, two, four and eight chunks of 32."""
+    for (m, n, k, seed) in ((13, 3, 4, 51), (12, 5, 5, 52), (11, 2, 6, 53), (10, 3, 7, 54),
+                            (11, 4, 8, 55)):
         _say("rows 16-bit mma", lp, m, n, k)
         # both operands 16-bit: exact products, FP32 accumulation
         err = _run(m, n, k, seed, lp, lp, R.ST_C64, R.KERN_ROWS, batch=2)
