@@ -210,10 +210,17 @@ def test_fp32_mfma_variants_vs_einsum(variant):
         ref = oracle.einsum_step(a, b, st.labels_a, st.labels_b, st.labels_c)
         err = _rel_rms(_values(C), ref)
         assert err < 2e-5, (ra, rb, s, variant, err)
+    # Sums of 16 over batches (the persistent walk crosses copies): fewer
+    # items than workgroups, a little more than one round of them, and many.
+    for (m, n, seed, batch) in ((7, 6, 21, 3), (10, 9, 22, 9), (12, 8, 23, 5)):
+        err = _run(m, n, 4, seed, R.ST_C64, R.ST_C64, R.ST_C64, R.KERN_MFMA, batch=batch,
+                   variant=variant)
+        assert err < 2e-5, (m, n, batch, variant, err)
 
 
 @pytest.mark.parametrize("variant", [R.VAR_SWAP, R.VAR_SWAP | R.VAR_TILES,
-                                     R.VAR_SWAP | R.VAR_PERSISTENT, R.VAR_SWAP | R.VAR_4M])
+                                     R.VAR_SWAP | R.VAR_PERSISTENT, R.VAR_SWAP | R.VAR_4M,
+                                     R.VAR_SWAP | R.VAR_PERSISTENT | R.VAR_4M])
 def test_fp32_mfma_exchanged_operands_vs_einsum(variant):
     """The FP32 matrix-core kernel with A and B exchanged inside the kernel
     (B's free indices on the tile rows) against einsum: outputs of 128 and
