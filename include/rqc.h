@@ -442,7 +442,9 @@ void rqc_server_destroy(rqc_server* s);
  * here the choice per step is measured).  For every step of the plan with
  * more than one valid (kernel, variant) pair -- the FP32 matrix-core kernel
  * with three or four real products per complex product, per-tile or
- * persistent; the row-streaming kernel where its conditions hold -- each
+ * persistent, and either kernel with the operands exchanged where B has
+ * the fewer free indices and at least seven; the row-streaming kernel where
+ * its conditions hold -- each
  * pair is timed with HIP events on `stream` for the group of slices and
  * bitstrings that a call of n_ids slices (0 = all) and n_batch bitstrings
  * in precision `prec` gets in this workspace, and the fastest is kept for
@@ -569,10 +571,10 @@ rqc_status rqc_plan_set_scale_bias(rqc_plan* p, int32_t bias,
  * product instead of three, 2 = one tile per workgroup, 4 = persistent
  * walk; any kernel: 8 = FP32 arithmetic on 16-bit stored operands; 16-bit
  * matrix cores: 16 = stream A past a resident tile of B, for sums of 32 to
- * 128 terms with A stored in 16 bits; FP32 matrix cores: 32 = the operands
- * exchanged inside the kernel, B taking the tile rows and A the columns,
- * same result).  EINVAL when the kernel's shape or layout conditions are not
- * met (no fallback). */
+ * 128 terms with A stored in 16 bits; FP32 and 16-bit matrix cores: 32 =
+ * the operands exchanged inside the kernel, B taking the tile rows and A the
+ * columns, same result).  EINVAL when the kernel's shape or layout
+ * conditions are not met (no fallback). */
 rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
                                     const int32_t* labels_b, int32_t rank_b,
                                     const int32_t* labels_c, int32_t rank_c,

@@ -666,8 +666,8 @@ rqc_status rqc_pair_contract_stored(const int32_t* labels_a, int32_t rank_a,
   }
   if (variant < 0 || variant > 63) throw rqc::Error{RQC_EINVAL, "variant out of range"};
   const bool swap = (variant & rqc::kVarSwap) != 0;
-  if (swap && kernel != rqc::KERN_MFMA)
-    throw rqc::Error{RQC_EINVAL, "exchanged operands need the FP32 matrix-core kernel"};
+  if (swap && kernel != rqc::KERN_MFMA && kernel != rqc::KERN_MFMA16)
+    throw rqc::Error{RQC_EINVAL, "exchanged operands need a matrix-core kernel"};
   int kern = kernel;
   rqc::StepDesc d = swap ? rqc::make_pair_desc(lb, la, lc, kern) : rqc::make_pair_desc(la, lb, lc, kern);
   if (kern != kernel) throw rqc::Error{RQC_EINVAL, "shape or layout not supported by the requested kernel"};

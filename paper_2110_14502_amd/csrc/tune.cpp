@@ -85,6 +85,10 @@ std::vector<std::pair<int, int>> candidates(rqc_plan* p, int m, size_t i) {
   if (fp32_mma && st.n >= 7 && st.m > st.n && valid(KERN_MFMA, kVarSwap))
     for (int v : {kVarTiles, kVarPersistent}) add(KERN_MFMA, v | kVarSwap);
   if (cur == KERN_MFMA16 && st.k >= 5 && st.k <= 7) add(KERN_MFMA16, kVarStream);
+  // The same exchange on the 16-bit matrix cores: a 128-column output is
+  // written in whole 128-column rows (one row tile) instead of half rows.
+  if (cur == KERN_MFMA16 && st.n >= 7 && st.m > st.n && valid(KERN_MFMA16, kVarSwap))
+    add(KERN_MFMA16, kVarSwap);
   // Reduced precision: a row-kernel step that the 16-bit matrix-core kernel
   // can also take.
   if (m != RQC_F32 && cur == KERN_ROWS && !base_var && valid(KERN_MFMA16)) add(KERN_MFMA16, 0);

@@ -253,6 +253,31 @@ def test_fp32_mfma_exchanged_operands_vs_einsum(variant):
 
 
 @pytest.mark.parametrize("lp", LP)
+def test_16bit_mfma_exchanged_operands(lp):
+    """The 16-bit matrix-core kernel with A and B exchanged inside the
+    kernel (B's free indices on the tile rows) against einsum on the stored
+    values: outputs of 128 and 256 columns, sums of 16..128 terms, batched
+    copies with a per-copy A and a shared B, both operands in 16 bits (exact
+    products) and B in complex64 (converted for the matrix cores)."""
+    for (m, n, k, seed) in ((10, 7, 4, 111), (12, 7, 5, 112), (9, 8, 6, 113), (11, 7, 7, 114)):
+        _say("mfma16 exchanged operands", lp, m, n, k)
+        err = _run(m, n, k, seed, lp, lp, R.ST_C64, R.KERN_MFMA16, batch=3, mma=MMA[lp],
+                   variant=R.VAR_SWAP)
+        assert err < 2e-5, (m, n, k, err)
+        err = _run(m, n, k, seed, lp, R.ST_C64, lp, R.KERN_MFMA16, batch=2, mma=MMA[lp],
+                   variant=R.VAR_SWAP)
+        assert 1e-6 < err < LP_TOL[lp], (m, n, k, err)
+    # B's free indices must fill a row tile: seven or more.
+    la, lb, lc = _plan_layout(10, 6, 5, 115)
+    A, _ = _store(rqcgen.random_complex(1 << 15, 1), lp)
+    B, _ = _store(rqcgen.random_complex(1 << 11, 2), lp)
+    C = _empty(1 << 16, R.ST_C64)
+    with pytest.raises(R.RqcError):
+        R.pair_contract_stored(A, B, C, la, lb, lc, lp, lp, 0, R.KERN_MFMA16, mma_prec=MMA[lp],
+                               variant=R.VAR_SWAP)
+
+
+@pytest.mark.parametrize("lp", LP)
 def test_16bit_mfma_streaming_variant(lp):
     """The 16-bit matrix-core kernel's streaming form (A streamed past a
     resident tile of B over the whole sum), sums of 32..128 terms, several
