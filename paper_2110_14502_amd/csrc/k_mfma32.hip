@@ -108,6 +108,10 @@ __device__ __forceinline__ void chunk_mfma(const float* Abuf_cb, const float2* B
         ni1 = As[o + kAPlane + 32];
         nb = Bs[2 * (kk + 1) * kBStride];
       }
+      // Keep the next step's LDS reads ahead of this step's products (left
+      // to itself the scheduler sinks them below the products and waits for
+      // them right away).
+      __builtin_amdgcn_sched_barrier(0);
       const float bs = b.x + b.y, as0 = ar0 + ai0, as1 = ar1 + ai1;
       acc.v[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar0, b.x, acc.v[0], 0, 0, 0);
       acc.v[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai0, b.y, acc.v[1], 0, 0, 0);
