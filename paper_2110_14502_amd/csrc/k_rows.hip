@@ -363,28 +363,48 @@ __global__ __launch_bounds__(256) void k_rows(StepDesc d) {
           float af[4][NJ];
     #pragma unroll
           for (int rb = 0; rb < 4; ++rb) unpack_raw<SA, K, NJ>(a[rb], g, af[rb]);
+          // B operand: real column lc of column chunk h (complex column
+          // h*NC + lc/2, part lc&1), real summation index of MFMA j.
+          // Unconditional reads (clamped column and summation index: the
+          // lanes they serve either hold zero rows of A, K = 1, or columns
+          // that are never stored), so that no LDS read sits in a branch.
+          // Chunk h + 1's values are read before chunk h's products are
+          // issued and used after them (scheduling barriers keep both there;
+          // left to itself the scheduler reads them just before their use
+          // and waits).
+          const int ncl = (lc >> 1) < NC ? (lc >> 1) : NC - 1, q = lc & 1;
+          float2 bv[NJ];
+    #pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int rk = K >= 2 ? g * NJ + j : g;
+            const int kk = (rk >> 1) < K ? (rk >> 1) : K - 1;
+            bv[j] = Bs[((cg * NCH) * NC + ncl) * KT + kc * K + kk];
+          }
     #pragma unroll
           for (int h = 0; h < NCH; ++h) {
-            // B operand: real column lc of column chunk h (complex column
-            // h*NC + lc/2, part lc&1), real summation index of MFMA j.
-            // Unconditional reads (clamped column and summation index: the
-            // lanes they serve either hold zero rows of A, K = 1, or columns
-            // that are never stored), so that no LDS read sits in a branch.
             float bop[NJ];
-            const int n = (cg * NCH + h) * NC + ((lc >> 1) < NC ? (lc >> 1) : NC - 1), q = lc & 1;
     #pragma unroll
             for (int j = 0; j < NJ; ++j) {
               const int rk = K >= 2 ? g * NJ + j : g;
-              const int kk = (rk >> 1) < K ? (rk >> 1) : K - 1;
-              const float2 b = Bs[n * KT + kc * K + kk];
+              const float2 b = bv[j];
               bop[j] = (rk & 1) == 0 ? (q == 0 ? b.x : b.y) : (q == 0 ? -b.y : b.x);
             }
+            if (h + 1 < NCH) {
+    #pragma unroll
+              for (int j = 0; j < NJ; ++j) {
+                const int rk = K >= 2 ? g * NJ + j : g;
+                const int kk = (rk >> 1) < K ? (rk >> 1) : K - 1;
+                bv[j] = Bs[((cg * NCH + h + 1) * NC + ncl) * KT + kc * K + kk];
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);
     #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
     #pragma unroll
               for (int j = 0; j < NJ; ++j)
                 acc[rb][h] =
                     __builtin_amdgcn_mfma_f32_16x16x4f32(af[rb][j], bop[j], acc[rb][h], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
         if (kc + 1 < nkc) {
