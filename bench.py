@@ -111,6 +111,9 @@ def parse():
     ap.add_argument("--graph-steps", type=int, default=1)
     ap.add_argument("--lp-steps", type=int, default=1,
                     help="timed steps of the reduced-precision (f16) comparison, 0 = skip")
+    ap.add_argument("--tune-cache", default="",
+                    help="per-step kernel choices file read before tuning and written after "
+                         "(runs that share it make the same choices)")
     ap.add_argument("--tune", type=int, default=1,
                     help="per-step kernel tuning of the benchmarked plan before timing (1 = on)")
     ap.add_argument("--serve-requests", type=int, default=200,
@@ -967,7 +970,8 @@ def main():
     tune = None
     if a.tune:
         t0 = time.perf_counter()
-        tune = plan.autotune(prec, n_ids=len(ids) if ids else 0, workspace=ws)
+        tune = plan.autotune(prec, n_ids=len(ids) if ids else 0, workspace=ws,
+                             cache_path=a.tune_cache or None)
         tune["seconds"] = round(time.perf_counter() - t0, 2)
         log(f"autotune {a.prec}: {tune}")
     def step(p, tag):
@@ -1086,7 +1090,8 @@ def main():
 
         if a.tune:
             t0 = time.perf_counter()
-            tune16 = lp_plan.autotune(R.F16, n_ids=len(ids) if ids else 0, workspace=ws)
+            tune16 = lp_plan.autotune(R.F16, n_ids=len(ids) if ids else 0, workspace=ws,
+                                      cache_path=a.tune_cache or None)
             tune16["seconds"] = round(time.perf_counter() - t0, 2)
             log(f"autotune f16: {tune16}")
         step16("f16 warmup")
