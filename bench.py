@@ -44,7 +44,8 @@ TRAFFIC_PROFILES = {(1, "f32"): "k_mfma32_config2_6x6x14_fp32_traffic.md",
                     (2, "f32"): "k_rows_config2_6x6x14_fp32_traffic.md",
                     (0, "f32"): "k_simt_config2_6x6x14_fp32_traffic.md",
                     (3, "f16"): "k_mfma16_config2_6x6x14_fp16_traffic.md",
-                    (2, "f16"): "k_rows_config2_6x6x14_fp16_traffic.md"}
+                    (2, "f16"): "k_rows_config2_6x6x14_fp16_traffic.md",
+                    (0, "f16"): "k_simt_config2_6x6x14_fp16_traffic.md"}
 
 
 def parse():
